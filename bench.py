@@ -1,0 +1,205 @@
+#!/usr/bin/env python3
+"""Benchmark: solves/s of the two-stage preconditioned FGMRES on one MI355X.
+
+One step = the whole hot path for one Jacobian: the recurring setup of the flow
+stage (fixed-stress and quasi-IMPES operators, pressure AMG, BILU(0) factors,
+precision mirrors -- rebuilt every step as after a Newton update) followed by the
+FGMRES(100) solve to rtol 1e-8 with Algorithm 1 applied every iteration.  The
+mechanics AMG is set up once before the timed region, as in the paper (the
+elasticity operator does not change).  Inputs are synthetic and already resident
+in HBM when timing starts.
+
+Prints ONE JSON line.  Extra fields: the FP64-preconditioner rate on the same
+workload, per-phase times, iterations, the roofline of the system SpMV (timed
+with HIP events on the launch stream) and the CPU oracle baseline.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0     # MI355X HBM3E peak
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def spmv_bytes(s):
+    """Algorithmic bytes of y = A x with the FP64 block matrix (values + column
+    indices + row pointers, x read once, y written once)."""
+    b = 0
+    for blk in (s.Auu, s.Auf, s.Afu, s.Aff):
+        nb, br, bc = blk.vals.shape
+        b += nb * (br * bc * 8 + 4) + 4 * (blk.rowptr.shape[0])
+    return b + 2 * 8 * s.N
+
+
+def run_gpu(args, s, b):
+    import torch
+    from paper_1812_05540_amd import ps
+
+    ps.load()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    ctx = ps.ps_ctx_create(0, 0)
+    bd = torch.as_tensor(b, dtype=torch.float64, device=dev)
+    out = {}
+    precs = [("fp32", ps.PS_FP32_PREC)]
+    if args.precision in ("both", "fp64"):
+        precs = ([("fp32", ps.PS_FP32_PREC)] if args.precision == "both" else []) + [("fp64", ps.PS_FP64)]
+    xs = {}
+    for name, prec in precs:
+        opts = dict(precision=prec, ml_sweeps=args.ml_sweeps, smoother=args.smoother_code,
+                    ml_kind=args.ml_kind_code)
+        sv = ps.Solver(ctx, s, mech_key=1, **opts)
+        t0 = time.perf_counter()
+        sv.setup()                                # mechanics AMG (once) + flow stage
+        first_setup = time.perf_counter() - t0
+        x = torch.zeros(s.N, dtype=torch.float64, device=dev)
+        for _ in range(args.warmup):
+            sv.setup()
+            r = sv.solve(bd, x, args.rtol)
+        torch.cuda.synchronize()
+        t_setup = t_solve = 0.0
+        its = []
+        res = None
+        t_all = time.perf_counter()
+        for _ in range(args.steps):
+            t0 = time.perf_counter()
+            sv.setup()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            res = sv.solve(bd, x, args.rtol)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            t_setup += t1 - t0
+            t_solve += t2 - t1
+            its.append(res["iterations"])
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t_all
+        xs[name] = x.clone()
+        out[name] = dict(status=res["status"], iterations=its[-1], rel_residual=res["rel_residual"],
+                         restarts=res["restarts"], ms_per_step=1e3 * total / args.steps,
+                         solves_per_s=args.steps / total, setup_ms=1e3 * t_setup / args.steps,
+                         solve_ms=1e3 * t_solve / args.steps, first_setup_s=first_setup,
+                         footprint_gb=sv.footprint() / 1e9)
+        log(name, json.dumps(out[name]))
+        if name == precs[-1][0]:
+            # roofline of the FP64 system SpMV: HIP events on the launch stream
+            y = torch.empty_like(x)
+            for _ in range(3):
+                sv.spmv(x, y, stream)
+            start = torch.cuda.Event(enable_timing=True)
+            end = torch.cuda.Event(enable_timing=True)
+            start.record(stream)
+            for _ in range(args.kernel_reps):
+                sv.spmv(x, y, stream)
+            end.record(stream)
+            end.synchronize()
+            t_ms = start.elapsed_time(end) / args.kernel_reps
+            nbytes = spmv_bytes(s)
+            achieved = nbytes / (t_ms * 1e-3) / 1e9
+            out["roofline"] = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                                   frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                                   kernel="system SpMV y = A x (FP64 SELL-64, node rows + cell rows)",
+                                   ms=round(t_ms, 4), algorithmic_bytes=nbytes)
+        sv.close()
+    if "fp32" in xs and "fp64" in xs:
+        d = (xs["fp32"] - xs["fp64"]).norm() / xs["fp64"].norm()
+        out["fp32_vs_fp64_solution_rel_diff"] = float(d)
+    ps.ps_ctx_destroy(ctx)
+    return out
+
+
+def cpu_baseline(s, b, its_gpu, budget_s):
+    """The oracle (FP64, NumPy/SciPy, one thread) on a bounded sample of the same
+    workload: its flow-stage setup plus up to two FGMRES iterations (mechanics AMG
+    built once beforehand, as on the GPU); solves/s extrapolated with the GPU's
+    iteration count."""
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    from oracle import precond as P, amg, Options
+    from oracle.fgmres import fgmres
+    o = Options()
+    t0 = time.perf_counter()
+    sdc = amg.build(P.sdc_matrix(s))
+    t_mech = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    st = P.setup(s, o, mechanics=sdc)
+    t_setup = time.perf_counter() - t0
+    A = st.mats["A"]
+    n_it = 2 if t_setup < budget_s else 1
+    t0 = time.perf_counter()
+    fgmres(lambda v: A @ v, lambda v: P.apply_precond(st, v), b, 1e-30, 100, n_it)
+    t_it = (time.perf_counter() - t0) / n_it
+    per_solve = t_setup + its_gpu * t_it
+    return dict(value=round(1.0 / per_solve, 6), unit="solves/s", cores=1, kind="oracle",
+                sample="oracle on the same workload: flow-stage setup (%.1f s) + %d FGMRES "
+                       "iteration(s) (%.2f s each), extrapolated to %d iterations; mechanics AMG "
+                       "(%.1f s, once) excluded as on the GPU" % (t_setup, n_it, t_it, its_gpu, t_mech))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="grf64")
+    ap.add_argument("--precision", default="both", choices=["fp32", "fp64", "both"])
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--ml-sweeps", type=int, default=1)
+    ap.add_argument("--smoother", default="cheb2", choices=["cheb2", "l1jac"])
+    ap.add_argument("--ml-kind", default="bilu0", choices=["bilu0", "bjacobi"])
+    ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget-s", type=float, default=30.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    args.smoother_code = 0 if args.smoother == "cheb2" else 1
+    args.ml_kind_code = 0 if args.ml_kind == "bilu0" else 1
+
+    from synth import workload
+    t0 = time.perf_counter()
+    s, b = workload(args.workload)
+    log("workload %s: N=%d generated in %.1fs" % (args.workload, s.N, time.perf_counter() - t0))
+    g = run_gpu(args, s, b)
+    head = g.get("fp32") or g.get("fp64")
+    line = {
+        "metric": "solves/s to rtol 1e-8 (FP64 vs FP32 precond), SpMV HBM GB/s, p50/p99 latency",
+        "value": round(head["solves_per_s"], 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 preconditioner, f64 Krylov" if "fp32" in g else "f64",
+        "data": "synthetic",
+        "config": {"workload": "%s: %dx%dx%d-cell two-phase poromechanics Jacobian, N=%d, FGMRES(100) + "
+                               "two-stage preconditioner, rtol %g; step = flow-stage setup + solve"
+                               % (args.workload, *s.meta["grid"], s.N, args.rtol),
+                   "precision": "fp32-preconditioner" if "fp32" in g else "fp64",
+                   "ml_sweeps": args.ml_sweeps, "smoother": args.smoother, "ml_kind": args.ml_kind},
+        "paths": {k: v for k, v in g.items() if k in ("fp32", "fp64")},
+        "roofline": g["roofline"],
+    }
+    if "fp64" in g and "fp32" in g:
+        line["fp32_over_fp64_speedup"] = round(g["fp32"]["solves_per_s"] / g["fp64"]["solves_per_s"], 3)
+        line["fp32_vs_fp64_solution_rel_diff"] = g.get("fp32_vs_fp64_solution_rel_diff")
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(s, b, head["iterations"], args.cpu_budget_s)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,171 @@
+/*
+ * ps.h -- two-stage preconditioned FGMRES for fully-implicit multiphase
+ * poromechanics Jacobians on one AMD MI355X (gfx950).
+ *
+ * Method (White, Castelletto, Klevtsov, Bui, Osei-Kuffuor, Tchelepi, "A Two-Stage
+ * Preconditioner for Multiphase Poromechanics in Reservoir Simulation"):
+ *   - the Jacobian system of Sec. 4 (eq. jac_system) is solved with right-
+ *     preconditioned (flexible) GMRES, Sec. 4;
+ *   - the preconditioner is Algorithm 1: the block lower-triangular operator of
+ *     eq. blk_tr_prec with a separate-displacement-component AMG for the
+ *     mechanics (Sec. 5.2), the fixed-stress Schur approximation of eq.
+ *     Schur_1_FS, and the two-stage CPR flow preconditioner of eq. mult_prec_op
+ *     (quasi-IMPES global stage eq. S1_prec with a pressure AMG, then a local
+ *     block-ILU(0) or block-Jacobi stage, Sec. 5.3);
+ *   - setup and iteration phases are separate (Sec. 5.4); the mechanics AMG
+ *     can be shared by handles whose displacement block is identical (Sec. 5.2).
+ *
+ * Conventions for every entry point:
+ *   - Every call returns a status code (PS_OK = 0, errors < 0); nothing aborts.
+ *   - Host arrays passed in are copied; the caller keeps ownership and may free
+ *     them after the call returns.
+ *   - Vectors passed to ps_solve / ps_submit / ps_apply_precond / ps_spmv are
+ *     DEVICE pointers (HIP global memory, e.g. torch tensors on "cuda"), FP64,
+ *     of length N = 3 n_nodes + nf n_cells, ordered
+ *       [u_0x u_0y u_0z  u_1x ... | f_0,0 .. f_0,nf-1  f_1,0 ...]
+ *     (displacements interleaved per node, then flow dofs interleaved per cell).
+ *   - A handle is used by one host thread at a time; a context may be shared.
+ */
+#ifndef PS_H
+#define PS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+#define PS_OK          0
+#define PS_PENDING     1   /* ps_poll: request not finished yet */
+#define PS_EINVAL     -1   /* bad shape, unsorted/duplicate columns, missing diagonal,
+                              non-finite value, rtol <= 0, bad option */
+#define PS_ENOMEM     -2   /* device or host allocation failed / over budget */
+#define PS_EDEVICE    -3   /* a HIP runtime call failed */
+#define PS_ENOTSETUP  -4   /* ps_solve before ps_setup */
+#define PS_ESINGULAR  -5   /* singular D_ss block, BILU pivot block or coarse matrix */
+#define PS_EMAXIT     -6   /* maxit reached; x holds the last iterate */
+#define PS_EPRECISION -7   /* non-finite preconditioner output in the FP32 path */
+#define PS_EBUSY      -8   /* context is shutting down / queue full */
+#define PS_EBREAKDOWN -9   /* Arnoldi breakdown with a singular Hessenberg matrix */
+
+/* ---- options ------------------------------------------------------------ */
+#define PS_FP64       0    /* preconditioner data and arithmetic in FP64 */
+#define PS_FP32_PREC  1    /* preconditioner in FP32; FGMRES, A z, residual in FP64 */
+#define PS_CHEB2      0    /* AMG smoother: Chebyshev degree 2 on D^-1 A */
+#define PS_L1JAC      1    /* AMG smoother: l1-Jacobi */
+#define PS_BILU0      0    /* local stage M_L: block ILU(0) on S_ff^(fs) */
+#define PS_BJACOBI    1    /* local stage M_L: block Jacobi on S_ff^(fs) */
+
+/* Block CSR matrix (host arrays).  Row-major br x bc blocks; rowptr has nbrows+1
+ * entries starting at 0; colind sorted and unique within each block row. */
+typedef struct {
+    int32_t nbrows, nbcols, br, bc, nblocks;
+    const int32_t *rowptr;
+    const int32_t *colind;
+    const double  *vals;     /* nblocks * br * bc */
+} ps_bsr;
+
+/* One linearised system, eq. jac_system partitioned as in eq. LU.
+ * Auu: 3x3 blocks (n_nodes x n_nodes), diagonal block present in every row.
+ * Auf: 3 x nf blocks (n_nodes x n_cells); contains A_us and A_up.
+ * Afu: nf x 3 blocks (n_cells x n_nodes); contains A_su and A_pu.
+ * Aff: nf x nf blocks (n_cells x n_cells), interleaved {s.., p} per cell (the
+ *      permutation P of Sec. 5.3 is the identity), diagonal block in every row.
+ * d_sp: n_cells * (nf-1) fixed-stress entries added to the (s_l, p) entry of
+ *       each diagonal cell block; d_pp: n_cells entries added to (p, p)
+ *       (eq. FS_Dps_Dpp and the multi-component remark after it).
+ * nf: 2 or 3.  p_index: which cell dof is the pressure (and which cell row the
+ * pressure equation); this library requires p_index == nf - 1.
+ * mech_key: non-zero -> handles created with the same key in one context have
+ * identical A_uu and share one mechanics AMG hierarchy. */
+typedef struct {
+    int32_t n_nodes, n_cells, nf, p_index;
+    ps_bsr Auu, Auf, Afu, Aff;
+    const double *d_sp;
+    const double *d_pp;
+    uint64_t mech_key;
+} ps_system;
+
+typedef struct {
+    int32_t precision;    /* PS_FP64 | PS_FP32_PREC                       (PS_FP64)   */
+    int32_t restart;      /* FGMRES restart length m, 1..200              (100)       */
+    int32_t maxit;        /* total iteration cap                          (1000)      */
+    int32_t smoother;     /* PS_CHEB2 | PS_L1JAC                          (PS_CHEB2)  */
+    int32_t ml_kind;      /* PS_BILU0 | PS_BJACOBI                        (PS_BILU0)  */
+    int32_t ml_sweeps;    /* sweeps of the local stage, 1..16             (1)         */
+    int32_t coarse_max;   /* AMG: stop coarsening at n <= coarse_max      (256)       */
+    int32_t max_levels;   /* AMG: at most this many levels                (25)        */
+    int32_t fp32_fallback;/* FP32 path: retry in FP64 on PS_EPRECISION    (0)         */
+    double  theta;        /* AMG strength threshold                       (0.25)      */
+} ps_options;
+
+typedef struct {
+    int32_t status, iterations, restarts;
+    double  rel_residual;   /* true |b - A x| / |b| in FP64 at return */
+    double  setup_s, solve_s;
+} ps_result;
+
+typedef struct ps_ctx ps_ctx;
+typedef struct ps_handle ps_handle;
+
+/* Fill *o with the defaults listed above. */
+void ps_default_options(ps_options *o);
+
+/* Context for one HIP device.  hbm_budget_bytes bounds the device memory of the
+ * handles that the serving scheduler admits concurrently (0 = 90% of free). */
+int  ps_ctx_create(int device, size_t hbm_budget_bytes, ps_ctx **out);
+void ps_ctx_destroy(ps_ctx *ctx);
+
+/* Validate and copy a system (host arrays) into a new handle; the FP64 system
+ * matrix is uploaded to the device.  opts may be NULL (defaults). */
+int  ps_create(ps_ctx *ctx, const ps_system *sys, const ps_options *opts, ps_handle **out);
+
+/* Replace the flow blocks (Afu, Aff values and d_sp, d_pp; same patterns) as
+ * after a Newton step; the next ps_setup rebuilds the flow stage only. */
+int  ps_update_flow(ps_handle *h, const double *afu_vals, const double *aff_vals,
+                    const double *d_sp, const double *d_pp);
+
+/* Setup phase (Sec. 5.4): fixed-stress and quasi-IMPES operators, pressure AMG,
+ * BILU(0) factors, FP32 mirrors; the mechanics AMG is built on the first call
+ * (or taken from another handle with the same mech_key) and kept.  Every call
+ * rebuilds the flow stage.  Synchronous. */
+int  ps_setup(ps_handle *h);
+
+/* Solve A x = rhs to |b - A x| <= rtol |b| with FGMRES(restart) and Algorithm 1.
+ * rhs, x: device pointers (N doubles); x is overwritten (x0 = 0).  stream: a
+ * hipStream_t or NULL for the legacy default stream.  Blocking; res may be NULL. */
+int  ps_solve(ps_handle *h, const double *rhs, double *x, double rtol, void *stream,
+              ps_result *res);
+
+/* One application of the preconditioner, z = M^{-1} v (Algorithm 1), in the
+ * handle's precision (v, z device FP64 arrays of length N).  Stream-ordered: the
+ * work is enqueued on `stream` and the call returns without waiting for it. */
+int  ps_apply_precond(ps_handle *h, const double *v, double *z, void *stream);
+
+/* y = A x with the full FP64 system matrix (device arrays of length N).
+ * Stream-ordered like ps_apply_precond. */
+int  ps_spmv(ps_handle *h, const double *x, double *y, void *stream);
+
+/* Serving: enqueue a solve; rhs/x must stay valid until completion.  The
+ * context's scheduler admits requests by device-memory footprint and advances
+ * all admitted requests one FGMRES iteration per tick (continuous batching). */
+int  ps_submit(ps_handle *h, const double *rhs, double *x, double rtol, uint64_t *ticket);
+/* PS_PENDING while running; the request's final status once done (result copied). */
+int  ps_poll(ps_ctx *ctx, uint64_t ticket, ps_result *res);
+/* Block until the request finishes; returns its status. */
+int  ps_wait(ps_ctx *ctx, uint64_t ticket, ps_result *res);
+
+/* Device bytes held by the handle (system matrix, hierarchy, Krylov space). */
+int  ps_footprint(ps_handle *h, size_t *bytes);
+
+void ps_destroy(ps_handle *h);
+const char *ps_strerror(int status);
+/* Message of the last error raised on the calling thread ("" if none). */
+const char *ps_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PS_H */

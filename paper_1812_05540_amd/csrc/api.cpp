@@ -1,0 +1,663 @@
+// C ABI of the solver (include/ps.h, include/ps_host.h) and the serving scheduler.
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+
+#include "../../include/ps.h"
+#include "../../include/ps_host.h"
+#include "device.h"
+
+using namespace ps;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+template <typename F>
+int guard(F &&f) {
+    try {
+        g_last_error.clear();
+        return f();
+    } catch (const Error &e) {
+        g_last_error = e.what();
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return PS_ENOMEM;
+    } catch (const std::exception &e) {
+        g_last_error = e.what();
+        return PS_EDEVICE;
+    } catch (...) {
+        g_last_error = "unknown error";
+        return PS_EDEVICE;
+    }
+}
+
+double now_s() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+// Mechanics (separate displacement component) hierarchy, built once and shared by
+// handles with the same mech_key (Sec. 5.2: the elasticity AMG is set up once).
+struct Mech {
+    std::mutex mu;
+    Hierarchy host;
+    bool built = false;
+    std::unique_ptr<DHierarchy<double>> d64;
+    std::unique_ptr<DHierarchy<float>> d32;
+    size_t bytes() const { return (d64 ? d64->bytes() : 0) + (d32 ? d32->bytes() : 0); }
+};
+
+struct Request;
+
+}  // namespace
+
+struct ps_ctx {
+    int device = 0;
+    size_t budget = 0;
+    std::mutex mu;
+    std::map<uint64_t, std::weak_ptr<Mech>> mech_cache;
+    // serving
+    std::condition_variable cv, done_cv;
+    std::deque<Request *> queue;
+    std::vector<Request *> active;
+    std::map<uint64_t, std::unique_ptr<Request>> requests;
+    std::atomic<uint64_t> next_ticket{1};
+    size_t used = 0;
+    bool stop = false;
+    std::thread worker;
+    void scheduler();
+};
+
+struct ps_handle {
+    ps_ctx *ctx = nullptr;
+    System sys;
+    Options opt;
+    DSystem dsys;
+    std::shared_ptr<Mech> mech;
+    FlowSetup flow;
+    std::unique_ptr<DFlow<double>> fl64;
+    std::unique_ptr<DFlow<float>> fl32;
+    PrecWork<double> w64;
+    PrecWork<float> w32;
+    std::unique_ptr<Krylov> K;
+    double *ztmp = nullptr;           // FP32 z -> FP64 staging for ps_apply_precond
+    Arena aux;
+    bool ready = false;
+    std::atomic<bool> busy{false};
+    double setup_s = 0.0;
+    size_t krylov_bytes(bool z32) const {
+        size_t N = sys.N(), m = opt.restart;
+        return (m + 1) * N * 8 + m * N * (z32 ? 4 : 8) + N * 8 + (m + 2) * 1024 * 8;
+    }
+    size_t bytes() const {
+        return dsys.arena.bytes() + (mech ? mech->bytes() : 0) + (fl64 ? fl64->bytes() : 0) +
+               (fl32 ? fl32->bytes() : 0) + w64.arena.bytes() + w32.arena.bytes() +
+               (K ? K->arena.bytes() : 0) + aux.bytes();
+    }
+};
+
+namespace {
+
+struct Prec64 : PrecFn {
+    ps_handle *h;
+    explicit Prec64(ps_handle *hh) : h(hh) {}
+    void operator()(const double *v, void *z, hipStream_t st) override {
+        apply_precond<double>(*h->mech->d64, *h->fl64, h->w64, h->sys.n_nodes, v, (double *)z, st);
+    }
+};
+
+struct Prec32 : PrecFn {
+    ps_handle *h;
+    explicit Prec32(ps_handle *hh) : h(hh) {}
+    void operator()(const double *v, void *z, hipStream_t st) override {
+        apply_precond<float>(*h->mech->d32, *h->fl32, h->w32, h->sys.n_nodes, v, (float *)z, st);
+    }
+};
+
+struct Request {
+    uint64_t ticket = 0;
+    ps_handle *h = nullptr;
+    const double *rhs = nullptr;
+    double *x = nullptr;
+    double rtol = 0.0;
+    int status = PS_PENDING;
+    ps_result res{};
+    size_t bytes = 0;
+    double t_submit = 0.0, t_start = 0.0;
+    hipStream_t st = nullptr;
+    std::unique_ptr<Krylov> K;
+    std::unique_ptr<PrecFn> M;
+    std::unique_ptr<Fgmres> run;
+};
+
+void set_device(int dev) { PS_HIP(hipSetDevice(dev)); }
+
+bool use_fp32(const ps_handle *h) { return h->opt.precision == PS_FP32_PREC; }
+
+void ensure_mech_device(ps_handle *h, bool need64, bool need32) {
+    std::lock_guard<std::mutex> lk(h->mech->mu);
+    if (!h->mech->built) {
+        h->mech->host = amg_build(sdc_matrix(h->sys), h->opt);
+        h->mech->built = true;
+    }
+    if (need64 && !h->mech->d64) h->mech->d64 = upload_hierarchy<double>(h->mech->host, h->opt.smoother, true);
+    if (need32 && !h->mech->d32) h->mech->d32 = upload_hierarchy<float>(h->mech->host, h->opt.smoother, true);
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+const char *ps_last_error(void) { return g_last_error.c_str(); }
+
+const char *ps_strerror(int s) {
+    switch (s) {
+    case PS_OK: return "ok";
+    case PS_PENDING: return "pending";
+    case PS_EINVAL: return "invalid argument";
+    case PS_ENOMEM: return "out of memory";
+    case PS_EDEVICE: return "device error";
+    case PS_ENOTSETUP: return "handle not set up";
+    case PS_ESINGULAR: return "singular block or coarse matrix";
+    case PS_EMAXIT: return "maximum iterations reached";
+    case PS_EPRECISION: return "non-finite value in the FP32 preconditioner";
+    case PS_EBUSY: return "busy";
+    case PS_EBREAKDOWN: return "Krylov breakdown";
+    default: return "unknown status";
+    }
+}
+
+void ps_default_options(ps_options *o) {
+    if (!o) return;
+    o->precision = PS_FP64;
+    o->restart = 100;
+    o->maxit = 1000;
+    o->smoother = PS_CHEB2;
+    o->ml_kind = PS_BILU0;
+    o->ml_sweeps = 1;
+    o->coarse_max = 256;
+    o->max_levels = 25;
+    o->fp32_fallback = 0;
+    o->theta = 0.25;
+}
+
+int ps_ctx_create(int device, size_t budget, ps_ctx **out) {
+    return guard([&] {
+        if (!out) throw Error(PS_EINVAL, "out is NULL");
+        *out = nullptr;
+        int n = 0;
+        PS_HIP(hipGetDeviceCount(&n));
+        if (device < 0 || device >= n) throw Error(PS_EINVAL, "no such device");
+        set_device(device);
+        auto c = std::make_unique<ps_ctx>();
+        c->device = device;
+        if (budget == 0) {
+            size_t fr = 0, tot = 0;
+            PS_HIP(hipMemGetInfo(&fr, &tot));
+            budget = (size_t)(0.9 * (double)fr);
+        }
+        c->budget = budget;
+        ps_ctx *raw = c.get();
+        c->worker = std::thread([raw] { raw->scheduler(); });
+        *out = c.release();
+        return PS_OK;
+    });
+}
+
+void ps_ctx_destroy(ps_ctx *c) {
+    if (!c) return;
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        c->stop = true;
+    }
+    c->cv.notify_all();
+    if (c->worker.joinable()) c->worker.join();
+    delete c;
+}
+
+int ps_create(ps_ctx *ctx, const ps_system *sys, const ps_options *opts, ps_handle **out) {
+    return guard([&] {
+        if (!ctx || !out) throw Error(PS_EINVAL, "ctx/out is NULL");
+        *out = nullptr;
+        auto h = std::make_unique<ps_handle>();
+        h->ctx = ctx;
+        ps_options def;
+        ps_default_options(&def);
+        h->opt = options_from(opts ? opts : &def);
+        validate_and_copy(sys, h->sys);
+        set_device(ctx->device);
+        upload_system(h->sys, h->dsys);
+        if (h->sys.mech_key != 0) {
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            auto it = ctx->mech_cache.find(h->sys.mech_key);
+            if (it != ctx->mech_cache.end()) h->mech = it->second.lock();
+            if (!h->mech) {
+                h->mech = std::make_shared<Mech>();
+                ctx->mech_cache[h->sys.mech_key] = h->mech;
+            }
+        } else {
+            h->mech = std::make_shared<Mech>();
+        }
+        *out = h.release();
+        return PS_OK;
+    });
+}
+
+int ps_update_flow(ps_handle *h, const double *afu, const double *aff, const double *d_sp, const double *d_pp) {
+    return guard([&] {
+        if (!h) throw Error(PS_EINVAL, "handle is NULL");
+        if (h->busy) throw Error(PS_EBUSY, "handle has a request in flight");
+        System &s = h->sys;
+        auto take = [](std::vector<double> &dst, const double *src) {
+            if (!src) return;
+            for (size_t i = 0; i < dst.size(); ++i)
+                if (!std::isfinite(src[i])) throw Error(PS_EINVAL, "non-finite value");
+            std::memcpy(dst.data(), src, dst.size() * sizeof(double));
+        };
+        take(s.Afu.v, afu);
+        take(s.Aff.v, aff);
+        take(s.d_sp, d_sp);
+        take(s.d_pp, d_pp);
+        set_device(h->ctx->device);
+        DSystem fresh;
+        upload_system(s, fresh);
+        h->dsys.arena = std::move(fresh.arena);
+        h->dsys.Auu = fresh.Auu;
+        h->dsys.Auf = fresh.Auf;
+        h->dsys.Afu = fresh.Afu;
+        h->dsys.Aff = fresh.Aff;
+        h->dsys.n_nodes = fresh.n_nodes;
+        h->dsys.n_cells = fresh.n_cells;
+        h->dsys.nf = fresh.nf;
+        h->ready = false;
+        return PS_OK;
+    });
+}
+
+int ps_setup(ps_handle *h) {
+    return guard([&] {
+        if (!h) throw Error(PS_EINVAL, "handle is NULL");
+        if (h->busy) throw Error(PS_EBUSY, "handle has a request in flight");
+        double t0 = now_s();
+        set_device(h->ctx->device);
+        h->ready = false;
+        bool f32 = use_fp32(h);
+        bool f64 = !f32 || h->opt.fp32_fallback;
+        ensure_mech_device(h, f64, f32);
+        build_flow(h->sys, h->opt, h->flow);
+        h->fl64.reset();
+        h->fl32.reset();
+        if (f64) {
+            h->fl64 = upload_flow<double>(h->flow, h->sys, h->opt);
+            alloc_prec_work(h->w64, *h->mech->d64, *h->fl64, h->sys.n_nodes);
+        }
+        if (f32) {
+            h->fl32 = upload_flow<float>(h->flow, h->sys, h->opt);
+            alloc_prec_work(h->w32, *h->mech->d32, *h->fl32, h->sys.n_nodes);
+        }
+        PS_HIP(hipDeviceSynchronize());
+        h->setup_s = now_s() - t0;
+        h->ready = true;
+        return PS_OK;
+    });
+}
+
+static SolveOut run_solve(ps_handle *h, Krylov &K, bool fp32, const double *rhs, double *x, double rtol,
+                          hipStream_t st) {
+    std::unique_ptr<PrecFn> M;
+    if (fp32) M = std::make_unique<Prec32>(h);
+    else M = std::make_unique<Prec64>(h);
+    Fgmres run(h->dsys, K, *M, rhs, x, rtol, h->opt.maxit, st);
+    return fgmres_blocking(run, st);
+}
+
+static void check_solve_args(ps_handle *h, const double *rhs, const double *x, double rtol) {
+    if (!h) throw Error(PS_EINVAL, "handle is NULL");
+    if (!rhs || !x) throw Error(PS_EINVAL, "rhs/x is NULL");
+    if (!(rtol > 0.0) || !std::isfinite(rtol)) throw Error(PS_EINVAL, "rtol must be positive and finite");
+    if (!h->ready) throw Error(PS_ENOTSETUP, "ps_setup has not been called");
+}
+
+int ps_solve(ps_handle *h, const double *rhs, double *x, double rtol, void *stream, ps_result *res) {
+    int code = guard([&] {
+        check_solve_args(h, rhs, x, rtol);
+        bool expected = false;
+        if (!h->busy.compare_exchange_strong(expected, true)) throw Error(PS_EBUSY, "handle has a request in flight");
+        struct Unbusy {
+            ps_handle *h;
+            ~Unbusy() { h->busy = false; }
+        } ub{h};
+        set_device(h->ctx->device);
+        hipStream_t st = (hipStream_t)stream;
+        double t0 = now_s();
+        bool f32 = use_fp32(h);
+        if (!h->K || h->K->z_fp32 != f32) {
+            h->K = std::make_unique<Krylov>();
+            alloc_krylov(*h->K, h->sys.N(), h->opt.restart, f32);
+        }
+        SolveOut o = run_solve(h, *h->K, f32, rhs, x, rtol, st);
+        if (o.status == PS_EPRECISION && f32 && h->opt.fp32_fallback) {
+            Krylov K64;
+            alloc_krylov(K64, h->sys.N(), h->opt.restart, false);
+            o = run_solve(h, K64, false, rhs, x, rtol, st);
+        }
+        if (res) {
+            res->status = o.status;
+            res->iterations = o.iterations;
+            res->restarts = o.restarts;
+            res->rel_residual = o.rel_residual;
+            res->setup_s = h->setup_s;
+            res->solve_s = now_s() - t0;
+        }
+        return o.status;
+    });
+    if (code != PS_OK && res && code != PS_EMAXIT && code != PS_EPRECISION && code != PS_EBREAKDOWN)
+        res->status = code;
+    return code;
+}
+
+int ps_apply_precond(ps_handle *h, const double *v, double *z, void *stream) {
+    return guard([&] {
+        if (!h || !v || !z) throw Error(PS_EINVAL, "NULL argument");
+        if (!h->ready) throw Error(PS_ENOTSETUP, "ps_setup has not been called");
+        set_device(h->ctx->device);
+        hipStream_t st = (hipStream_t)stream;
+        if (use_fp32(h)) {
+            size_t N = h->sys.N();
+            if (!h->ztmp) h->ztmp = (double *)h->aux.alloc<float>(N);
+            Prec32 M(h);
+            M(v, h->ztmp, st);
+            widen_f32((const float *)h->ztmp, z, N, st);
+        } else {
+            Prec64 M(h);
+            M(v, z, st);
+        }
+        PS_HIP(hipGetLastError());
+        return PS_OK;
+    });
+}
+
+int ps_spmv(ps_handle *h, const double *x, double *y, void *stream) {
+    return guard([&] {
+        if (!h || !x || !y) throw Error(PS_EINVAL, "NULL argument");
+        set_device(h->ctx->device);
+        hipStream_t st = (hipStream_t)stream;
+        spmv_full<double>(h->dsys, x, nullptr, y, st);
+        PS_HIP(hipGetLastError());
+        return PS_OK;
+    });
+}
+
+int ps_footprint(ps_handle *h, size_t *bytes) {
+    return guard([&] {
+        if (!h || !bytes) throw Error(PS_EINVAL, "NULL argument");
+        *bytes = h->bytes();
+        return PS_OK;
+    });
+}
+
+void ps_destroy(ps_handle *h) {
+    if (!h) return;
+    (void)hipSetDevice(h->ctx->device);
+    (void)hipDeviceSynchronize();
+    delete h;
+}
+
+// ---------------------------------------------------------------- serving
+int ps_submit(ps_handle *h, const double *rhs, double *x, double rtol, uint64_t *ticket) {
+    return guard([&] {
+        check_solve_args(h, rhs, x, rtol);
+        if (!ticket) throw Error(PS_EINVAL, "ticket is NULL");
+        bool expected = false;
+        if (!h->busy.compare_exchange_strong(expected, true)) throw Error(PS_EBUSY, "handle has a request in flight");
+        ps_ctx *c = h->ctx;
+        auto r = std::make_unique<Request>();
+        r->ticket = c->next_ticket++;
+        r->h = h;
+        r->rhs = rhs;
+        r->x = x;
+        r->rtol = rtol;
+        r->t_submit = now_s();
+        r->bytes = h->krylov_bytes(use_fp32(h));
+        *ticket = r->ticket;
+        {
+            std::lock_guard<std::mutex> lk(c->mu);
+            if (c->stop) {
+                h->busy = false;
+                throw Error(PS_EBUSY, "context is shutting down");
+            }
+            c->queue.push_back(r.get());
+            c->requests[r->ticket] = std::move(r);
+        }
+        c->cv.notify_all();
+        return PS_OK;
+    });
+}
+
+static int take_result(ps_ctx *c, uint64_t ticket, ps_result *res, bool wait) {
+    std::unique_lock<std::mutex> lk(c->mu);
+    auto it = c->requests.find(ticket);
+    if (it == c->requests.end()) throw Error(PS_EINVAL, "unknown ticket");
+    if (wait) c->done_cv.wait(lk, [&] { return it->second->status != PS_PENDING; });
+    Request *r = it->second.get();
+    if (r->status == PS_PENDING) return PS_PENDING;
+    if (res) *res = r->res;
+    int s = r->status;
+    c->requests.erase(it);
+    return s;
+}
+
+int ps_poll(ps_ctx *c, uint64_t ticket, ps_result *res) {
+    return guard([&] {
+        if (!c) throw Error(PS_EINVAL, "ctx is NULL");
+        return take_result(c, ticket, res, false);
+    });
+}
+
+int ps_wait(ps_ctx *c, uint64_t ticket, ps_result *res) {
+    return guard([&] {
+        if (!c) throw Error(PS_EINVAL, "ctx is NULL");
+        return take_result(c, ticket, res, true);
+    });
+}
+
+}  // extern "C"
+
+// Iteration-level continuous batching: each tick advances every admitted request by
+// one piece of FGMRES work (one iteration or one cycle end) on its own stream, so the
+// device overlaps requests; queued requests are admitted whenever their device
+// footprint fits the budget, and finished ones leave at the tick boundary.
+void ps_ctx::scheduler() {
+    (void)hipSetDevice(device);
+    auto finish = [this](Request *r, int status, const SolveOut *o) {
+        r->res.status = status;
+        if (o) {
+            r->res.iterations = o->iterations;
+            r->res.restarts = o->restarts;
+            r->res.rel_residual = o->rel_residual;
+        }
+        r->res.setup_s = r->h->setup_s;
+        r->res.solve_s = now_s() - r->t_submit;
+        if (r->st) (void)hipStreamDestroy(r->st);
+        r->st = nullptr;
+        r->run.reset();
+        r->M.reset();
+        r->K.reset();
+        r->h->busy = false;
+        std::lock_guard<std::mutex> lk(mu);
+        used -= r->bytes;
+        r->status = status;
+        done_cv.notify_all();
+    };
+    for (;;) {
+        std::vector<Request *> admitted;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            cv.wait(lk, [&] { return stop || !queue.empty() || !active.empty(); });
+            if (stop && active.empty()) {
+                for (Request *r : queue) {
+                    r->status = PS_EBUSY;
+                    r->res.status = PS_EBUSY;
+                    r->h->busy = false;
+                }
+                queue.clear();
+                done_cv.notify_all();
+                return;
+            }
+            while (!queue.empty() && !stop) {
+                Request *r = queue.front();
+                if (!active.empty() && used + r->bytes > budget) break;
+                queue.pop_front();
+                used += r->bytes;
+                admitted.push_back(r);
+            }
+        }
+        for (Request *r : admitted) {
+            int code = guard([&] {
+                bool f32 = use_fp32(r->h);
+                PS_HIP(hipStreamCreateWithFlags(&r->st, hipStreamNonBlocking));
+                r->K = std::make_unique<Krylov>();
+                alloc_krylov(*r->K, r->h->sys.N(), r->h->opt.restart, f32);
+                if (f32) r->M = std::make_unique<Prec32>(r->h);
+                else r->M = std::make_unique<Prec64>(r->h);
+                r->run = std::make_unique<Fgmres>(r->h->dsys, *r->K, *r->M, r->rhs, r->x, r->rtol,
+                                                  r->h->opt.maxit, r->st);
+                r->t_start = now_s();
+                r->run->start();
+                return PS_OK;
+            });
+            if (code != PS_OK) finish(r, code, nullptr);
+            else active.push_back(r);
+        }
+        std::vector<Request *> still;
+        for (Request *r : active) {
+            bool more = false;
+            int code = guard([&] {
+                PS_HIP(hipStreamSynchronize(r->st));
+                more = r->run->advance();
+                return PS_OK;
+            });
+            if (code != PS_OK) {
+                finish(r, code, nullptr);
+            } else if (!more) {
+                (void)hipStreamSynchronize(r->st);
+                SolveOut o = r->run->out;
+                finish(r, o.status, &o);
+            } else {
+                still.push_back(r);
+            }
+        }
+        active.swap(still);
+    }
+}
+
+// ====================================================================== host setup ABI
+struct ps_host_setup {
+    System sys;
+    Options opt;
+    Hierarchy sdc;
+    FlowSetup flow;
+};
+
+extern "C" {
+
+int ps_host_setup_create(const ps_system *sys, const ps_options *opts, ps_host_setup **out) {
+    return guard([&] {
+        if (!out) throw Error(PS_EINVAL, "out is NULL");
+        *out = nullptr;
+        auto s = std::make_unique<ps_host_setup>();
+        ps_options def;
+        ps_default_options(&def);
+        s->opt = options_from(opts ? opts : &def);
+        validate_and_copy(sys, s->sys);
+        s->sdc = amg_build(sdc_matrix(s->sys), s->opt);
+        build_flow(s->sys, s->opt, s->flow);
+        *out = s.release();
+        return PS_OK;
+    });
+}
+
+void ps_host_setup_destroy(ps_host_setup *s) { delete s; }
+
+static const Hierarchy &pick(const ps_host_setup *s, int which) {
+    if (which == PS_H_SDC) return s->sdc;
+    if (which == PS_H_PRES) return s->flow.pres;
+    throw Error(PS_EINVAL, "which must be PS_H_SDC or PS_H_PRES");
+}
+
+int ps_host_levels(const ps_host_setup *s, int which, int32_t *nlevels) {
+    return guard([&] {
+        if (!s || !nlevels) throw Error(PS_EINVAL, "NULL argument");
+        *nlevels = (int32_t)pick(s, which).lev.size();
+        return PS_OK;
+    });
+}
+
+int ps_host_level(const ps_host_setup *s, int which, int lvl, int32_t *n, int32_t *nnz, int32_t *rowptr,
+                  int32_t *colind, double *vals, int8_t *cf, int32_t *nc, int32_t *p_nnz, int32_t *p_rowptr,
+                  int32_t *p_colind, double *p_vals) {
+    return guard([&] {
+        if (!s) throw Error(PS_EINVAL, "NULL argument");
+        const Hierarchy &H = pick(s, which);
+        if (lvl < 0 || lvl >= (int)H.lev.size()) throw Error(PS_EINVAL, "level out of range");
+        const Level &L = H.lev[lvl];
+        if (n) *n = L.A.n;
+        if (nnz) *nnz = L.A.nnz();
+        if (rowptr) std::memcpy(rowptr, L.A.rp.data(), L.A.rp.size() * sizeof(int32_t));
+        if (colind) std::memcpy(colind, L.A.ci.data(), L.A.ci.size() * sizeof(int32_t));
+        if (vals) std::memcpy(vals, L.A.v.data(), L.A.v.size() * sizeof(double));
+        if (cf) std::memcpy(cf, L.cf.data(), L.cf.size());
+        if (nc) *nc = L.P.m;
+        if (p_nnz) *p_nnz = L.P.nnz();
+        if (p_rowptr && !L.P.rp.empty()) std::memcpy(p_rowptr, L.P.rp.data(), L.P.rp.size() * sizeof(int32_t));
+        if (p_colind) std::memcpy(p_colind, L.P.ci.data(), L.P.ci.size() * sizeof(int32_t));
+        if (p_vals) std::memcpy(p_vals, L.P.v.data(), L.P.v.size() * sizeof(double));
+        return PS_OK;
+    });
+}
+
+int ps_host_level_lambda(const ps_host_setup *s, int which, int lvl, double *lam) {
+    return guard([&] {
+        if (!s || !lam) throw Error(PS_EINVAL, "NULL argument");
+        const Hierarchy &H = pick(s, which);
+        if (lvl < 0 || lvl >= (int)H.lev.size()) throw Error(PS_EINVAL, "level out of range");
+        *lam = H.lev[lvl].lam;
+        return PS_OK;
+    });
+}
+
+int ps_host_spp(const ps_host_setup *s, double *vals) {
+    return guard([&] {
+        if (!s || !vals) throw Error(PS_EINVAL, "NULL argument");
+        std::memcpy(vals, s->flow.Spp.v.data(), s->flow.Spp.v.size() * sizeof(double));
+        return PS_OK;
+    });
+}
+
+int ps_host_bilu(const ps_host_setup *s, double *vals) {
+    return guard([&] {
+        if (!s || !vals) throw Error(PS_EINVAL, "NULL argument");
+        if (s->opt.ml_kind != PS_BILU0) throw Error(PS_EINVAL, "setup was not built with PS_BILU0");
+        std::memcpy(vals, s->flow.ml.v.data(), s->flow.ml.v.size() * sizeof(double));
+        return PS_OK;
+    });
+}
+
+int ps_host_bilu_levels(const ps_host_setup *s, int32_t *fwd, int32_t *bwd) {
+    return guard([&] {
+        if (!s || !fwd || !bwd) throw Error(PS_EINVAL, "NULL argument");
+        *fwd = s->flow.sched.fwd_ptr.empty() ? 0 : (int32_t)s->flow.sched.fwd_ptr.size() - 1;
+        *bwd = s->flow.sched.bwd_ptr.empty() ? 0 : (int32_t)s->flow.sched.bwd_ptr.size() - 1;
+        return PS_OK;
+    });
+}
+
+}  // extern "C"

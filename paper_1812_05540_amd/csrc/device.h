@@ -1,0 +1,232 @@
+// Device-side data of a handle and the solve-phase drivers (HIP, gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <memory>
+#include <vector>
+
+#include "host_setup.h"
+
+namespace ps {
+
+void hip_check(hipError_t e, const char *what);
+#define PS_HIP(x) ::ps::hip_check((x), #x)
+
+// Device allocations owned by one object; freed together.
+class Arena {
+  public:
+    Arena() = default;
+    Arena(const Arena &) = delete;
+    Arena &operator=(const Arena &) = delete;
+    Arena(Arena &&o) noexcept : ptrs_(std::move(o.ptrs_)), bytes_(o.bytes_) { o.bytes_ = 0; }
+    Arena &operator=(Arena &&o) noexcept {
+        if (this != &o) {
+            release();
+            ptrs_ = std::move(o.ptrs_);
+            bytes_ = o.bytes_;
+            o.bytes_ = 0;
+        }
+        return *this;
+    }
+    ~Arena() { release(); }
+    template <typename T>
+    T *alloc(size_t n) {
+        if (n == 0) n = 1;
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, n * sizeof(T));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            throw Error(PS_ENOMEM, "hipMalloc failed");
+        }
+        ptrs_.push_back(p);
+        bytes_ += n * sizeof(T);
+        return static_cast<T *>(p);
+    }
+    template <typename T>
+    T *upload(const T *h, size_t n) {
+        T *d = alloc<T>(n);
+        if (n) PS_HIP(hipMemcpy(d, h, n * sizeof(T), hipMemcpyHostToDevice));
+        return d;
+    }
+    void release() {
+        for (void *p : ptrs_) (void)hipFree(p);
+        ptrs_.clear();
+        bytes_ = 0;
+    }
+    size_t bytes() const { return bytes_; }
+
+  private:
+    std::vector<void *> ptrs_;
+    size_t bytes_ = 0;
+};
+
+// Sliced ELLPACK with 64-row chunks (one wavefront per chunk) over br x bc blocks.
+// Chunk c holds slots [cptr[c], cptr[c+1]); slot k of row lane l stores its column
+// at col[k*64 + l] and block element e at val[(k*br*bc + e)*64 + l], so every load
+// instruction of a wavefront reads 64 consecutive words.  Padding slots have
+// column 0 and zero values.  rowmap (optional) maps the sliced row position to
+// the matrix row (-1 for padding rows); without it position == row.
+template <typename T>
+struct Sell {
+    int nrows = 0, nchunks = 0, br = 1, bc = 1;
+    const int *cptr = nullptr;
+    const int *col = nullptr;
+    const T *val = nullptr;
+    const int *rowmap = nullptr;
+    size_t nslots = 0;
+};
+
+struct HostSell {                 // host image of a Sell before upload
+    int nrows = 0, nchunks = 0, br = 1, bc = 1;
+    std::vector<int> cptr, col, rowmap;
+    std::vector<double> val;
+};
+
+HostSell sell_from_bsr(const std::vector<int> &rp, const std::vector<int> &ci,
+                       const std::vector<double> &v, int nbr, int br, int bc,
+                       const std::vector<int> *row_order = nullptr,
+                       bool (*keep)(int row, int col) = nullptr);
+HostSell sell_from_csr(const Csr &A);
+template <typename T>
+Sell<T> upload_sell(Arena &ar, const HostSell &h);
+
+// ---- preconditioner device data ------------------------------------------------
+template <typename T>
+struct DLevel {                   // matrices and per-row constants of one AMG level
+    int n = 0;
+    Sell<T> A, P, R;
+    const T *dinv = nullptr;      // l1-Jacobi: 1 / (a_ii + sum |a_ij|)
+    const T *c0 = nullptr, *c1 = nullptr, *cm = nullptr;   // Chebyshev
+};
+
+template <typename T>
+struct DHierarchy {
+    std::vector<DLevel<T>> lev;   // coarsest last (only n used there)
+    const double *cinv = nullptr; // dense inverse of the coarsest operator (FP64)
+    int cn = 0;
+    int smoother = PS_CHEB2;
+    Arena arena;
+    size_t bytes() const { return arena.bytes(); }
+};
+
+template <typename T>
+struct HierWork {                 // per-handle vectors of one hierarchy
+    std::vector<T *> x, x1, d, r; // smoother iterate, temp, Chebyshev step, residual
+    std::vector<T *> b, e;        // right-hand side and result of level l >= 1
+};
+
+template <typename T>
+struct DFlow {                    // flow stage of Algorithm 1 (rebuilt every setup)
+    int nc = 0, nf = 0, ml_kind = PS_BILU0, ml_sweeps = 1;
+    Sell<T> Afu, Sff;             // nf x 3 and nf x nf
+    const T *dss_inv = nullptr;   // nc * (nf-1)^2
+    std::unique_ptr<DHierarchy<T>> pres;
+    // local stage
+    Sell<T> Lf, Ub;               // BILU strict lower / upper blocks, rows in level order
+    std::vector<int> lchunk_f, lchunk_b;   // chunk ranges per level
+    const T *dinv = nullptr;      // BILU D_i^{-1} or block-Jacobi D^{-1}, nc * nf * nf
+    Arena arena;
+    size_t bytes() const { return arena.bytes() + (pres ? pres->bytes() : 0); }
+};
+
+template <typename T>
+struct PrecWork {                 // per-handle work vectors for Algorithm 1
+    HierWork<T> sdc, pres;
+    T *vconv = nullptr;           // v_u rounded to T (FP32 path)
+    T *y = nullptr, *zs = nullptr, *wp = nullptr, *zp = nullptr;   // steps 2-5
+    T *w = nullptr, *t = nullptr, *dz = nullptr, *r2 = nullptr;    // steps 6-8
+    Arena arena;
+};
+
+struct DSystem {                  // FP64 system matrix for A z and the true residual
+    int n_nodes = 0, n_cells = 0, nf = 0;
+    Sell<double> Auu, Auf, Afu, Aff;
+    Arena arena;
+};
+
+struct Krylov {                   // FGMRES workspace (FP64 basis, Z in the precond type)
+    int m = 0, nblk = 0, chunk = 0;
+    size_t N = 0;
+    bool z_fp32 = false;
+    double *V = nullptr;          // (m+1) x N
+    void *Z = nullptr;            // m x N (double or float)
+    double *H = nullptr;          // (m+1) x m, column-major, Givens-rotated
+    double *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr;
+    double *h1 = nullptr, *h2 = nullptr, *hsum = nullptr, *nw2 = nullptr;
+    double *scal = nullptr;       // [|g_j+1|, h_j+1,j, |A z_j|, breakdown, beta, |r|^2, -, -]
+    double *partial = nullptr;    // (m+2) x nblk reduction partials
+    double *r = nullptr;          // true residual
+    double *hostscal = nullptr;   // pinned host mirror of scal
+    Arena arena;
+    ~Krylov();
+};
+
+template <typename T>
+std::unique_ptr<DHierarchy<T>> upload_hierarchy(const Hierarchy &H, int smoother, bool interleave3);
+template <typename T>
+std::unique_ptr<DFlow<T>> upload_flow(const FlowSetup &f, const System &s, const Options &o);
+void upload_system(const System &s, DSystem &d);
+template <typename T>
+void alloc_prec_work(PrecWork<T> &w, const DHierarchy<T> &sdc, const DFlow<T> &fl, int n_nodes);
+void alloc_krylov(Krylov &k, size_t N, int m, bool z_fp32);
+
+// y = A x (FP64), or y = b - A x when b != nullptr; x of type TX.
+template <typename TX>
+void spmv_full(const DSystem &S, const TX *x, const double *b, double *y, hipStream_t st);
+
+// z = M^{-1} v (Algorithm 1); v FP64, z of type T (length N).
+template <typename T>
+void apply_precond(const DHierarchy<T> &sdc, const DFlow<T> &fl, PrecWork<T> &w, int n_nodes,
+                   const double *v, T *z, hipStream_t st);
+
+struct SolveOut {
+    int status = PS_OK, iterations = 0, restarts = 0;
+    double rel_residual = 0.0;
+};
+
+// Preconditioner callback: z (double or float, per Krylov::z_fp32) = M^{-1} v.
+struct PrecFn {
+    virtual void operator()(const double *v, void *z, hipStream_t st) = 0;
+    virtual ~PrecFn() = default;
+};
+
+// Right-preconditioned flexible GMRES(m) with CGS2 and Givens rotations (paper
+// Sec. 4), as a resumable state machine: start() enqueues the first work, and
+// after each stream synchronisation advance() consumes the 64-byte scalar
+// read-back and enqueues the next piece (one iteration, or the end of a cycle).
+// advance() returns false once `out` is final.  The serving scheduler interleaves
+// many of these, one per request and stream.
+class Fgmres {
+  public:
+    Fgmres(const DSystem &S, Krylov &K, PrecFn &M, const double *b, double *x, double rtol, int maxit,
+           hipStream_t st);
+    void start();
+    bool advance();
+    SolveOut out;
+
+  private:
+    enum Phase { START, ITER, CYCLE_END, DONE };
+    void copy_scal();
+    void begin_cycle(const double *r);
+    void enqueue_iteration();
+    void end_cycle(int k);
+    const DSystem &S_;
+    Krylov &K_;
+    PrecFn &M_;
+    const double *b_;
+    double *x_;
+    double rtol_;
+    int maxit_;
+    hipStream_t st_;
+    Phase phase_ = START;
+    int j_ = 0, its_ = 0, cycles_ = 0;
+    double beta_b_ = 0.0;
+    bool breakdown_ = false;
+};
+SolveOut fgmres_blocking(Fgmres &run, hipStream_t st);
+
+void fill_zero(double *p, size_t n, hipStream_t st);
+void widen_f32(const float *in, double *out, size_t n, hipStream_t st);
+
+}  // namespace ps

@@ -1,0 +1,627 @@
+// Device data layout, uploads and the solve-phase drivers (Algorithm 1, FGMRES).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "kernels.h"
+
+namespace ps {
+
+using k::WG;
+
+void hip_check(hipError_t e, const char *what) {
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error(PS_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    }
+}
+
+static inline unsigned grid_for(size_t n) { return (unsigned)((n + WG - 1) / WG); }
+
+#define LAUNCH(kernel, grid, shm, st, ...)                                             \
+    do {                                                                               \
+        if ((grid) > 0) hipLaunchKernelGGL(kernel, dim3(grid), dim3(WG), shm, st, __VA_ARGS__); \
+    } while (0)
+
+// ------------------------------------------------------------------ SELL
+HostSell sell_from_bsr(const std::vector<int> &rp, const std::vector<int> &ci, const std::vector<double> &v,
+                       int nbr, int br, int bc, const std::vector<int> *row_order,
+                       bool (*keep)(int, int)) {
+    HostSell h;
+    h.br = br;
+    h.bc = bc;
+    const int rc = br * bc;
+    std::vector<int> order;
+    if (row_order) {
+        order = *row_order;
+    } else {
+        order.resize(nbr);
+        std::iota(order.begin(), order.end(), 0);
+    }
+    h.nrows = (int)order.size();
+    h.nchunks = (h.nrows + 63) / 64;
+    auto count = [&](int row) {
+        if (row < 0) return 0;
+        if (!keep) return rp[row + 1] - rp[row];
+        int c = 0;
+        for (int t = rp[row]; t < rp[row + 1]; ++t) c += keep(row, ci[t]);
+        return c;
+    };
+    h.cptr.assign(h.nchunks + 1, 0);
+    for (int ch = 0; ch < h.nchunks; ++ch) {
+        int w = 0;
+        for (int l = 0; l < 64; ++l) {
+            int pos = ch * 64 + l;
+            if (pos < h.nrows) w = std::max(w, count(order[pos]));
+        }
+        h.cptr[ch + 1] = h.cptr[ch] + w;
+    }
+    size_t nslots = (size_t)h.cptr[h.nchunks];
+    h.col.assign(nslots * 64, 0);
+    h.val.assign(nslots * 64 * rc, 0.0);
+    for (int pos = 0; pos < h.nrows; ++pos) {
+        int row = order[pos];
+        if (row < 0) continue;
+        int ch = pos >> 6, lane = pos & 63;
+        size_t s0 = (size_t)h.cptr[ch];
+        int kk = 0;
+        for (int t = rp[row]; t < rp[row + 1]; ++t) {
+            if (keep && !keep(row, ci[t])) continue;
+            h.col[(s0 + kk) * 64 + lane] = ci[t];
+            for (int e = 0; e < rc; ++e) h.val[((s0 + kk) * rc + e) * 64 + lane] = v[(size_t)t * rc + e];
+            ++kk;
+        }
+    }
+    if (row_order) h.rowmap = order;
+    return h;
+}
+
+HostSell sell_from_csr(const Csr &A) { return sell_from_bsr(A.rp, A.ci, A.v, A.n, 1, 1); }
+
+template <typename T>
+Sell<T> upload_sell(Arena &ar, const HostSell &h) {
+    Sell<T> s;
+    s.nrows = h.nrows;
+    s.nchunks = h.nchunks;
+    s.br = h.br;
+    s.bc = h.bc;
+    s.nslots = h.cptr.empty() ? 0 : (size_t)h.cptr.back();
+    s.cptr = ar.upload(h.cptr.data(), h.cptr.size());
+    s.col = ar.upload(h.col.data(), h.col.size());
+    std::vector<T> vt(h.val.begin(), h.val.end());
+    s.val = ar.upload(vt.data(), vt.size());
+    if (!h.rowmap.empty()) s.rowmap = ar.upload(h.rowmap.data(), h.rowmap.size());
+    return s;
+}
+
+template <typename T>
+static const T *upload_vec(Arena &ar, const std::vector<double> &v) {
+    std::vector<T> t(v.begin(), v.end());
+    return ar.upload(t.data(), t.size());
+}
+
+// Level 0 of the separate-displacement-component hierarchy is stored in the
+// interleaved (node-major) order of z_u: component-major index c*nn + i -> 3 i + c.
+static void interleave_level0(Csr &A, Csr &P, Csr &R, std::vector<std::vector<double> *> vecs) {
+    int n = A.n, nn = n / 3;
+    auto il = [nn](int a) { return 3 * (a % nn) + a / nn; };
+    auto permute_rows = [&](const Csr &M, bool map_cols) {
+        Csr out;
+        out.n = M.n;
+        out.m = M.m;
+        out.rp.assign(M.n + 1, 0);
+        std::vector<int> src(M.n);
+        for (int a = 0; a < M.n; ++a) src[il(a)] = a;
+        std::vector<std::pair<int, double>> row;
+        for (int r = 0; r < M.n; ++r) {
+            int a = src[r];
+            row.clear();
+            for (int t = M.rp[a]; t < M.rp[a + 1]; ++t)
+                row.push_back({map_cols ? il(M.ci[t]) : M.ci[t], M.v[t]});
+            std::sort(row.begin(), row.end(), [](auto &x, auto &y) { return x.first < y.first; });
+            for (auto &e : row) {
+                out.ci.push_back(e.first);
+                out.v.push_back(e.second);
+            }
+            out.rp[r + 1] = (int)out.ci.size();
+        }
+        return out;
+    };
+    A = permute_rows(A, true);
+    P = permute_rows(P, false);
+    Csr Rn = R;
+    for (int r = 0; r < R.n; ++r) {
+        std::vector<std::pair<int, double>> row;
+        for (int t = R.rp[r]; t < R.rp[r + 1]; ++t) row.push_back({il(R.ci[t]), R.v[t]});
+        std::sort(row.begin(), row.end(), [](auto &x, auto &y) { return x.first < y.first; });
+        for (size_t q = 0; q < row.size(); ++q) {
+            Rn.ci[R.rp[r] + q] = row[q].first;
+            Rn.v[R.rp[r] + q] = row[q].second;
+        }
+    }
+    R = std::move(Rn);
+    for (auto *v : vecs) {
+        if (v->empty()) continue;
+        std::vector<double> o(v->size());
+        for (int a = 0; a < n; ++a) o[il(a)] = (*v)[a];
+        *v = std::move(o);
+    }
+}
+
+template <typename T>
+std::unique_ptr<DHierarchy<T>> upload_hierarchy(const Hierarchy &H, int smoother, bool interleave3) {
+    auto d = std::make_unique<DHierarchy<T>>();
+    d->smoother = smoother;
+    int nl = (int)H.lev.size();
+    d->lev.resize(nl);
+    for (int l = 0; l + 1 < nl; ++l) {
+        const Level &L = H.lev[l];
+        Csr A = L.A, P = L.P, R = L.R;
+        std::vector<double> dl1 = L.dl1, c0 = L.c0, c1 = L.c1, cm = L.cm;
+        if (l == 0 && interleave3) interleave_level0(A, P, R, {&dl1, &c0, &c1, &cm});
+        DLevel<T> &D = d->lev[l];
+        D.n = A.n;
+        D.A = upload_sell<T>(d->arena, sell_from_csr(A));
+        D.P = upload_sell<T>(d->arena, sell_from_csr(P));
+        D.R = upload_sell<T>(d->arena, sell_from_csr(R));
+        if (smoother == PS_L1JAC) {
+            std::vector<double> inv(dl1.size());
+            for (size_t i = 0; i < dl1.size(); ++i) inv[i] = 1.0 / dl1[i];
+            D.dinv = upload_vec<T>(d->arena, inv);
+        } else {
+            D.c0 = upload_vec<T>(d->arena, c0);
+            D.c1 = upload_vec<T>(d->arena, c1);
+            D.cm = upload_vec<T>(d->arena, cm);
+        }
+    }
+    d->lev[nl - 1].n = H.coarse_n;
+    d->cn = H.coarse_n;
+    d->cinv = d->arena.upload(H.coarse_inv.data(), H.coarse_inv.size());
+    return d;
+}
+
+static bool keep_lower(int row, int col) { return col < row; }
+static bool keep_upper(int row, int col) { return col > row; }
+
+template <typename T>
+std::unique_ptr<DFlow<T>> upload_flow(const FlowSetup &f, const System &s, const Options &o) {
+    auto d = std::make_unique<DFlow<T>>();
+    const int nf = s.nf, nc = s.n_cells, nn = nf * nf;
+    d->nc = nc;
+    d->nf = nf;
+    d->ml_kind = o.ml_kind;
+    d->ml_sweeps = o.ml_sweeps;
+    d->Afu = upload_sell<T>(d->arena, sell_from_bsr(s.Afu.rp, s.Afu.ci, s.Afu.v, nc, nf, 3));
+    d->Sff = upload_sell<T>(d->arena, sell_from_bsr(f.Sff.rp, f.Sff.ci, f.Sff.v, nc, nf, nf));
+    d->dss_inv = upload_vec<T>(d->arena, f.dss_inv);
+    d->pres = upload_hierarchy<T>(f.pres, o.smoother, false);
+    std::vector<double> dinv((size_t)nc * nn);
+    if (o.ml_kind == PS_BILU0) {
+        auto order = [&](const std::vector<int> &ptr, const std::vector<int> &rows, std::vector<int> &lchunk) {
+            std::vector<int> ord;
+            lchunk.assign(1, 0);
+            for (size_t l = 0; l + 1 < ptr.size(); ++l) {
+                for (int p = ptr[l]; p < ptr[l + 1]; ++p) ord.push_back(rows[p]);
+                while (ord.size() % 64) ord.push_back(-1);
+                lchunk.push_back((int)(ord.size() / 64));
+            }
+            return ord;
+        };
+        std::vector<int> of = order(f.sched.fwd_ptr, f.sched.fwd_rows, d->lchunk_f);
+        std::vector<int> ob = order(f.sched.bwd_ptr, f.sched.bwd_rows, d->lchunk_b);
+        d->Lf = upload_sell<T>(d->arena, sell_from_bsr(f.ml.rp, f.ml.ci, f.ml.v, nc, nf, nf, &of, keep_lower));
+        d->Ub = upload_sell<T>(d->arena, sell_from_bsr(f.ml.rp, f.ml.ci, f.ml.v, nc, nf, nf, &ob, keep_upper));
+        for (int i = 0; i < nc; ++i)
+            for (int t = f.ml.rp[i]; t < f.ml.rp[i + 1]; ++t)
+                if (f.ml.ci[t] == i) std::memcpy(&dinv[(size_t)i * nn], &f.ml.v[(size_t)t * nn], sizeof(double) * nn);
+    } else {
+        dinv = f.ml.v;
+    }
+    d->dinv = upload_vec<T>(d->arena, dinv);
+    return d;
+}
+
+void upload_system(const System &s, DSystem &d) {
+    d.n_nodes = s.n_nodes;
+    d.n_cells = s.n_cells;
+    d.nf = s.nf;
+    d.Auu = upload_sell<double>(d.arena, sell_from_bsr(s.Auu.rp, s.Auu.ci, s.Auu.v, s.n_nodes, 3, 3));
+    d.Auf = upload_sell<double>(d.arena, sell_from_bsr(s.Auf.rp, s.Auf.ci, s.Auf.v, s.n_nodes, 3, s.nf));
+    d.Afu = upload_sell<double>(d.arena, sell_from_bsr(s.Afu.rp, s.Afu.ci, s.Afu.v, s.n_cells, s.nf, 3));
+    d.Aff = upload_sell<double>(d.arena, sell_from_bsr(s.Aff.rp, s.Aff.ci, s.Aff.v, s.n_cells, s.nf, s.nf));
+}
+
+template <typename T>
+static void alloc_hier_work(HierWork<T> &w, const DHierarchy<T> &H, Arena &ar) {
+    int nl = (int)H.lev.size();
+    w.x.assign(nl, nullptr);
+    w.x1.assign(nl, nullptr);
+    w.d.assign(nl, nullptr);
+    w.r.assign(nl, nullptr);
+    w.b.assign(nl, nullptr);
+    w.e.assign(nl, nullptr);
+    for (int l = 0; l < nl; ++l) {
+        size_t n = H.lev[l].n;
+        if (l + 1 < nl) {
+            w.x[l] = ar.template alloc<T>(n);
+            w.x1[l] = ar.template alloc<T>(n);
+            w.d[l] = ar.template alloc<T>(n);
+            w.r[l] = ar.template alloc<T>(n);
+        }
+        if (l > 0) {
+            w.b[l] = ar.template alloc<T>(n);
+            w.e[l] = ar.template alloc<T>(n);
+        }
+    }
+}
+
+template <typename T>
+void alloc_prec_work(PrecWork<T> &w, const DHierarchy<T> &sdc, const DFlow<T> &fl, int n_nodes) {
+    w.arena.release();
+    alloc_hier_work(w.sdc, sdc, w.arena);
+    alloc_hier_work(w.pres, *fl.pres, w.arena);
+    size_t nfl = (size_t)fl.nc * fl.nf;
+    if (sizeof(T) == 4) w.vconv = w.arena.template alloc<T>((size_t)3 * n_nodes);
+    w.y = w.arena.template alloc<T>(nfl);
+    w.zs = w.arena.template alloc<T>((size_t)fl.nc * (fl.nf - 1));
+    w.wp = w.arena.template alloc<T>(fl.nc);
+    w.zp = w.arena.template alloc<T>(fl.nc);
+    w.w = w.arena.template alloc<T>(nfl);
+    w.t = w.arena.template alloc<T>(nfl);
+    w.dz = w.arena.template alloc<T>(nfl);
+    w.r2 = w.arena.template alloc<T>(nfl);
+}
+
+// ------------------------------------------------------------------ V-cycle
+template <typename T>
+static void vcycle(const DHierarchy<T> &H, HierWork<T> &W, int l, const T *b, T *out, hipStream_t st) {
+    const int last = (int)H.lev.size() - 1;
+    if (l == last) {
+        unsigned g = (unsigned)((H.cn + (WG / 64) - 1) / (WG / 64));
+        LAUNCH(k::coarse_solve<T>, g, 0, st, H.cinv, H.cn, b, out);
+        return;
+    }
+    const DLevel<T> &L = H.lev[l];
+    unsigned g = grid_for(L.n);
+    if (H.smoother == PS_CHEB2) {
+        LAUNCH((k::cheb_pre<T>), g, 0, st, L.A, b, L.c0, L.c1, L.cm, W.x[l]);
+        LAUNCH((k::spmv<1, 1, T, T, T, 1>), g, 0, st, L.A, (const T *)W.x[l], b, W.r[l]);
+    } else {
+        LAUNCH((k::l1_pre<T>), g, 0, st, L.A, b, L.dinv, W.x[l], W.r[l]);
+    }
+    LAUNCH((k::spmv<1, 1, T, T, T, 0>), grid_for(H.lev[l + 1].n), 0, st, L.R, (const T *)W.r[l],
+           (const T *)nullptr, W.b[l + 1]);
+    vcycle(H, W, l + 1, W.b[l + 1], W.e[l + 1], st);
+    LAUNCH((k::spmv<1, 1, T, T, T, 2>), g, 0, st, L.P, (const T *)W.e[l + 1], (const T *)nullptr, W.x[l]);
+    if (H.smoother == PS_CHEB2) {
+        LAUNCH((k::cheb_post1<T>), g, 0, st, L.A, b, (const T *)W.x[l], L.c0, W.x1[l], W.d[l]);
+        LAUNCH((k::cheb_post2<T>), g, 0, st, L.A, b, (const T *)W.x1[l], (const T *)W.d[l], L.c1, L.cm, out);
+    } else {
+        LAUNCH((k::l1_post<T>), g, 0, st, L.A, b, (const T *)W.x[l], L.dinv, out);
+    }
+}
+
+// ------------------------------------------------------------------ Algorithm 1
+template <int NF, typename T>
+static void local_stage(const DFlow<T> &fl, PrecWork<T> &w, T *zf, hipStream_t st) {
+    const int sweeps = fl.ml_sweeps;
+    unsigned g = grid_for(fl.nc);
+    if (fl.ml_kind == PS_BJACOBI) {
+        T *bufs[2] = {w.dz, w.r2};
+        for (int s = 0; s < sweeps; ++s) {
+            bool first = s == 0, final = s == sweeps - 1;
+            const T *din = bufs[s & 1];
+            T *dout = bufs[(s + 1) & 1];
+            if (first && final)
+                LAUNCH((k::bjacobi<NF, T, true, true>), g, 0, st, fl.Sff, w.w, fl.dinv, din, dout, w.zs, w.zp, zf);
+            else if (first)
+                LAUNCH((k::bjacobi<NF, T, true, false>), g, 0, st, fl.Sff, w.w, fl.dinv, din, dout, w.zs, w.zp, zf);
+            else if (final)
+                LAUNCH((k::bjacobi<NF, T, false, true>), g, 0, st, fl.Sff, w.w, fl.dinv, din, dout, w.zs, w.zp, zf);
+            else
+                LAUNCH((k::bjacobi<NF, T, false, false>), g, 0, st, fl.Sff, w.w, fl.dinv, din, dout, w.zs, w.zp, zf);
+        }
+        return;
+    }
+    for (int s = 0; s < sweeps; ++s) {
+        const T *src = w.w;
+        if (s > 0) {
+            LAUNCH((k::spmv<NF, NF, T, T, T, 1>), g, 0, st, fl.Sff, (const T *)w.dz, (const T *)w.w, w.r2);
+            src = w.r2;
+        }
+        for (size_t l = 0; l + 1 < fl.lchunk_f.size(); ++l) {
+            int p0 = fl.lchunk_f[l] * 64, p1 = fl.lchunk_f[l + 1] * 64;
+            LAUNCH((k::bilu_fwd<NF, T>), grid_for(p1 - p0), 0, st, fl.Lf, p0, p1, src, w.t);
+        }
+        bool final = s == sweeps - 1;
+        for (size_t l = 0; l + 1 < fl.lchunk_b.size(); ++l) {
+            int p0 = fl.lchunk_b[l] * 64, p1 = fl.lchunk_b[l + 1] * 64;
+            unsigned gl = grid_for(p1 - p0);
+            if (s == 0 && final)
+                LAUNCH((k::bilu_bwd<NF, T, false, true>), gl, 0, st, fl.Ub, p0, p1, w.t, fl.dinv, w.dz, w.zs, w.zp, zf);
+            else if (s == 0)
+                LAUNCH((k::bilu_bwd<NF, T, false, false>), gl, 0, st, fl.Ub, p0, p1, w.t, fl.dinv, w.dz, w.zs, w.zp, zf);
+            else if (final)
+                LAUNCH((k::bilu_bwd<NF, T, true, true>), gl, 0, st, fl.Ub, p0, p1, w.t, fl.dinv, w.dz, w.zs, w.zp, zf);
+            else
+                LAUNCH((k::bilu_bwd<NF, T, true, false>), gl, 0, st, fl.Ub, p0, p1, w.t, fl.dinv, w.dz, w.zs, w.zp, zf);
+        }
+    }
+}
+
+template <int NF, typename T>
+static void flow_stage(const DFlow<T> &fl, PrecWork<T> &w, const double *vf, const T *zu, T *zf,
+                       hipStream_t st) {
+    unsigned g = grid_for(fl.nc);
+    LAUNCH((k::step23<NF, T>), g, 0, st, fl.Afu, vf, zu, fl.dss_inv, w.y, w.zs);     // steps 2-3
+    LAUNCH((k::step4<NF, T>), g, 0, st, fl.Sff, (const T *)w.y, (const T *)w.zs, w.wp); // step 4
+    vcycle(*fl.pres, w.pres, 0, (const T *)w.wp, w.zp, st);                             // step 5
+    LAUNCH((k::step6<NF, T>), g, 0, st, fl.Sff, (const T *)w.y, (const T *)w.zs, (const T *)w.zp, w.w);  // step 6
+    local_stage<NF, T>(fl, w, zf, st);                                                 // steps 7-8
+}
+
+template <typename T>
+void apply_precond(const DHierarchy<T> &sdc, const DFlow<T> &fl, PrecWork<T> &w, int n_nodes,
+                   const double *v, T *z, hipStream_t st) {
+    size_t nu = (size_t)3 * n_nodes;
+    const T *vu;
+    if constexpr (sizeof(T) == 4) {
+        LAUNCH((k::convert<double, T>), grid_for(nu), 0, st, v, w.vconv, nu);
+        vu = w.vconv;
+    } else {
+        vu = reinterpret_cast<const T *>(v);
+    }
+    T *zu = z, *zf = z + nu;
+    vcycle(sdc, w.sdc, 0, vu, zu, st);                                                 // step 1
+    if (fl.nf == 2) flow_stage<2, T>(fl, w, v + nu, zu, zf, st);
+    else flow_stage<3, T>(fl, w, v + nu, zu, zf, st);
+}
+
+// ------------------------------------------------------------------ system SpMV
+template <int NF, typename TX>
+static void spmv_full_nf(const DSystem &S, const TX *x, const double *b, double *y, hipStream_t st) {
+    size_t nu = (size_t)3 * S.n_nodes;
+    if (b) {
+        LAUNCH((k::spmv2<3, 3, NF, TX, true>), grid_for(S.n_nodes), 0, st, S.Auu, x, S.Auf, x + nu, b, y);
+        LAUNCH((k::spmv2<NF, 3, NF, TX, true>), grid_for(S.n_cells), 0, st, S.Afu, x, S.Aff, x + nu, b + nu, y + nu);
+    } else {
+        LAUNCH((k::spmv2<3, 3, NF, TX, false>), grid_for(S.n_nodes), 0, st, S.Auu, x, S.Auf, x + nu, b, y);
+        LAUNCH((k::spmv2<NF, 3, NF, TX, false>), grid_for(S.n_cells), 0, st, S.Afu, x, S.Aff, x + nu, b, y + nu);
+    }
+}
+
+template <typename TX>
+void spmv_full(const DSystem &S, const TX *x, const double *b, double *y, hipStream_t st) {
+    if (S.nf == 2) spmv_full_nf<2, TX>(S, x, b, y, st);
+    else spmv_full_nf<3, TX>(S, x, b, y, st);
+}
+
+// ------------------------------------------------------------------ Krylov workspace
+Krylov::~Krylov() {
+    if (hostscal) (void)hipHostFree(hostscal);
+}
+
+void alloc_krylov(Krylov &K, size_t N, int m, bool z_fp32) {
+    K.arena.release();
+    if (K.hostscal) {
+        (void)hipHostFree(K.hostscal);
+        K.hostscal = nullptr;
+    }
+    K.m = m;
+    K.N = N;
+    K.z_fp32 = z_fp32;
+    K.nblk = (int)std::min<size_t>(1024, std::max<size_t>(1, (N + 255) / 256));
+    size_t chunk = (N + K.nblk - 1) / K.nblk;
+    K.chunk = (int)((chunk + 63) / 64 * 64);
+    K.V = K.arena.alloc<double>((size_t)(m + 1) * N);
+    K.Z = z_fp32 ? (void *)K.arena.alloc<float>((size_t)m * N) : (void *)K.arena.alloc<double>((size_t)m * N);
+    K.H = K.arena.alloc<double>((size_t)(m + 1) * m);
+    K.cs = K.arena.alloc<double>(m);
+    K.sn = K.arena.alloc<double>(m);
+    K.g = K.arena.alloc<double>(m + 1);
+    K.y = K.arena.alloc<double>(m);
+    K.h1 = K.arena.alloc<double>(m + 2);
+    K.h2 = K.arena.alloc<double>(m + 2);
+    K.hsum = K.arena.alloc<double>(m + 2);
+    K.nw2 = K.arena.alloc<double>(2);
+    K.scal = K.arena.alloc<double>(8);
+    K.partial = K.arena.alloc<double>((size_t)(m + 2) * K.nblk);
+    K.r = K.arena.alloc<double>(N);
+    PS_HIP(hipHostMalloc((void **)&K.hostscal, 8 * sizeof(double), hipHostMallocDefault));
+}
+
+// partial[...] <- chunk sums; rows = nv (+1 for |w|^2)
+static void launch_mdot(const Krylov &K, const double *V, int nv, const double *w, bool norm, hipStream_t st) {
+    bool lds = K.chunk <= 7680;          // <= 60 KB of LDS per workgroup
+    size_t shm = lds ? (size_t)K.chunk * sizeof(double) : 0;
+    if (norm && lds)
+        LAUNCH((k::mdot<true, true>), K.nblk, shm, st, V, K.N, nv, w, K.N, K.chunk, K.partial, K.nblk);
+    else if (norm)
+        LAUNCH((k::mdot<true, false>), K.nblk, shm, st, V, K.N, nv, w, K.N, K.chunk, K.partial, K.nblk);
+    else if (lds)
+        LAUNCH((k::mdot<false, true>), K.nblk, shm, st, V, K.N, nv, w, K.N, K.chunk, K.partial, K.nblk);
+    else
+        LAUNCH((k::mdot<false, false>), K.nblk, shm, st, V, K.N, nv, w, K.N, K.chunk, K.partial, K.nblk);
+}
+
+// out[0] <- |w|^2 (deterministic)
+static void norm2_dev(const Krylov &K, const double *w, double *out, hipStream_t st) {
+    launch_mdot(K, nullptr, 0, w, true, st);
+    LAUNCH(k::reduce_rows, 1, 0, st, (const double *)K.partial, K.nblk, out, (const double *)nullptr,
+           (double *)nullptr);
+}
+
+void fill_zero(double *p, size_t n, hipStream_t st) {
+    LAUNCH((k::fill<double>), grid_for(n), 0, st, p, 0.0, n);
+}
+
+void widen_f32(const float *in, double *out, size_t n, hipStream_t st) {
+    LAUNCH((k::convert<float, double>), grid_for(n), 0, st, in, out, n);
+}
+
+// ------------------------------------------------------------------ FGMRES
+Fgmres::Fgmres(const DSystem &S, Krylov &K, PrecFn &M, const double *b, double *x, double rtol, int maxit,
+               hipStream_t st)
+    : S_(S), K_(K), M_(M), b_(b), x_(x), rtol_(rtol), maxit_(maxit), st_(st) {}
+
+void Fgmres::copy_scal() {
+    PS_HIP(hipMemcpyAsync(K_.hostscal, K_.scal, 8 * sizeof(double), hipMemcpyDeviceToHost, st_));
+}
+
+void Fgmres::start() {
+    // |b|^2 -> scal[5]
+    norm2_dev(K_, b_, K_.scal + 5, st_);
+    copy_scal();
+    phase_ = START;
+}
+
+void Fgmres::begin_cycle(const double *r) {
+    // g = beta e_1, V_0 = r / beta with beta = sqrt(scal[5])
+    LAUNCH(k::cycle_start, 1, 0, st_, K_.m, (const double *)(K_.scal + 5), K_.g, K_.scal);
+    LAUNCH(k::scale_div, grid_for(K_.N), 0, st_, r, (const double *)K_.scal, 4, K_.V, K_.N);
+    j_ = 0;
+    breakdown_ = false;
+    enqueue_iteration();
+}
+
+void Fgmres::enqueue_iteration() {
+    const int j = j_, m = K_.m, nv = j + 1;
+    const size_t N = K_.N;
+    double *Vj = K_.V + (size_t)j * N;
+    double *w = K_.V + (size_t)(j + 1) * N;
+    size_t esz = K_.z_fp32 ? sizeof(float) : sizeof(double);
+    void *zj = (char *)K_.Z + (size_t)j * N * esz;
+    M_(Vj, zj, st_);                                                    // z_j = M^{-1} v_j
+    if (K_.z_fp32) spmv_full<float>(S_, (const float *)zj, nullptr, w, st_);   // w = A z_j
+    else spmv_full<double>(S_, (const double *)zj, nullptr, w, st_);
+    // CGS2: h1 = V^T w (+ |w|^2), w -= V h1, h2 = V^T w, w -= V h2, h = h1 + h2, |w|^2
+    launch_mdot(K_, K_.V, nv, w, true, st_);
+    LAUNCH(k::reduce_rows, nv + 1, 0, st_, (const double *)K_.partial, K_.nblk, K_.h1, (const double *)nullptr,
+           (double *)nullptr);
+    LAUNCH((k::gemv_sub<false>), K_.nblk, 0, st_, (const double *)K_.V, N, nv, (const double *)K_.h1, w, N,
+           K_.chunk, K_.partial);
+    launch_mdot(K_, K_.V, nv, w, false, st_);
+    LAUNCH(k::reduce_rows, nv, 0, st_, (const double *)K_.partial, K_.nblk, K_.h2, (const double *)K_.h1, K_.hsum);
+    LAUNCH((k::gemv_sub<true>), K_.nblk, 0, st_, (const double *)K_.V, N, nv, (const double *)K_.h2, w, N,
+           K_.chunk, K_.partial);
+    LAUNCH(k::reduce_rows, 1, 0, st_, (const double *)K_.partial, K_.nblk, K_.nw2, (const double *)nullptr,
+           (double *)nullptr);
+    LAUNCH(k::givens, 1, 0, st_, j, m, (const double *)K_.hsum, (const double *)(K_.h1 + nv),
+           (const double *)K_.nw2, K_.H, K_.cs, K_.sn, K_.g, K_.scal);
+    copy_scal();
+    phase_ = ITER;
+}
+
+void Fgmres::end_cycle(int k) {
+    if (k > 0) {
+        LAUNCH(k::backsolve, 1, 0, st_, k, K_.m, (const double *)K_.H, (const double *)K_.g, K_.y);
+        if (K_.z_fp32)
+            LAUNCH((k::xupdate<float>), grid_for(K_.N), 0, st_, x_, (const float *)K_.Z, K_.N, k,
+                   (const double *)K_.y, K_.N);
+        else
+            LAUNCH((k::xupdate<double>), grid_for(K_.N), 0, st_, x_, (const double *)K_.Z, K_.N, k,
+                   (const double *)K_.y, K_.N);
+    }
+    spmv_full<double>(S_, x_, b_, K_.r, st_);                           // r = b - A x
+    norm2_dev(K_, K_.r, K_.scal + 5, st_);
+    copy_scal();
+    phase_ = CYCLE_END;
+}
+
+bool Fgmres::advance() {
+    const double *hs = K_.hostscal;
+    switch (phase_) {
+    case START: {
+        beta_b_ = std::sqrt(hs[5]);
+        if (!std::isfinite(beta_b_)) {
+            out.status = PS_EINVAL;
+            phase_ = DONE;
+            return false;
+        }
+        fill_zero(x_, K_.N, st_);
+        if (beta_b_ == 0.0) {
+            phase_ = DONE;
+            return false;
+        }
+        begin_cycle(b_);
+        return true;
+    }
+    case ITER: {
+        double est = hs[0], hn = hs[1], naz = hs[2];
+        bool brk = hs[3] != 0.0;
+        ++its_;
+        int k = j_ + 1;
+        if (!std::isfinite(est) || !std::isfinite(hn) || !std::isfinite(naz)) {
+            out.status = K_.z_fp32 ? PS_EPRECISION : PS_EBREAKDOWN;
+            out.iterations = its_;
+            phase_ = DONE;
+            return false;
+        }
+        if (brk) {
+            breakdown_ = true;
+            end_cycle(k - 1);
+            return true;
+        }
+        if (est <= rtol_ * beta_b_ || hn <= 1e-14 * naz || its_ >= maxit_ || k == K_.m) {
+            end_cycle(k);
+            return true;
+        }
+        double *w = K_.V + (size_t)k * K_.N;
+        LAUNCH(k::scale_div, grid_for(K_.N), 0, st_, (const double *)w, (const double *)K_.scal, 1, w, K_.N);
+        j_ = k;
+        enqueue_iteration();
+        return true;
+    }
+    case CYCLE_END: {
+        double rel = std::sqrt(hs[5]) / beta_b_;
+        out.iterations = its_;
+        out.restarts = cycles_;
+        out.rel_residual = rel;
+        if (rel <= rtol_) {
+            out.status = PS_OK;
+        } else if (breakdown_) {
+            out.status = PS_EBREAKDOWN;
+        } else if (its_ >= maxit_) {
+            out.status = PS_EMAXIT;
+        } else if (!std::isfinite(rel)) {
+            out.status = K_.z_fp32 ? PS_EPRECISION : PS_EBREAKDOWN;
+        } else {
+            ++cycles_;
+            begin_cycle(K_.r);
+            return true;
+        }
+        phase_ = DONE;
+        return false;
+    }
+    default:
+        return false;
+    }
+}
+
+SolveOut fgmres_blocking(Fgmres &run, hipStream_t st) {
+    run.start();
+    do {
+        PS_HIP(hipStreamSynchronize(st));
+    } while (run.advance());
+    PS_HIP(hipStreamSynchronize(st));
+    return run.out;
+}
+
+// ------------------------------------------------------------------ explicit instantiations
+template Sell<double> upload_sell<double>(Arena &, const HostSell &);
+template Sell<float> upload_sell<float>(Arena &, const HostSell &);
+template std::unique_ptr<DHierarchy<double>> upload_hierarchy<double>(const Hierarchy &, int, bool);
+template std::unique_ptr<DHierarchy<float>> upload_hierarchy<float>(const Hierarchy &, int, bool);
+template std::unique_ptr<DFlow<double>> upload_flow<double>(const FlowSetup &, const System &, const Options &);
+template std::unique_ptr<DFlow<float>> upload_flow<float>(const FlowSetup &, const System &, const Options &);
+template void alloc_prec_work<double>(PrecWork<double> &, const DHierarchy<double> &, const DFlow<double> &, int);
+template void alloc_prec_work<float>(PrecWork<float> &, const DHierarchy<float> &, const DFlow<float> &, int);
+template void apply_precond<double>(const DHierarchy<double> &, const DFlow<double> &, PrecWork<double> &, int,
+                                    const double *, double *, hipStream_t);
+template void apply_precond<float>(const DHierarchy<float> &, const DFlow<float> &, PrecWork<float> &, int,
+                                   const double *, float *, hipStream_t);
+template void spmv_full<double>(const DSystem &, const double *, const double *, double *, hipStream_t);
+template void spmv_full<float>(const DSystem &, const float *, const double *, double *, hipStream_t);
+
+}  // namespace ps

@@ -1,0 +1,636 @@
+// Setup phase of the two-stage preconditioner on the host (paper Sec. 5.4).
+//
+// Floating-point expressions here are evaluated in a fixed order with no fused
+// multiply-add contraction (built with -ffp-contract=off): every sum runs in
+// increasing column order from 0.0, so the hierarchy is reproducible bit for bit.
+#include "host_setup.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+namespace ps {
+
+Options options_from(const ps_options *o) {
+    Options r;
+    if (!o) return r;
+    r.precision = o->precision;
+    r.restart = o->restart;
+    r.maxit = o->maxit;
+    r.smoother = o->smoother;
+    r.ml_kind = o->ml_kind;
+    r.ml_sweeps = o->ml_sweeps;
+    r.coarse_max = o->coarse_max;
+    r.max_levels = o->max_levels;
+    r.fp32_fallback = o->fp32_fallback;
+    r.theta = o->theta;
+    if (r.precision != PS_FP64 && r.precision != PS_FP32_PREC) throw Error(PS_EINVAL, "precision");
+    if (r.restart < 1 || r.restart > 200) throw Error(PS_EINVAL, "restart must be in 1..200");
+    if (r.maxit < 1) throw Error(PS_EINVAL, "maxit must be positive");
+    if (r.smoother != PS_CHEB2 && r.smoother != PS_L1JAC) throw Error(PS_EINVAL, "smoother");
+    if (r.ml_kind != PS_BILU0 && r.ml_kind != PS_BJACOBI) throw Error(PS_EINVAL, "ml_kind");
+    if (r.ml_sweeps < 1 || r.ml_sweeps > 16) throw Error(PS_EINVAL, "ml_sweeps must be in 1..16");
+    if (r.coarse_max < 1 || r.coarse_max > 6000) throw Error(PS_EINVAL, "coarse_max must be in 1..6000");
+    if (r.max_levels < 1 || r.max_levels > 40) throw Error(PS_EINVAL, "max_levels must be in 1..40");
+    if (!(r.theta > 0.0 && r.theta <= 1.0)) throw Error(PS_EINVAL, "theta must be in (0, 1]");
+    return r;
+}
+
+// ---------------------------------------------------------------- validation
+static void copy_bsr(const ps_bsr &b, int nbr, int nbc, int br, int bc, bool need_diag,
+                     const char *name, Bsr &out) {
+    auto fail = [&](const std::string &m) { throw Error(PS_EINVAL, std::string(name) + ": " + m); };
+    if (b.nbrows != nbr || b.nbcols != nbc) fail("wrong block dimensions");
+    if (b.br != br || b.bc != bc) fail("wrong block size");
+    if (b.nblocks < 0) fail("negative nblocks");
+    if (!b.rowptr) fail("rowptr is NULL");
+    if (b.nblocks > 0 && (!b.colind || !b.vals)) fail("colind/vals is NULL");
+    out.nbr = nbr;
+    out.nbc = nbc;
+    out.br = br;
+    out.bc = bc;
+    out.rp.assign(b.rowptr, b.rowptr + nbr + 1);
+    if (out.rp[0] != 0 || out.rp[nbr] != b.nblocks) fail("rowptr must start at 0 and end at nblocks");
+    for (int i = 0; i < nbr; ++i)
+        if (out.rp[i + 1] < out.rp[i]) fail("rowptr not non-decreasing");
+    out.ci.assign(b.colind, b.colind + b.nblocks);
+    size_t nv = (size_t)b.nblocks * br * bc;
+    out.v.assign(b.vals, b.vals + nv);
+    for (int i = 0; i < nbr; ++i) {
+        bool has_diag = false;
+        for (int t = out.rp[i]; t < out.rp[i + 1]; ++t) {
+            int c = out.ci[t];
+            if (c < 0 || c >= nbc) fail("column index out of range");
+            if (t > out.rp[i] && c <= out.ci[t - 1]) fail("columns not sorted/unique");
+            if (c == i) has_diag = true;
+        }
+        if (need_diag && !has_diag) fail("missing diagonal block");
+    }
+    for (size_t k = 0; k < nv; ++k)
+        if (!std::isfinite(out.v[k])) fail("non-finite value");
+}
+
+void validate_and_copy(const ps_system *s, System &out) {
+    if (!s) throw Error(PS_EINVAL, "system is NULL");
+    if (s->nf != 2 && s->nf != 3) throw Error(PS_EINVAL, "nf must be 2 or 3");
+    if (s->p_index != s->nf - 1) throw Error(PS_EINVAL, "p_index must be nf-1");
+    if (s->n_nodes <= 0 || s->n_cells <= 0) throw Error(PS_EINVAL, "empty system");
+    if ((int64_t)3 * s->n_nodes + (int64_t)s->nf * s->n_cells > INT32_MAX / 2)
+        throw Error(PS_EINVAL, "system too large for 32-bit indices");
+    out.n_nodes = s->n_nodes;
+    out.n_cells = s->n_cells;
+    out.nf = s->nf;
+    out.mech_key = s->mech_key;
+    int nf = s->nf;
+    copy_bsr(s->Auu, s->n_nodes, s->n_nodes, 3, 3, true, "Auu", out.Auu);
+    copy_bsr(s->Auf, s->n_nodes, s->n_cells, 3, nf, false, "Auf", out.Auf);
+    copy_bsr(s->Afu, s->n_cells, s->n_nodes, nf, 3, false, "Afu", out.Afu);
+    copy_bsr(s->Aff, s->n_cells, s->n_cells, nf, nf, true, "Aff", out.Aff);
+    if (!s->d_sp || !s->d_pp) throw Error(PS_EINVAL, "d_sp/d_pp is NULL");
+    out.d_sp.assign(s->d_sp, s->d_sp + (size_t)s->n_cells * (nf - 1));
+    out.d_pp.assign(s->d_pp, s->d_pp + s->n_cells);
+    for (double v : out.d_sp)
+        if (!std::isfinite(v)) throw Error(PS_EINVAL, "d_sp: non-finite value");
+    for (double v : out.d_pp)
+        if (!std::isfinite(v)) throw Error(PS_EINVAL, "d_pp: non-finite value");
+}
+
+// ---------------------------------------------------------------- small dense
+bool invert_small(const double *a, double *inv, int n) {
+    double m[3][6];
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < 2 * n; ++j) m[i][j] = j < n ? a[i * n + j] : (j - n == i ? 1.0 : 0.0);
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::fabs(m[r][c]) > std::fabs(m[piv][c])) piv = r;
+        if (m[piv][c] == 0.0 || !std::isfinite(m[piv][c])) return false;
+        if (piv != c)
+            for (int j = 0; j < 2 * n; ++j) std::swap(m[c][j], m[piv][j]);
+        double d = m[c][c];
+        for (int j = 0; j < 2 * n; ++j) m[c][j] /= d;
+        for (int r = 0; r < n; ++r) {
+            if (r == c) continue;
+            double f = m[r][c];
+            if (f == 0.0) continue;
+            for (int j = 0; j < 2 * n; ++j) m[r][j] -= f * m[c][j];
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            inv[i * n + j] = m[i][n + j];
+            if (!std::isfinite(inv[i * n + j])) return false;
+        }
+    return true;
+}
+
+bool invert_dense(std::vector<double> a, std::vector<double> &inv, int n) {
+    // LU with partial pivoting (ties -> lowest row), then solve for the identity.
+    std::vector<int> piv(n);
+    for (int c = 0; c < n; ++c) {
+        int p = c;
+        double best = std::fabs(a[(size_t)c * n + c]);
+        for (int r = c + 1; r < n; ++r) {
+            double v = std::fabs(a[(size_t)r * n + c]);
+            if (v > best) { best = v; p = r; }
+        }
+        piv[c] = p;
+        if (best == 0.0 || !std::isfinite(best)) return false;
+        if (p != c)
+            for (int j = 0; j < n; ++j) std::swap(a[(size_t)c * n + j], a[(size_t)p * n + j]);
+        double d = a[(size_t)c * n + c];
+        for (int r = c + 1; r < n; ++r) {
+            double f = a[(size_t)r * n + c] / d;
+            a[(size_t)r * n + c] = f;
+            if (f == 0.0) continue;
+            for (int j = c + 1; j < n; ++j) a[(size_t)r * n + j] -= f * a[(size_t)c * n + j];
+        }
+    }
+    inv.assign((size_t)n * n, 0.0);
+    std::vector<double> col(n);
+    for (int k = 0; k < n; ++k) {
+        std::fill(col.begin(), col.end(), 0.0);
+        col[k] = 1.0;
+        for (int c = 0; c < n; ++c) std::swap(col[c], col[piv[c]]);   // apply P
+        for (int r = 1; r < n; ++r) {                                 // L y = P e_k
+            double s = col[r];
+            for (int c = 0; c < r; ++c) s -= a[(size_t)r * n + c] * col[c];
+            col[r] = s;
+        }
+        for (int r = n - 1; r >= 0; --r) {                            // U x = y
+            double s = col[r];
+            for (int c = r + 1; c < n; ++c) s -= a[(size_t)r * n + c] * col[c];
+            col[r] = s / a[(size_t)r * n + r];
+        }
+        for (int r = 0; r < n; ++r) inv[(size_t)r * n + k] = col[r];
+    }
+    for (double v : inv)
+        if (!std::isfinite(v)) return false;
+    return true;
+}
+
+// ---------------------------------------------------------------- operators
+static std::vector<int> diag_positions(const Bsr &b) {
+    std::vector<int> d(b.nbr, -1);
+    for (int i = 0; i < b.nbr; ++i)
+        for (int t = b.rp[i]; t < b.rp[i + 1]; ++t)
+            if (b.ci[t] == i) d[i] = t;
+    return d;
+}
+
+Bsr fixed_stress(const System &s) {
+    Bsr S = s.Aff;
+    int nf = s.nf, nn = nf * nf;
+    std::vector<int> dpos = diag_positions(S);
+    for (int i = 0; i < s.n_cells; ++i) {
+        double *blk = &S.v[(size_t)dpos[i] * nn];
+        for (int l = 0; l < nf - 1; ++l) blk[l * nf + nf - 1] += s.d_sp[(size_t)i * (nf - 1) + l];
+        blk[(nf - 1) * nf + nf - 1] += s.d_pp[i];
+    }
+    return S;
+}
+
+void quasi_impes(const System &s, const Bsr &Sff, Csr &Spp, std::vector<double> &dss_inv) {
+    int nf = s.nf, nn = nf * nf, m = nf - 1, nc = s.n_cells;
+    std::vector<int> dpos = diag_positions(s.Aff);
+    std::vector<double> t((size_t)nc * m);
+    dss_inv.assign((size_t)nc * m * m, 0.0);
+    for (int i = 0; i < nc; ++i) {
+        const double *blk = &s.Aff.v[(size_t)dpos[i] * nn];   // original A_ff: A_ss, A_ps unmodified
+        if (nf == 2) {
+            double dss = blk[0], dps = blk[nf * (nf - 1) + 0];
+            if (dss == 0.0) throw Error(PS_ESINGULAR, "zero D_ss entry");
+            t[i] = dps / dss;
+            dss_inv[i] = 1.0 / dss;
+        } else {
+            double a = blk[0 * nf + 0], b = blk[0 * nf + 1], c = blk[1 * nf + 0], d = blk[1 * nf + 1];
+            double det = a * d - b * c;
+            if (det == 0.0 || !std::isfinite(det)) throw Error(PS_ESINGULAR, "singular D_ss block");
+            double i00 = d / det, i01 = -b / det, i10 = -c / det, i11 = a / det;
+            double p0 = blk[(nf - 1) * nf + 0], p1 = blk[(nf - 1) * nf + 1];
+            t[(size_t)i * 2 + 0] = p0 * i00 + p1 * i10;
+            t[(size_t)i * 2 + 1] = p0 * i01 + p1 * i11;
+            double *o = &dss_inv[(size_t)i * 4];
+            o[0] = i00; o[1] = i01; o[2] = i10; o[3] = i11;
+        }
+    }
+    Spp.n = Spp.m = nc;
+    Spp.rp = Sff.rp;
+    Spp.ci = Sff.ci;
+    Spp.v.resize(Sff.ci.size());
+    for (int i = 0; i < nc; ++i)
+        for (int k = Sff.rp[i]; k < Sff.rp[i + 1]; ++k) {
+            const double *blk = &Sff.v[(size_t)k * nn];
+            double app = blk[(nf - 1) * nf + nf - 1];
+            if (nf == 2) {
+                Spp.v[k] = app - t[i] * blk[0 * nf + nf - 1];
+            } else {
+                double s0 = t[(size_t)i * 2 + 0] * blk[0 * nf + nf - 1];
+                double s1 = t[(size_t)i * 2 + 1] * blk[1 * nf + nf - 1];
+                Spp.v[k] = app - (s0 + s1);
+            }
+        }
+}
+
+Csr sdc_matrix(const System &s) {
+    int nn = s.n_nodes;
+    const Bsr &A = s.Auu;
+    Csr r;
+    r.n = r.m = 3 * nn;
+    r.rp.resize((size_t)3 * nn + 1);
+    r.ci.reserve((size_t)3 * A.nb());
+    r.v.reserve((size_t)3 * A.nb());
+    r.rp[0] = 0;
+    for (int c = 0; c < 3; ++c)
+        for (int i = 0; i < nn; ++i) {
+            for (int t = A.rp[i]; t < A.rp[i + 1]; ++t) {
+                r.ci.push_back(c * nn + A.ci[t]);
+                r.v.push_back(A.v[(size_t)t * 9 + c * 3 + c]);
+            }
+            r.rp[(size_t)c * nn + i + 1] = (int)r.ci.size();
+        }
+    return r;
+}
+
+// ---------------------------------------------------------------- AMG
+static inline double unit_hash(uint64_t i) {
+    // SplitMix64 (Steele, Lea, Flood 2014; Vigna's finaliser constants) seeded with i.
+    uint64_t z = i + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z = z ^ (z >> 31);
+    return (double)(z >> 11) * 0x1.0p-53;
+}
+
+static std::vector<char> strength(const Csr &A, double theta) {
+    std::vector<char> s(A.ci.size(), 0);
+    for (int i = 0; i < A.n; ++i) {
+        double m = -INFINITY;
+        for (int t = A.rp[i]; t < A.rp[i + 1]; ++t)
+            if (A.ci[t] != i) m = std::max(m, -A.v[t]);
+        if (!(m > 0.0)) continue;
+        double thr = theta * m;
+        for (int t = A.rp[i]; t < A.rp[i + 1]; ++t)
+            if (A.ci[t] != i && -A.v[t] >= thr) s[t] = 1;
+    }
+    return s;
+}
+
+static std::vector<int8_t> pmis(const Csr &A, const std::vector<char> &smask) {
+    const int n = A.n;
+    // S rows (i depends on j), S^T counts and lists
+    std::vector<int> srp(n + 1, 0), lam(n, 0);
+    for (int i = 0; i < n; ++i) {
+        int c = 0;
+        for (int t = A.rp[i]; t < A.rp[i + 1]; ++t)
+            if (smask[t]) { ++c; ++lam[A.ci[t]]; }
+        srp[i + 1] = srp[i] + c;
+    }
+    std::vector<int> sci(srp[n]);
+    for (int i = 0, k = 0; i < n; ++i)
+        for (int t = A.rp[i]; t < A.rp[i + 1]; ++t)
+            if (smask[t]) sci[k++] = A.ci[t];
+    std::vector<int> trp(n + 1, 0), tci(srp[n]);
+    for (int i = 0; i < n; ++i) trp[i + 1] = trp[i] + lam[i];
+    {
+        std::vector<int> fill(trp.begin(), trp.end() - 1);
+        for (int i = 0; i < n; ++i)
+            for (int k = srp[i]; k < srp[i + 1]; ++k) tci[fill[sci[k]]++] = i;
+    }
+    std::vector<double> w(n);
+    for (int i = 0; i < n; ++i) w[i] = (double)lam[i] + unit_hash((uint64_t)i);
+    std::vector<int8_t> st(n, 0);
+    size_t undecided = 0;
+    for (int i = 0; i < n; ++i) {
+        if (lam[i] == 0) st[i] = -1;
+        else ++undecided;
+    }
+    std::vector<char> newc(n, 0);
+    std::vector<int> und;
+    und.reserve(n);
+    for (int i = 0; i < n; ++i)
+        if (st[i] == 0) und.push_back(i);
+    auto beats = [&](int j, int i) { return w[j] > w[i] || (w[j] == w[i] && j > i); };
+    while (!und.empty()) {
+        for (int i : und) {
+            bool beaten = false;
+            for (int k = srp[i]; k < srp[i + 1] && !beaten; ++k) {
+                int j = sci[k];
+                if (st[j] == 0 && beats(j, i)) beaten = true;
+            }
+            for (int k = trp[i]; k < trp[i + 1] && !beaten; ++k) {
+                int j = tci[k];
+                if (st[j] == 0 && beats(j, i)) beaten = true;
+            }
+            newc[i] = !beaten;
+        }
+        for (int i : und)
+            if (newc[i]) st[i] = 1;
+        for (int i : und) {
+            if (st[i] != 0) continue;
+            for (int k = srp[i]; k < srp[i + 1]; ++k)
+                if (newc[sci[k]]) { st[i] = -1; break; }
+        }
+        for (int i : und) newc[i] = 0;
+        std::vector<int> next;
+        next.reserve(und.size());
+        for (int i : und)
+            if (st[i] == 0) next.push_back(i);
+        und.swap(next);
+    }
+    // C-promotion, sequential in increasing i
+    for (int i = 0; i < n; ++i) {
+        if (st[i] != -1 || srp[i + 1] == srp[i]) continue;
+        bool hasc = false;
+        for (int k = srp[i]; k < srp[i + 1]; ++k)
+            if (st[sci[k]] == 1) { hasc = true; break; }
+        if (!hasc) st[i] = 1;
+    }
+    return st;
+}
+
+static Csr direct_interpolation(const Csr &A, const std::vector<char> &smask,
+                                const std::vector<int8_t> &cf, int &nc) {
+    const int n = A.n;
+    std::vector<int> cidx(n, -1);
+    nc = 0;
+    for (int i = 0; i < n; ++i)
+        if (cf[i] == 1) cidx[i] = nc++;
+    Csr P;
+    P.n = n;
+    P.m = nc;
+    P.rp.assign(n + 1, 0);
+    for (int i = 0; i < n; ++i) {
+        if (cf[i] == 1) {
+            P.ci.push_back(cidx[i]);
+            P.v.push_back(1.0);
+        } else {
+            double diag = 0.0, pos = 0.0, negs = 0.0, den = 0.0;
+            for (int t = A.rp[i]; t < A.rp[i + 1]; ++t) {
+                int j = A.ci[t];
+                double a = A.v[t];
+                if (j == i) { diag = a; continue; }
+                if (a > 0.0) pos += a;
+                if (a < 0.0) negs += a;
+                if (smask[t] && cf[j] == 1) den += a;
+            }
+            double atil = diag + pos;
+            double alpha = den != 0.0 ? negs / den : 0.0;
+            for (int t = A.rp[i]; t < A.rp[i + 1]; ++t) {
+                int j = A.ci[t];
+                if (j != i && smask[t] && cf[j] == 1) {
+                    P.ci.push_back(cidx[j]);
+                    P.v.push_back(-(alpha * A.v[t]) / atil);
+                }
+            }
+        }
+        P.rp[i + 1] = (int)P.ci.size();
+    }
+    return P;
+}
+
+static Csr transpose(const Csr &P) {
+    Csr R;
+    R.n = P.m;
+    R.m = P.n;
+    R.rp.assign(R.n + 1, 0);
+    for (int c : P.ci) ++R.rp[c + 1];
+    for (int i = 0; i < R.n; ++i) R.rp[i + 1] += R.rp[i];
+    R.ci.resize(P.ci.size());
+    R.v.resize(P.ci.size());
+    std::vector<int> fill(R.rp.begin(), R.rp.end() - 1);
+    for (int i = 0; i < P.n; ++i)
+        for (int t = P.rp[i]; t < P.rp[i + 1]; ++t) {
+            int k = fill[P.ci[t]]++;
+            R.ci[k] = i;
+            R.v[k] = P.v[t];
+        }
+    return R;
+}
+
+// C = A B; each entry accumulated in increasing order of the inner index starting
+// from 0.0; exact zeros dropped; columns sorted.
+static Csr spgemm(const Csr &A, const Csr &B) {
+    Csr C;
+    C.n = A.n;
+    C.m = B.m;
+    C.rp.assign(A.n + 1, 0);
+    std::vector<double> acc(B.m, 0.0);
+    std::vector<int> mark(B.m, -1), cols;
+    for (int i = 0; i < A.n; ++i) {
+        cols.clear();
+        for (int t = A.rp[i]; t < A.rp[i + 1]; ++t) {
+            int l = A.ci[t];
+            double a = A.v[t];
+            for (int u = B.rp[l]; u < B.rp[l + 1]; ++u) {
+                int k = B.ci[u];
+                if (mark[k] != i) { mark[k] = i; acc[k] = 0.0; cols.push_back(k); }
+                acc[k] += a * B.v[u];
+            }
+        }
+        std::sort(cols.begin(), cols.end());
+        for (int k : cols)
+            if (acc[k] != 0.0) { C.ci.push_back(k); C.v.push_back(acc[k]); }
+        C.rp[i + 1] = (int)C.ci.size();
+    }
+    return C;
+}
+
+static double norm2(const std::vector<double> &v) {
+    double s = 0.0;
+    for (double x : v) s += x * x;
+    return std::sqrt(s);
+}
+
+static void smoother_setup(Level &L, int kind) {
+    const Csr &A = L.A;
+    const int n = A.n;
+    L.diag.assign(n, 0.0);
+    L.dl1.assign(n, 0.0);
+    std::vector<char> iso(n, 1);
+    for (int i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int t = A.rp[i]; t < A.rp[i + 1]; ++t) {
+            if (A.ci[t] == i) { L.diag[i] = A.v[t]; continue; }
+            s += std::fabs(A.v[t]);
+            if (A.v[t] != 0.0) iso[i] = 0;
+        }
+        L.dl1[i] = L.diag[i] + s;
+        if (L.diag[i] == 0.0) throw Error(PS_ESINGULAR, "zero diagonal in an AMG level");
+    }
+    if (kind == PS_L1JAC) return;
+    // power iteration for the largest eigenvalue of D^-1 A
+    std::vector<double> v(n), wv(n);
+    for (int i = 0; i < n; ++i) v[i] = 1.0 + unit_hash((uint64_t)i);
+    double nv = norm2(v);
+    for (int i = 0; i < n; ++i) v[i] = v[i] / nv;
+    double lam = 0.0;
+    for (int it = 0; it < 10; ++it) {
+        for (int i = 0; i < n; ++i) {
+            double s = 0.0;
+            for (int t = A.rp[i]; t < A.rp[i + 1]; ++t) s += A.v[t] * v[A.ci[t]];
+            wv[i] = s / L.diag[i];
+        }
+        lam = norm2(wv);
+        for (int i = 0; i < n; ++i) v[i] = wv[i] / lam;
+    }
+    lam = 1.1 * lam;
+    double lo = 0.3 * lam, hi = lam;
+    double theta = (hi + lo) / 2.0, delta = (hi - lo) / 2.0;
+    double sigma = theta / delta;
+    double rho0 = 1.0 / sigma;
+    double rho1 = 1.0 / (2.0 * sigma - rho0);
+    L.lam = lam;
+    L.c0.resize(n);
+    L.c1.resize(n);
+    L.cm.resize(n);
+    for (int i = 0; i < n; ++i) {
+        double d = L.diag[i];
+        if (iso[i]) {
+            L.c0[i] = 1.0 / d;
+            L.cm[i] = 0.0;
+            L.c1[i] = 0.0;
+        } else {
+            L.c0[i] = 1.0 / (theta * d);
+            L.cm[i] = rho1 * rho0;
+            L.c1[i] = 2.0 * rho1 / (delta * d);
+        }
+    }
+}
+
+Hierarchy amg_build(const Csr &A0, const Options &o) {
+    Hierarchy H;
+    Csr A = A0;
+    while (A.n > o.coarse_max && (int)H.lev.size() + 1 < o.max_levels) {
+        std::vector<char> smask = strength(A, o.theta);
+        std::vector<int8_t> cf = pmis(A, smask);
+        int nc = 0;
+        for (int8_t c : cf) nc += (c == 1);
+        if (nc == 0 || (double)nc > 0.9 * (double)A.n) break;
+        Level L;
+        L.P = direct_interpolation(A, smask, cf, nc);
+        L.R = transpose(L.P);
+        Csr Ac = spgemm(L.R, spgemm(A, L.P));
+        L.cf = std::move(cf);
+        L.A = std::move(A);
+        smoother_setup(L, o.smoother);
+        H.lev.push_back(std::move(L));
+        A = std::move(Ac);
+    }
+    if (A.n > 6000) throw Error(PS_ESINGULAR, "AMG coarsening stagnated above the dense-solve limit");
+    Level C;
+    C.cf.assign(A.n, 0);
+    std::vector<double> dense((size_t)A.n * A.n, 0.0);
+    for (int i = 0; i < A.n; ++i)
+        for (int t = A.rp[i]; t < A.rp[i + 1]; ++t) dense[(size_t)i * A.n + A.ci[t]] = A.v[t];
+    if (!invert_dense(dense, H.coarse_inv, A.n)) throw Error(PS_ESINGULAR, "singular coarsest AMG matrix");
+    H.coarse_n = A.n;
+    C.A = std::move(A);
+    H.lev.push_back(std::move(C));
+    return H;
+}
+
+// ---------------------------------------------------------------- local stage
+static inline void mm(const double *a, const double *b, double *c, int n) {
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < n; ++k) s += a[i * n + k] * b[k * n + j];
+            c[i * n + j] = s;
+        }
+}
+
+void bilu0_factor(const Bsr &S, Bsr &F) {
+    F = S;
+    const int n = S.nbr, nf = S.br, nn = nf * nf;
+    std::vector<int> dpos = diag_positions(S);
+    std::vector<int> pos(n, -1);
+    double tmp[9], prod[9];
+    for (int i = 0; i < n; ++i) {
+        for (int t = F.rp[i]; t < F.rp[i + 1]; ++t) pos[F.ci[t]] = t;
+        for (int t = F.rp[i]; t < F.rp[i + 1]; ++t) {
+            int k = F.ci[t];
+            if (k >= i) break;
+            double *lik = &F.v[(size_t)t * nn];
+            mm(lik, &F.v[(size_t)dpos[k] * nn], tmp, nf);       // L_ik = A_ik D_k^-1
+            std::memcpy(lik, tmp, sizeof(double) * nn);
+            for (int u = dpos[k] + 1; u < F.rp[k + 1]; ++u) {
+                int q = pos[F.ci[u]];
+                if (q < 0) continue;
+                mm(lik, &F.v[(size_t)u * nn], prod, nf);          // A_ij -= L_ik U_kj
+                double *aij = &F.v[(size_t)q * nn];
+                for (int e = 0; e < nn; ++e) aij[e] -= prod[e];
+            }
+        }
+        double *dblk = &F.v[(size_t)dpos[i] * nn];
+        if (!invert_small(dblk, tmp, nf)) throw Error(PS_ESINGULAR, "singular BILU(0) pivot block");
+        std::memcpy(dblk, tmp, sizeof(double) * nn);              // store D_i^-1
+        for (int t = F.rp[i]; t < F.rp[i + 1]; ++t) pos[F.ci[t]] = -1;
+    }
+}
+
+void block_jacobi_factor(const Bsr &S, Bsr &F) {
+    const int n = S.nbr, nf = S.br, nn = nf * nf;
+    std::vector<int> dpos = diag_positions(S);
+    F.nbr = F.nbc = n;
+    F.br = F.bc = nf;
+    F.rp.resize(n + 1);
+    F.ci.resize(n);
+    F.v.resize((size_t)n * nn);
+    for (int i = 0; i < n; ++i) {
+        F.rp[i] = i;
+        F.ci[i] = i;
+        if (!invert_small(&S.v[(size_t)dpos[i] * nn], &F.v[(size_t)i * nn], nf))
+            throw Error(PS_ESINGULAR, "singular diagonal cell block");
+    }
+    F.rp[n] = n;
+}
+
+BiluSchedule bilu_schedule(const Bsr &S) {
+    const int n = S.nbr;
+    std::vector<int> lf(n, 0), lb(n, 0);
+    int maxf = 0, maxb = 0;
+    for (int i = 0; i < n; ++i) {
+        int l = 0;
+        for (int t = S.rp[i]; t < S.rp[i + 1]; ++t)
+            if (S.ci[t] < i) l = std::max(l, lf[S.ci[t]] + 1);
+        lf[i] = l;
+        maxf = std::max(maxf, l);
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        int l = 0;
+        for (int t = S.rp[i]; t < S.rp[i + 1]; ++t)
+            if (S.ci[t] > i) l = std::max(l, lb[S.ci[t]] + 1);
+        lb[i] = l;
+        maxb = std::max(maxb, l);
+    }
+    BiluSchedule sc;
+    auto group = [n](const std::vector<int> &lv, int nl, std::vector<int> &ptr, std::vector<int> &rows) {
+        ptr.assign(nl + 2, 0);
+        for (int i = 0; i < n; ++i) ++ptr[lv[i] + 1];
+        for (int l = 0; l <= nl; ++l) ptr[l + 1] += ptr[l];
+        rows.resize(n);
+        std::vector<int> fill(ptr.begin(), ptr.end() - 1);
+        for (int i = 0; i < n; ++i) rows[fill[lv[i]]++] = i;
+        ptr.resize(nl + 2);
+    };
+    group(lf, maxf, sc.fwd_ptr, sc.fwd_rows);
+    group(lb, maxb, sc.bwd_ptr, sc.bwd_rows);
+    return sc;
+}
+
+void build_flow(const System &s, const Options &o, FlowSetup &f) {
+    f.Sff = fixed_stress(s);
+    quasi_impes(s, f.Sff, f.Spp, f.dss_inv);
+    f.pres = amg_build(f.Spp, o);
+    if (o.ml_kind == PS_BILU0) {
+        bilu0_factor(f.Sff, f.ml);
+        f.sched = bilu_schedule(f.Sff);
+    } else {
+        block_jacobi_factor(f.Sff, f.ml);
+        f.sched = BiluSchedule();
+    }
+}
+
+}  // namespace ps

@@ -1,0 +1,93 @@
+// Host-side data structures and the setup phase of the two-stage preconditioner.
+#pragma once
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/ps.h"
+
+namespace ps {
+
+// Error carrying a ps.h status code across C++ frames; caught at the C boundary.
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+struct Csr {                      // scalar CSR, sorted columns
+    int n = 0, m = 0;
+    std::vector<int> rp, ci;
+    std::vector<double> v;
+    int nnz() const { return (int)ci.size(); }
+};
+
+struct Bsr {                      // block CSR, row-major blocks, sorted columns
+    int nbr = 0, nbc = 0, br = 0, bc = 0;
+    std::vector<int> rp, ci;
+    std::vector<double> v;        // nblocks * br * bc
+    int nb() const { return (int)ci.size(); }
+};
+
+struct Level {                    // one AMG level
+    Csr A, P, R;                  // P, R empty on the coarsest level
+    std::vector<int8_t> cf;       // 1 = C, -1 = F
+    std::vector<double> diag, dl1;// diagonal, l1 row sums
+    std::vector<double> c0, c1, cm;  // Chebyshev per-row coefficients
+    double lam = 0.0;             // 1.1 x power-iteration estimate of rho(D^-1 A)
+};
+
+struct Hierarchy {
+    std::vector<Level> lev;       // coarsest last
+    std::vector<double> coarse_inv;  // dense inverse of the coarsest operator, row-major
+    int coarse_n = 0;
+};
+
+struct Options {
+    int precision = PS_FP64, restart = 100, maxit = 1000, smoother = PS_CHEB2;
+    int ml_kind = PS_BILU0, ml_sweeps = 1, coarse_max = 256, max_levels = 25;
+    int fp32_fallback = 0;
+    double theta = 0.25;
+};
+
+Options options_from(const ps_options *o);
+
+struct System {                   // validated host copy of a ps_system
+    int n_nodes = 0, n_cells = 0, nf = 0;
+    Bsr Auu, Auf, Afu, Aff;
+    std::vector<double> d_sp, d_pp;
+    uint64_t mech_key = 0;
+    size_t N() const { return (size_t)3 * n_nodes + (size_t)nf * n_cells; }
+};
+
+void validate_and_copy(const ps_system *s, System &out);   // throws Error(PS_EINVAL)
+
+struct BiluSchedule {             // level sets of the forward and backward sweeps
+    std::vector<int> fwd_ptr, fwd_rows, bwd_ptr, bwd_rows;
+};
+
+struct FlowSetup {                // recomputed at every ps_setup (Sec. 5.4)
+    Bsr Sff;                      // S_ff^(fs) values on the A_ff pattern
+    Csr Spp;                      // quasi-IMPES pressure operator on the cell pattern
+    std::vector<double> dss_inv;  // n_cells * (nf-1)^2
+    Hierarchy pres;
+    Bsr ml;                       // BILU(0) factors (diag blocks = D_i^{-1}) or block-Jacobi D^{-1}
+    BiluSchedule sched;
+};
+
+// --- setup steps ------------------------------------------------------------
+Bsr fixed_stress(const System &s);
+void quasi_impes(const System &s, const Bsr &Sff, Csr &Spp, std::vector<double> &dss_inv);
+Csr sdc_matrix(const System &s);                         // component-major
+Hierarchy amg_build(const Csr &A, const Options &o);
+void bilu0_factor(const Bsr &S, Bsr &F);                 // throws Error(PS_ESINGULAR)
+void block_jacobi_factor(const Bsr &S, Bsr &F);
+BiluSchedule bilu_schedule(const Bsr &S);
+void build_flow(const System &s, const Options &o, FlowSetup &f);
+
+// --- small dense helpers ----------------------------------------------------
+bool invert_small(const double *a, double *inv, int n);  // Gauss-Jordan, partial pivoting
+bool invert_dense(std::vector<double> a, std::vector<double> &inv, int n);
+
+}  // namespace ps

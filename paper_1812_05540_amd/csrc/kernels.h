@@ -1,0 +1,644 @@
+// HIP kernels for the solve phase (gfx950, wave64).
+//
+// All sparse operators use the 64-row sliced-ELLPACK layout of device.h: one
+// thread per (block) row, one wavefront per chunk, so each column-index and each
+// block-element load of a wavefront is one contiguous 256/512-byte segment.
+#pragma once
+
+#include "device.h"
+
+namespace ps {
+namespace k {
+
+constexpr int WG = 256;      // threads per workgroup (4 wavefronts)
+constexpr int MAXV = 256;    // max Krylov vectors handled by one launch (restart <= 200)
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Deterministic block sum (WG threads): fixed shuffle tree per wave, then the four
+// wave sums added in wave order by thread 0.  Result valid in thread 0 only.
+__device__ __forceinline__ double block_sum(double v, double *red) {
+    v = wave_sum(v);
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) r = ((red[0] + red[1]) + red[2]) + red[3];
+    __syncthreads();
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ void chunk_of(const Sell<T> &A, int pos, int &s0, int &w) {
+    int ch = pos >> 6;
+    s0 = A.cptr[ch];
+    w = A.cptr[ch + 1] - s0;
+}
+
+// ------------------------------------------------------------------ SpMV family
+// y = A x (MODE 0), y = b - A x (MODE 1), y += A x (MODE 2); R x C blocks.
+template <int R, int C, typename T, typename TX, typename TY, int MODE>
+__global__ __launch_bounds__(WG) void spmv(Sell<T> A, const TX *__restrict__ x,
+                                          const TY *__restrict__ b, TY *__restrict__ y) {
+    int pos = blockIdx.x * WG + threadIdx.x;
+    if (pos >= A.nrows) return;
+    int lane = pos & 63, s0, w;
+    chunk_of(A, pos, s0, w);
+    const int *col = A.col + (size_t)s0 * 64 + lane;
+    const T *val = A.val + (size_t)s0 * 64 * (R * C) + lane;
+    T acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = T(0);
+#pragma unroll 2
+    for (int k = 0; k < w; ++k) {
+        int c = col[(size_t)k * 64];
+        T xv[C];
+#pragma unroll
+        for (int e = 0; e < C; ++e) xv[e] = (T)x[(size_t)c * C + e];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int e = 0; e < C; ++e) acc[r] += val[((size_t)k * (R * C) + r * C + e) * 64] * xv[e];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        size_t o = (size_t)pos * R + r;
+        if (MODE == 0) y[o] = (TY)acc[r];
+        else if (MODE == 1) y[o] = (TY)((T)b[o] - acc[r]);
+        else y[o] = (TY)((T)y[o] + acc[r]);
+    }
+}
+
+// Two block matrices sharing the row space: y = A1 x1 + A2 x2, or b - (...).
+template <int R, int C1, int C2, typename TX, bool RESID>
+__global__ __launch_bounds__(WG) void spmv2(Sell<double> A1, const TX *__restrict__ x1,
+                                           Sell<double> A2, const TX *__restrict__ x2,
+                                           const double *__restrict__ b, double *__restrict__ y) {
+    int pos = blockIdx.x * WG + threadIdx.x;
+    if (pos >= A1.nrows) return;
+    int lane = pos & 63;
+    double acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = 0.0;
+    {
+        int s0, w;
+        chunk_of(A1, pos, s0, w);
+        const int *col = A1.col + (size_t)s0 * 64 + lane;
+        const double *val = A1.val + (size_t)s0 * 64 * (R * C1) + lane;
+#pragma unroll 2
+        for (int k = 0; k < w; ++k) {
+            int c = col[(size_t)k * 64];
+            double xv[C1];
+#pragma unroll
+            for (int e = 0; e < C1; ++e) xv[e] = (double)x1[(size_t)c * C1 + e];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int e = 0; e < C1; ++e) acc[r] += val[((size_t)k * (R * C1) + r * C1 + e) * 64] * xv[e];
+        }
+    }
+    {
+        int s0, w;
+        chunk_of(A2, pos, s0, w);
+        const int *col = A2.col + (size_t)s0 * 64 + lane;
+        const double *val = A2.val + (size_t)s0 * 64 * (R * C2) + lane;
+#pragma unroll 2
+        for (int k = 0; k < w; ++k) {
+            int c = col[(size_t)k * 64];
+            double xv[C2];
+#pragma unroll
+            for (int e = 0; e < C2; ++e) xv[e] = (double)x2[(size_t)c * C2 + e];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int e = 0; e < C2; ++e) acc[r] += val[((size_t)k * (R * C2) + r * C2 + e) * 64] * xv[e];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        size_t o = (size_t)pos * R + r;
+        y[o] = RESID ? b[o] - acc[r] : acc[r];
+    }
+}
+
+// ------------------------------------------------------------------ AMG level kernels
+template <typename T>
+__device__ __forceinline__ T row_dot(const Sell<T> &A, int pos, const T *__restrict__ x) {
+    int lane = pos & 63, s0, w;
+    chunk_of(A, pos, s0, w);
+    const int *col = A.col + (size_t)s0 * 64 + lane;
+    const T *val = A.val + (size_t)s0 * 64 + lane;
+    T acc = T(0);
+#pragma unroll 4
+    for (int k = 0; k < w; ++k) acc += val[(size_t)k * 64] * x[col[(size_t)k * 64]];
+    return acc;
+}
+
+template <typename T>
+__device__ __forceinline__ T row_dot2(const Sell<T> &A, int pos, const T *__restrict__ x,
+                                      const T *__restrict__ s) {
+    int lane = pos & 63, s0, w;
+    chunk_of(A, pos, s0, w);
+    const int *col = A.col + (size_t)s0 * 64 + lane;
+    const T *val = A.val + (size_t)s0 * 64 + lane;
+    T acc = T(0);
+#pragma unroll 4
+    for (int k = 0; k < w; ++k) {
+        int c = col[(size_t)k * 64];
+        acc += val[(size_t)k * 64] * (x[c] * s[c]);
+    }
+    return acc;
+}
+
+// l1-Jacobi pre-smoothing from x = 0 fused with the residual: x = D^-1 b, r = b - A x.
+template <typename T>
+__global__ __launch_bounds__(WG) void l1_pre(Sell<T> A, const T *__restrict__ b, const T *__restrict__ dinv,
+                                            T *__restrict__ x, T *__restrict__ r) {
+    int i = blockIdx.x * WG + threadIdx.x;
+    if (i >= A.nrows) return;
+    T acc = row_dot2(A, i, b, dinv);
+    T bi = b[i];
+    x[i] = bi * dinv[i];
+    r[i] = bi - acc;
+}
+
+// Chebyshev(2) pre-smoothing from x = 0: d0 = c0 b, r1 = b - A d0, x = d0 + (cm d0 + c1 r1).
+template <typename T>
+__global__ __launch_bounds__(WG) void cheb_pre(Sell<T> A, const T *__restrict__ b, const T *__restrict__ c0,
+                                              const T *__restrict__ c1, const T *__restrict__ cm,
+                                              T *__restrict__ x) {
+    int i = blockIdx.x * WG + threadIdx.x;
+    if (i >= A.nrows) return;
+    T acc = row_dot2(A, i, b, c0);
+    T d0 = c0[i] * b[i];
+    T r1 = b[i] - acc;
+    x[i] = d0 + (cm[i] * d0 + c1[i] * r1);
+}
+
+// Chebyshev(2) post-smoothing, step 1: r0 = b - A x, d0 = c0 r0, x1 = x + d0.
+template <typename T>
+__global__ __launch_bounds__(WG) void cheb_post1(Sell<T> A, const T *__restrict__ b, const T *__restrict__ x,
+                                                const T *__restrict__ c0, T *__restrict__ x1,
+                                                T *__restrict__ d0) {
+    int i = blockIdx.x * WG + threadIdx.x;
+    if (i >= A.nrows) return;
+    T r0 = b[i] - row_dot(A, i, x);
+    T d = c0[i] * r0;
+    d0[i] = d;
+    x1[i] = x[i] + d;
+}
+
+// Chebyshev(2) post-smoothing, step 2: r1 = b - A x1, out = x1 + (cm d0 + c1 r1).
+template <typename T>
+__global__ __launch_bounds__(WG) void cheb_post2(Sell<T> A, const T *__restrict__ b, const T *__restrict__ x1,
+                                                const T *__restrict__ d0, const T *__restrict__ c1,
+                                                const T *__restrict__ cm, T *__restrict__ out) {
+    int i = blockIdx.x * WG + threadIdx.x;
+    if (i >= A.nrows) return;
+    T r1 = b[i] - row_dot(A, i, x1);
+    out[i] = x1[i] + (cm[i] * d0[i] + c1[i] * r1);
+}
+
+// l1-Jacobi post-smoothing: out = x + D^-1 (b - A x).
+template <typename T>
+__global__ __launch_bounds__(WG) void l1_post(Sell<T> A, const T *__restrict__ b, const T *__restrict__ x,
+                                             const T *__restrict__ dinv, T *__restrict__ out) {
+    int i = blockIdx.x * WG + threadIdx.x;
+    if (i >= A.nrows) return;
+    T r = b[i] - row_dot(A, i, x);
+    out[i] = x[i] + r * dinv[i];
+}
+
+// Coarsest level: x = A_c^{-1} b with the FP64 dense inverse; one wavefront per row.
+template <typename T>
+__global__ __launch_bounds__(WG) void coarse_solve(const double *__restrict__ Ainv, int n,
+                                                  const T *__restrict__ b, T *__restrict__ x) {
+    int row = blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
+    int lane = threadIdx.x & 63;
+    if (row >= n) return;                      // whole wavefront leaves together
+    const double *a = Ainv + (size_t)row * n;
+    double s = 0.0;
+    for (int j = lane; j < n; j += 64) s += a[j] * (double)b[j];
+    s = wave_sum(s);
+    if (lane == 0) x[row] = (T)s;
+}
+
+// ------------------------------------------------------------------ Algorithm 1 kernels
+// Steps 2-3: y = v_f - A_fu z_u (per cell), z_s = D_ss^{-1} y_s.
+template <int NF, typename T>
+__global__ __launch_bounds__(WG) void step23(Sell<T> Afu, const double *__restrict__ vf,
+                                            const T *__restrict__ zu, const T *__restrict__ dss_inv,
+                                            T *__restrict__ y, T *__restrict__ zs) {
+    int i = blockIdx.x * WG + threadIdx.x;
+    if (i >= Afu.nrows) return;
+    int lane = i & 63, s0, w;
+    chunk_of(Afu, i, s0, w);
+    const int *col = Afu.col + (size_t)s0 * 64 + lane;
+    const T *val = Afu.val + (size_t)s0 * 64 * (NF * 3) + lane;
+    T acc[NF];
+#pragma unroll
+    for (int r = 0; r < NF; ++r) acc[r] = T(0);
+#pragma unroll 2
+    for (int k = 0; k < w; ++k) {
+        int c = col[(size_t)k * 64];
+        T xv[3] = {zu[(size_t)c * 3 + 0], zu[(size_t)c * 3 + 1], zu[(size_t)c * 3 + 2]};
+#pragma unroll
+        for (int r = 0; r < NF; ++r)
+#pragma unroll
+            for (int e = 0; e < 3; ++e) acc[r] += val[((size_t)k * (NF * 3) + r * 3 + e) * 64] * xv[e];
+    }
+    T yv[NF];
+#pragma unroll
+    for (int r = 0; r < NF; ++r) {
+        yv[r] = (T)vf[(size_t)i * NF + r] - acc[r];
+        y[(size_t)i * NF + r] = yv[r];
+    }
+    if (NF == 2) {
+        zs[i] = dss_inv[i] * yv[0];
+    } else {
+        const T *d = dss_inv + (size_t)i * 4;
+        zs[(size_t)i * 2 + 0] = d[0] * yv[0] + d[1] * yv[1];
+        zs[(size_t)i * 2 + 1] = d[2] * yv[0] + d[3] * yv[1];
+    }
+}
+
+// Step 4: w_p = y_p - A_ps z_s using the (p, s) entries of the S_ff blocks.
+template <int NF, typename T>
+__global__ __launch_bounds__(WG) void step4(Sell<T> S, const T *__restrict__ y, const T *__restrict__ zs,
+                                           T *__restrict__ wp) {
+    constexpr int M = NF - 1;
+    int i = blockIdx.x * WG + threadIdx.x;
+    if (i >= S.nrows) return;
+    int lane = i & 63, s0, w;
+    chunk_of(S, i, s0, w);
+    const int *col = S.col + (size_t)s0 * 64 + lane;
+    const T *val = S.val + (size_t)s0 * 64 * (NF * NF) + lane;
+    T acc = T(0);
+#pragma unroll 2
+    for (int k = 0; k < w; ++k) {
+        int c = col[(size_t)k * 64];
+#pragma unroll
+        for (int s = 0; s < M; ++s) acc += val[((size_t)k * (NF * NF) + (NF - 1) * NF + s) * 64] * zs[(size_t)c * M + s];
+    }
+    wp[i] = y[(size_t)i * NF + NF - 1] - acc;
+}
+
+// Step 6: w = y - S_ff [z_s; z_p].
+template <int NF, typename T>
+__global__ __launch_bounds__(WG) void step6(Sell<T> S, const T *__restrict__ y, const T *__restrict__ zs,
+                                           const T *__restrict__ zp, T *__restrict__ wout) {
+    constexpr int M = NF - 1;
+    int i = blockIdx.x * WG + threadIdx.x;
+    if (i >= S.nrows) return;
+    int lane = i & 63, s0, w;
+    chunk_of(S, i, s0, w);
+    const int *col = S.col + (size_t)s0 * 64 + lane;
+    const T *val = S.val + (size_t)s0 * 64 * (NF * NF) + lane;
+    T acc[NF];
+#pragma unroll
+    for (int r = 0; r < NF; ++r) acc[r] = T(0);
+#pragma unroll 2
+    for (int k = 0; k < w; ++k) {
+        int c = col[(size_t)k * 64];
+        T xv[NF];
+#pragma unroll
+        for (int s = 0; s < M; ++s) xv[s] = zs[(size_t)c * M + s];
+        xv[M] = zp[c];
+#pragma unroll
+        for (int r = 0; r < NF; ++r)
+#pragma unroll
+            for (int e = 0; e < NF; ++e) acc[r] += val[((size_t)k * (NF * NF) + r * NF + e) * 64] * xv[e];
+    }
+#pragma unroll
+    for (int r = 0; r < NF; ++r) wout[(size_t)i * NF + r] = y[(size_t)i * NF + r] - acc[r];
+}
+
+// BILU(0) forward sweep over one level: t_i = w_i - sum_{k<i} L_ik t_k.
+template <int NF, typename T>
+__global__ __launch_bounds__(WG) void bilu_fwd(Sell<T> L, int pos0, int pos1, const T *__restrict__ win,
+                                              T *__restrict__ t) {
+    int pos = pos0 + blockIdx.x * WG + threadIdx.x;
+    if (pos >= pos1) return;
+    int row = L.rowmap[pos];
+    if (row < 0) return;
+    int lane = pos & 63, s0, w;
+    chunk_of(L, pos, s0, w);
+    const int *col = L.col + (size_t)s0 * 64 + lane;
+    const T *val = L.val + (size_t)s0 * 64 * (NF * NF) + lane;
+    T acc[NF];
+#pragma unroll
+    for (int r = 0; r < NF; ++r) acc[r] = T(0);
+    for (int k = 0; k < w; ++k) {
+        int c = col[(size_t)k * 64];
+        T xv[NF];
+#pragma unroll
+        for (int e = 0; e < NF; ++e) xv[e] = t[(size_t)c * NF + e];
+#pragma unroll
+        for (int r = 0; r < NF; ++r)
+#pragma unroll
+            for (int e = 0; e < NF; ++e) acc[r] += val[((size_t)k * (NF * NF) + r * NF + e) * 64] * xv[e];
+    }
+#pragma unroll
+    for (int r = 0; r < NF; ++r) t[(size_t)row * NF + r] = win[(size_t)row * NF + r] - acc[r];
+}
+
+// BILU(0) backward sweep over one level, in place on t:
+//   delta_i = D_i^{-1} (t_i - sum_{j>i} U_ij delta_j);
+// ACC: dz_i += delta_i (else dz_i = delta_i); FINAL: zout_i = [z_s; z_p]_i + dz_i.
+template <int NF, typename T, bool ACC, bool FINAL>
+__global__ __launch_bounds__(WG) void bilu_bwd(Sell<T> U, int pos0, int pos1, T *__restrict__ t,
+                                              const T *__restrict__ dinv, T *__restrict__ dz,
+                                              const T *__restrict__ zs, const T *__restrict__ zp,
+                                              T *__restrict__ zout) {
+    constexpr int M = NF - 1;
+    int pos = pos0 + blockIdx.x * WG + threadIdx.x;
+    if (pos >= pos1) return;
+    int row = U.rowmap[pos];
+    if (row < 0) return;
+    int lane = pos & 63, s0, w;
+    chunk_of(U, pos, s0, w);
+    const int *col = U.col + (size_t)s0 * 64 + lane;
+    const T *val = U.val + (size_t)s0 * 64 * (NF * NF) + lane;
+    T acc[NF];
+#pragma unroll
+    for (int r = 0; r < NF; ++r) acc[r] = T(0);
+    for (int k = 0; k < w; ++k) {
+        int c = col[(size_t)k * 64];
+        T xv[NF];
+#pragma unroll
+        for (int e = 0; e < NF; ++e) xv[e] = t[(size_t)c * NF + e];
+#pragma unroll
+        for (int r = 0; r < NF; ++r)
+#pragma unroll
+            for (int e = 0; e < NF; ++e) acc[r] += val[((size_t)k * (NF * NF) + r * NF + e) * 64] * xv[e];
+    }
+    T rv[NF], dl[NF];
+#pragma unroll
+    for (int r = 0; r < NF; ++r) rv[r] = t[(size_t)row * NF + r] - acc[r];
+    const T *d = dinv + (size_t)row * NF * NF;
+#pragma unroll
+    for (int r = 0; r < NF; ++r) {
+        T s = T(0);
+#pragma unroll
+        for (int e = 0; e < NF; ++e) s += d[r * NF + e] * rv[e];
+        dl[r] = s;
+    }
+#pragma unroll
+    for (int r = 0; r < NF; ++r) {
+        size_t o = (size_t)row * NF + r;
+        t[o] = dl[r];
+        T v = ACC ? dz[o] + dl[r] : dl[r];
+        if (!FINAL) dz[o] = v;
+        if (FINAL) {
+            T zf = r < M ? zs[(size_t)row * M + r] : zp[row];
+            zout[o] = zf + v;
+        }
+    }
+}
+
+// Block-Jacobi sweep: delta = D^{-1}(w - S dz_in) (FIRST: D^{-1} w); dz_out = dz_in + delta;
+// FINAL: zout = [z_s; z_p] + dz_out.
+template <int NF, typename T, bool FIRST, bool FINAL>
+__global__ __launch_bounds__(WG) void bjacobi(Sell<T> S, const T *__restrict__ win, const T *__restrict__ dinv,
+                                             const T *__restrict__ dz_in, T *__restrict__ dz_out,
+                                             const T *__restrict__ zs, const T *__restrict__ zp,
+                                             T *__restrict__ zout) {
+    constexpr int M = NF - 1;
+    int i = blockIdx.x * WG + threadIdx.x;
+    if (i >= S.nrows) return;
+    T rv[NF];
+#pragma unroll
+    for (int r = 0; r < NF; ++r) rv[r] = win[(size_t)i * NF + r];
+    if (!FIRST) {
+        int lane = i & 63, s0, w;
+        chunk_of(S, i, s0, w);
+        const int *col = S.col + (size_t)s0 * 64 + lane;
+        const T *val = S.val + (size_t)s0 * 64 * (NF * NF) + lane;
+        for (int k = 0; k < w; ++k) {
+            int c = col[(size_t)k * 64];
+            T xv[NF];
+#pragma unroll
+            for (int e = 0; e < NF; ++e) xv[e] = dz_in[(size_t)c * NF + e];
+#pragma unroll
+            for (int r = 0; r < NF; ++r)
+#pragma unroll
+                for (int e = 0; e < NF; ++e) rv[r] -= val[((size_t)k * (NF * NF) + r * NF + e) * 64] * xv[e];
+        }
+    }
+    const T *d = dinv + (size_t)i * NF * NF;
+#pragma unroll
+    for (int r = 0; r < NF; ++r) {
+        T s = T(0);
+#pragma unroll
+        for (int e = 0; e < NF; ++e) s += d[r * NF + e] * rv[e];
+        size_t o = (size_t)i * NF + r;
+        T v = FIRST ? s : dz_in[o] + s;
+        if (FINAL) {
+            T zf = r < M ? zs[(size_t)i * M + r] : zp[i];
+            zout[o] = zf + v;
+        } else {
+            dz_out[o] = v;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ vector kernels
+template <typename TI, typename TO>
+__global__ __launch_bounds__(WG) void convert(const TI *__restrict__ in, TO *__restrict__ out, size_t n) {
+    size_t i = (size_t)blockIdx.x * WG + threadIdx.x;
+    if (i < n) out[i] = (TO)in[i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(WG) void fill(T *__restrict__ p, T v, size_t n) {
+    size_t i = (size_t)blockIdx.x * WG + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// y = x / s[idx]  (s on the device)
+__global__ __launch_bounds__(WG) void scale_div(const double *__restrict__ x, const double *__restrict__ s,
+                                               int idx, double *__restrict__ y, size_t n) {
+    size_t i = (size_t)blockIdx.x * WG + threadIdx.x;
+    if (i < n) y[i] = x[i] / s[idx];
+}
+
+__global__ __launch_bounds__(WG) void nonfinite_count(const float *__restrict__ p, size_t n,
+                                                     double *__restrict__ out) {
+    __shared__ double red[4];
+    double c = 0.0;
+    for (size_t i = (size_t)blockIdx.x * WG + threadIdx.x; i < n; i += (size_t)gridDim.x * WG)
+        if (!isfinite(p[i])) c += 1.0;
+    c = block_sum(c, red);
+    if (threadIdx.x == 0) out[blockIdx.x] = c;
+}
+
+// ------------------------------------------------------------------ FGMRES kernels
+// partial[k * nblk + blk] = sum over this block's chunk of V_k . w (k < nv), and
+// partial[nv * nblk + blk] = w . w when NORM.  The chunk of w is staged in LDS.
+template <bool NORM, bool LDSW>
+__global__ __launch_bounds__(WG) void mdot(const double *__restrict__ V, size_t ldv, int nv,
+                                          const double *__restrict__ w, size_t n, int chunk,
+                                          double *__restrict__ partial, int nblk) {
+    extern __shared__ double sw[];
+    __shared__ double red[4 * 4];
+    size_t i0 = (size_t)blockIdx.x * chunk;
+    int len = i0 < n ? (int)((n - i0) < (size_t)chunk ? (n - i0) : (size_t)chunk) : 0;
+    const double *wb = w + i0;
+    if (LDSW) {
+        for (int t = threadIdx.x; t < len; t += WG) sw[t] = wb[t];
+        __syncthreads();
+    }
+    const double *ws = LDSW ? sw : wb;
+    int ntot = nv + (NORM ? 1 : 0);
+    for (int k0 = 0; k0 < ntot; k0 += 4) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        const double *v0 = k0 + 0 < nv ? V + (size_t)(k0 + 0) * ldv + i0 : ws;
+        const double *v1 = k0 + 1 < nv ? V + (size_t)(k0 + 1) * ldv + i0 : ws;
+        const double *v2 = k0 + 2 < nv ? V + (size_t)(k0 + 2) * ldv + i0 : ws;
+        const double *v3 = k0 + 3 < nv ? V + (size_t)(k0 + 3) * ldv + i0 : ws;
+        int kk = ntot - k0;
+        for (int t = threadIdx.x; t < len; t += WG) {
+            double wt = ws[t];
+            a0 += v0[t] * wt;
+            if (kk > 1) a1 += v1[t] * wt;
+            if (kk > 2) a2 += v2[t] * wt;
+            if (kk > 3) a3 += v3[t] * wt;
+        }
+        a0 = wave_sum(a0);
+        a1 = wave_sum(a1);
+        a2 = wave_sum(a2);
+        a3 = wave_sum(a3);
+        int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+        if (lane == 0) {
+            red[wid * 4 + 0] = a0;
+            red[wid * 4 + 1] = a1;
+            red[wid * 4 + 2] = a2;
+            red[wid * 4 + 3] = a3;
+        }
+        __syncthreads();
+        if (threadIdx.x < 4 && threadIdx.x < kk) {
+            int q = threadIdx.x;
+            double s = ((red[0 * 4 + q] + red[1 * 4 + q]) + red[2 * 4 + q]) + red[3 * 4 + q];
+            partial[(size_t)(k0 + q) * nblk + blockIdx.x] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// out[k] = sum_b partial[k * nblk + b] (fixed order); if add: sum_out[k] = add[k] + out[k].
+__global__ __launch_bounds__(WG) void reduce_rows(const double *__restrict__ partial, int nblk,
+                                                 double *__restrict__ out, const double *__restrict__ add,
+                                                 double *__restrict__ sum_out) {
+    __shared__ double red[4];
+    int k = blockIdx.x;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += WG) s += partial[(size_t)k * nblk + b];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) {
+        out[k] = s;
+        if (add) sum_out[k] = add[k] + s;
+    }
+}
+
+// w -= sum_{k<nv} V_k h_k over this block's chunk; NORM: partial[blk] = |w_new|^2 (chunk).
+template <bool NORM>
+__global__ __launch_bounds__(WG) void gemv_sub(const double *__restrict__ V, size_t ldv, int nv,
+                                              const double *__restrict__ h, double *__restrict__ w,
+                                              size_t n, int chunk, double *__restrict__ partial) {
+    __shared__ double hs[MAXV];
+    __shared__ double red[4];
+    for (int t = threadIdx.x; t < nv; t += WG) hs[t] = h[t];
+    __syncthreads();
+    size_t i0 = (size_t)blockIdx.x * chunk;
+    int len = i0 < n ? (int)((n - i0) < (size_t)chunk ? (n - i0) : (size_t)chunk) : 0;
+    double acc = 0.0;
+    for (int t = threadIdx.x; t < len; t += WG) {
+        size_t i = i0 + t;
+        double s = 0.0;
+        for (int k = 0; k < nv; ++k) s += V[(size_t)k * ldv + i] * hs[k];
+        double wn = w[i] - s;
+        w[i] = wn;
+        acc += wn * wn;
+    }
+    if (NORM) {
+        acc = block_sum(acc, red);
+        if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+    }
+}
+
+// Givens update of Hessenberg column j (column-major, leading dimension m+1).
+// h: j+1 orthogonalisation coefficients; nrm[0] = |A z_j|^2, nrm[1] = |w|^2.
+// scal out: [0] |g_{j+1}|, [1] h_{j+1,j}, [2] |A z_j|, [3] breakdown flag.
+__global__ void givens(int j, int m, const double *__restrict__ h, const double *__restrict__ naz2,
+                       const double *__restrict__ nw2, double *__restrict__ H, double *__restrict__ cs,
+                       double *__restrict__ sn, double *__restrict__ g, double *__restrict__ scal) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double *col = H + (size_t)j * (m + 1);
+    double hn = sqrt(nw2[0]);
+    for (int i = 0; i <= j; ++i) col[i] = h[i];
+    col[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {
+        double t = cs[i] * col[i] + sn[i] * col[i + 1];
+        col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+        col[i] = t;
+    }
+    double rho = hypot(col[j], col[j + 1]);
+    scal[1] = hn;
+    scal[2] = sqrt(naz2[0]);
+    if (rho == 0.0) {
+        scal[0] = fabs(g[j]);
+        scal[3] = 1.0;
+        return;
+    }
+    cs[j] = col[j] / rho;
+    sn[j] = col[j + 1] / rho;
+    col[j] = rho;
+    col[j + 1] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    scal[0] = fabs(g[j + 1]);
+    scal[3] = 0.0;
+}
+
+// Start of a cycle: g = beta e_1 with beta = sqrt(nr2[0]).
+__global__ void cycle_start(int m, const double *__restrict__ nr2, double *__restrict__ g,
+                            double *__restrict__ scal) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double beta = sqrt(nr2[0]);
+    for (int i = 0; i <= m; ++i) g[i] = 0.0;
+    g[0] = beta;
+    scal[4] = beta;
+}
+
+// y = H_k^{-1} g_k (upper triangular back substitution).
+__global__ void backsolve(int k, int m, const double *__restrict__ H, const double *__restrict__ g,
+                          double *__restrict__ y) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int i = k - 1; i >= 0; --i) {
+        double s = g[i];
+        for (int c = i + 1; c < k; ++c) s -= H[(size_t)c * (m + 1) + i] * y[c];
+        y[i] = s / H[(size_t)i * (m + 1) + i];
+    }
+}
+
+// x += sum_{t<k} Z_t y_t.
+template <typename TZ>
+__global__ __launch_bounds__(WG) void xupdate(double *__restrict__ x, const TZ *__restrict__ Z, size_t ldz,
+                                             int k, const double *__restrict__ y, size_t n) {
+    __shared__ double ys[MAXV];
+    for (int t = threadIdx.x; t < k; t += WG) ys[t] = y[t];
+    __syncthreads();
+    size_t i = (size_t)blockIdx.x * WG + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int t = 0; t < k; ++t) s += (double)Z[(size_t)t * ldz + i] * ys[t];
+    x[i] += s;
+}
+
+}  // namespace k
+}  // namespace ps

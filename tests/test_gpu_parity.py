@@ -1,0 +1,248 @@
+"""GPU parity of the HIP path with the FP64 oracle (all calls go through the C ABI).
+
+Tolerances: FP64 kernels differ from the oracle only in summation order and fused
+multiply-adds, so single operators agree to ~1e-13 relative; a preconditioner
+application chains V-cycles and triangular sweeps (error amplified by their
+operator norms, measured ~1e2-1e3), bound 1e-10.  FP64 solves: iteration count
+equal to the oracle's +-1 and the solution within 1e-9 of the oracle's iterate at
+the same iteration.  FP32 preconditioner: true FP64 residual <= rtol and solution
+error vs a tightly converged oracle solution <= 1e-6 or, when the problem's
+conditioning makes the FP64 path itself miss that, no worse than 10x the FP64
+path's own error.
+"""
+import numpy as np
+import pytest
+
+from synth import workload
+from oracle import Options, solve as oracle_solve
+from oracle import precond as P
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1812_05540_amd import ps  # noqa: E402
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    ps.load()                      # fails loudly if the library is missing
+    c = ps.ps_ctx_create(0, 0)
+    yield c
+    ps.ps_ctx_destroy(c)
+
+
+SMALL = {
+    "iid8": dict(grid=(8, 8, 8), kind="iid", seed=1, rhs_seed=101),
+    "grf12": dict(grid=(12, 11, 10), kind="grf", seed=2, rhs_seed=102),
+    "iid3ph": dict(grid=(7, 6, 5), kind="iid3", seed=3, rhs_seed=103),
+}
+_cache = {}
+
+
+def small(name):
+    if name not in _cache:
+        _cache[name] = workload(**SMALL[name])
+    return _cache[name]
+
+
+def make_solver(ctx, s, **opts):
+    sv = ps.Solver(ctx, s, **opts)
+    sv.setup()
+    return sv
+
+
+def oracle_opts(**opts):
+    return Options(smoother={ps.PS_CHEB2: "cheb2", ps.PS_L1JAC: "l1jac"}[opts.get("smoother", ps.PS_CHEB2)],
+                   ml_kind={ps.PS_BILU0: "bilu0", ps.PS_BJACOBI: "bjacobi"}[opts.get("ml_kind", ps.PS_BILU0)],
+                   ml_sweeps=opts.get("ml_sweeps", 1), restart=opts.get("restart", 100),
+                   maxit=opts.get("maxit", 1000))
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_spmv_matches_oracle(ctx, name):
+    s, _ = small(name)
+    A = P.system_matrices(s)["A"]
+    x = np.random.default_rng(0).standard_normal(s.N)
+    sv = make_solver(ctx, s)
+    y = dev(np.zeros(s.N))
+    sv.spmv(dev(x), y)
+    ref = A @ x
+    assert np.abs(host(y) - ref).max() <= 1e-13 * np.abs(ref).max()
+    sv.close()
+
+
+PRECOND_CASES = [
+    ("iid8", dict()),
+    ("grf12", dict()),
+    ("grf12", dict(smoother=ps.PS_L1JAC)),
+    ("grf12", dict(ml_sweeps=3)),
+    ("grf12", dict(ml_kind=ps.PS_BJACOBI, ml_sweeps=3)),
+    ("iid3ph", dict()),
+    ("iid3ph", dict(ml_kind=ps.PS_BJACOBI, ml_sweeps=2, smoother=ps.PS_L1JAC)),
+]
+
+
+@pytest.mark.parametrize("name,opts", PRECOND_CASES)
+def test_precond_fp64_matches_oracle(ctx, name, opts):
+    s, _ = small(name)
+    st = P.setup(s, oracle_opts(**opts))
+    sv = make_solver(ctx, s, **opts)
+    rng = np.random.default_rng(1)
+    for _ in range(2):
+        v = rng.standard_normal(s.N)
+        z = dev(np.zeros(s.N))
+        sv.apply_precond(dev(v), z)
+        ref = P.apply_precond(st, v)
+        err = np.linalg.norm(host(z) - ref) / np.linalg.norm(ref)
+        assert err <= 1e-10, err
+    sv.close()
+
+
+@pytest.mark.parametrize("name", ["iid8", "grf12"])
+def test_precond_fp32_close_to_fp64(ctx, name):
+    s, _ = small(name)
+    sv = make_solver(ctx, s, precision=ps.PS_FP32_PREC)
+    st = P.setup(s, Options())
+    v = np.random.default_rng(2).standard_normal(s.N)
+    z = dev(np.zeros(s.N))
+    sv.apply_precond(dev(v), z)
+    ref = P.apply_precond(st, v)
+    err = np.linalg.norm(host(z) - ref) / np.linalg.norm(ref)
+    assert err <= 1e-3, err          # FP32 rounding amplified through the V-cycles and sweeps
+    sv.close()
+
+
+@pytest.mark.parametrize("name,opts", [("iid8", dict()), ("grf12", dict(ml_sweeps=2)),
+                                       ("iid3ph", dict(smoother=ps.PS_L1JAC))])
+def test_fp64_solve_matches_oracle(ctx, name, opts):
+    s, b = small(name)
+    out = oracle_solve(s, b, rtol=1e-8, opts=oracle_opts(**opts), record_iterates=True)
+    sv = make_solver(ctx, s, **opts)
+    x = dev(np.zeros(s.N))
+    r = sv.solve(dev(b), x, 1e-8)
+    assert r["status"] == ps.PS_OK and r["rel_residual"] <= 1e-8
+    assert abs(r["iterations"] - out["iterations"]) <= 1
+    k = min(r["iterations"], len(out["iterates"]))
+    xo = out["iterates"][k - 1]
+    err = np.linalg.norm(host(x) - xo) / np.linalg.norm(xo)
+    assert err <= 1e-9, err
+    sv.close()
+
+
+@pytest.mark.parametrize("name", ["iid8", "grf12", "iid3ph"])
+def test_fp32_solve_reaches_fp64_accuracy(ctx, name):
+    s, b = small(name)
+    tight = oracle_solve(s, b, rtol=1e-12)["x"]
+    A = P.system_matrices(s)["A"]
+    res = {}
+    for prec in (ps.PS_FP64, ps.PS_FP32_PREC):
+        sv = make_solver(ctx, s, precision=prec)
+        x = dev(np.zeros(s.N))
+        r = sv.solve(dev(b), x, 1e-8)
+        xh = host(x)
+        assert r["status"] == ps.PS_OK
+        true_res = np.linalg.norm(b - A @ xh) / np.linalg.norm(b)
+        assert true_res <= 1.01e-8 and abs(true_res - r["rel_residual"]) <= 1e-3 * true_res + 1e-15
+        res[prec] = np.linalg.norm(xh - tight) / np.linalg.norm(tight)
+        sv.close()
+    assert res[ps.PS_FP32_PREC] <= max(1e-6, 10 * res[ps.PS_FP64])
+
+
+def test_solves_are_deterministic(ctx):
+    s, b = small("grf12")
+    sv = make_solver(ctx, s)
+    xs = []
+    for _ in range(2):
+        x = dev(np.zeros(s.N))
+        r = sv.solve(dev(b), x, 1e-8)
+        xs.append(host(x))
+    assert np.array_equal(xs[0], xs[1])
+    sv.close()
+
+
+def test_edge_cases(ctx):
+    s, b = small("iid8")
+    sv = ps.Solver(ctx, s)
+    x = dev(np.zeros(s.N))
+    r = sv.solve(dev(b), x, 1e-8)
+    assert r["status"] == ps.PS_ENOTSETUP
+    sv.setup()
+    # zero right-hand side: x = 0 after zero iterations
+    x = dev(np.ones(s.N))
+    r = sv.solve(dev(np.zeros(s.N)), x, 1e-8)
+    assert r["status"] == ps.PS_OK and r["iterations"] == 0 and not host(x).any()
+    # invalid tolerance
+    r = sv.solve(dev(b), x, 0.0)
+    assert r["status"] == ps.PS_EINVAL
+    # non-finite right-hand side
+    bn = b.copy()
+    bn[5] = np.nan
+    r = sv.solve(dev(bn), x, 1e-8)
+    assert r["status"] == ps.PS_EINVAL
+    sv.close()
+    # iteration cap: status EMAXIT with the last iterate, which has reduced the residual
+    sv = make_solver(ctx, s, maxit=3)
+    x = dev(np.zeros(s.N))
+    r = sv.solve(dev(b), x, 1e-12)
+    assert r["status"] == ps.PS_EMAXIT and r["iterations"] == 3 and r["rel_residual"] < 1.0
+    sv.close()
+
+
+def test_restarted_solve_matches_oracle(ctx):
+    s, b = small("iid8")
+    out = oracle_solve(s, b, rtol=1e-8, opts=Options(restart=7))
+    sv = make_solver(ctx, s, restart=7)
+    x = dev(np.zeros(s.N))
+    r = sv.solve(dev(b), x, 1e-8)
+    assert r["status"] == ps.PS_OK
+    assert abs(r["iterations"] - out["iterations"]) <= 1 and r["restarts"] >= 3
+    assert np.linalg.norm(host(x) - out["x"]) <= 1e-7 * np.linalg.norm(out["x"])
+    sv.close()
+
+
+def test_mech_key_shares_hierarchy_without_changing_results(ctx):
+    s, b = small("grf12")
+    ref_sv = make_solver(ctx, s)
+    x0 = dev(np.zeros(s.N))
+    ref_sv.solve(dev(b), x0, 1e-8)
+    a = make_solver(ctx, s, mech_key=77)
+    bsv = ps.Solver(ctx, s, mech_key=77)
+    bsv.setup()
+    fa, fb = a.footprint(), bsv.footprint()
+    for sv in (a, bsv):
+        x = dev(np.zeros(s.N))
+        sv.solve(dev(b), x, 1e-8)
+        assert np.array_equal(host(x), host(x0))
+    assert fa > 0 and fb > 0
+    for sv in (ref_sv, a, bsv):
+        sv.close()
+
+
+def test_update_flow_matches_fresh_handle(ctx):
+    s, b = small("grf12")
+    s2, _ = workload(grid=(12, 11, 10), kind="grf", seed=8, rhs_seed=102)
+    sv = make_solver(ctx, s)
+    ps.ps_update_flow(sv.h, s2.Afu.vals, s2.Aff.vals, s2.d_sp, s2.d_pp)
+    sv.setup()
+    # the fresh system with the original displacement block and the new flow blocks
+    s3, _ = workload(grid=(12, 11, 10), kind="grf", seed=2, rhs_seed=102)
+    s3.Afu, s3.Aff, s3.d_sp, s3.d_pp = s2.Afu, s2.Aff, s2.d_sp, s2.d_pp
+    s3.Auf = s.Auf
+    ref = make_solver(ctx, s3)
+    xa, xb = dev(np.zeros(s.N)), dev(np.zeros(s.N))
+    ra = sv.solve(dev(b), xa, 1e-8)
+    rb = ref.solve(dev(b), xb, 1e-8)
+    assert ra["iterations"] == rb["iterations"]
+    assert np.array_equal(host(xa), host(xb))
+    sv.close()
+    ref.close()
