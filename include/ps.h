@@ -57,6 +57,7 @@ extern "C" {
 #define PS_L1JAC      1    /* AMG smoother: l1-Jacobi */
 #define PS_BILU0      0    /* local stage M_L: block ILU(0) on S_ff^(fs) */
 #define PS_BJACOBI    1    /* local stage M_L: block Jacobi on S_ff^(fs) */
+#define PS_MCGS       2    /* local stage M_L: hybrid block Gauss-Seidel in multicolour order */
 
 /* Block CSR matrix (host arrays).  Row-major br x bc blocks; rowptr has nbrows+1
  * entries starting at 0; colind sorted and unique within each block row. */
@@ -93,7 +94,7 @@ typedef struct {
     int32_t restart;      /* FGMRES restart length m, 1..200              (100)       */
     int32_t maxit;        /* total iteration cap                          (1000)      */
     int32_t smoother;     /* PS_CHEB2 | PS_L1JAC                          (PS_CHEB2)  */
-    int32_t ml_kind;      /* PS_BILU0 | PS_BJACOBI                        (PS_BILU0)  */
+    int32_t ml_kind;      /* PS_BILU0 | PS_BJACOBI | PS_MCGS              (PS_BILU0)  */
     int32_t ml_sweeps;    /* sweeps of the local stage, 1..16             (1)         */
     int32_t coarse_max;   /* AMG: stop coarsening at n <= coarse_max      (256)       */
     int32_t max_levels;   /* AMG: at most this many levels                (25)        */

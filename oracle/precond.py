@@ -41,7 +41,7 @@ class Options:
     coarse_max: int = 256
     max_levels: int = 25
     smoother: str = "cheb2"        # "cheb2" | "l1jac"
-    ml_kind: str = "bilu0"         # "bilu0" | "bjacobi"
+    ml_kind: str = "bilu0"         # "bilu0" | "bjacobi" | "mcgs"
     ml_sweeps: int = 1             # sweeps of the local stage (BILU(0) or block Jacobi)
 
 
@@ -180,6 +180,9 @@ def setup(system, opts=None, mechanics=None):
         ml = ("bilu0",) + local.bilu0_factor(system.Aff.rowptr, system.Aff.colind, sff_vals)
     elif opts.ml_kind == "bjacobi":
         ml = ("bjacobi", local.block_diag_inv(system.Aff.rowptr, system.Aff.colind, sff_vals))
+    elif opts.ml_kind == "mcgs":
+        ml = ("mcgs", local.block_diag_inv(system.Aff.rowptr, system.Aff.colind, sff_vals),
+              local.greedy_colors(system.Aff.rowptr, system.Aff.colind))
     else:
         raise ValueError(opts.ml_kind)
     return Setup(system, opts, mats, sff_vals, Sff, Spp, dss_inv, Aps, sdc, pres, ml)
@@ -226,6 +229,11 @@ def apply_precond(st, v):
         def ML(w):
             return local.bilu0_sweeps(s.Aff.rowptr, s.Aff.colind, F, Dinv, diag, st.Sff,
                                       w.reshape(-1, nf), o.ml_sweeps).ravel()
+    elif st.ml[0] == "mcgs":
+        Dinv, colors = st.ml[1], st.ml[2]
+
+        def ML(w):
+            return local.mcgs_apply(st.Sff, Dinv, colors, w.reshape(-1, nf), o.ml_sweeps).ravel()
     else:
         Dinv = st.ml[1]
 

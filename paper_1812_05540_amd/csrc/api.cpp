@@ -1,6 +1,8 @@
 // C ABI of the solver (include/ps.h, include/ps_host.h) and the serving scheduler.
 #include <atomic>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -42,6 +44,24 @@ double now_s() {
     using namespace std::chrono;
     return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
+
+// PS_TRACE=1 in the environment prints setup phase timings to stderr.
+bool tracing() {
+    static const bool on = [] {
+        const char *e = std::getenv("PS_TRACE");
+        return e && *e && *e != '0';
+    }();
+    return on;
+}
+
+struct PhaseTimer {
+    const char *what;
+    double t0;
+    explicit PhaseTimer(const char *w) : what(w), t0(now_s()) {}
+    ~PhaseTimer() {
+        if (tracing()) std::fprintf(stderr, "[ps] %-28s %8.2f ms\n", what, 1e3 * (now_s() - t0));
+    }
+};
 
 // Mechanics (separate displacement component) hierarchy, built once and shared by
 // handles with the same mech_key (Sec. 5.2: the elasticity AMG is set up once).
@@ -291,8 +311,15 @@ int ps_setup(ps_handle *h) {
         h->ready = false;
         bool f32 = use_fp32(h);
         bool f64 = !f32 || h->opt.fp32_fallback;
-        ensure_mech_device(h, f64, f32);
-        build_flow(h->sys, h->opt, h->flow);
+        {
+            PhaseTimer pt("mechanics (if not built)");
+            ensure_mech_device(h, f64, f32);
+        }
+        {
+            PhaseTimer pt("flow setup (host)");
+            build_flow(h->sys, h->opt, h->flow);
+        }
+        PhaseTimer pt("flow upload + work");
         h->fl64.reset();
         h->fl32.reset();
         if (f64) {

@@ -215,6 +215,16 @@ std::unique_ptr<DFlow<T>> upload_flow(const FlowSetup &f, const System &s, const
         for (int i = 0; i < nc; ++i)
             for (int t = f.ml.rp[i]; t < f.ml.rp[i + 1]; ++t)
                 if (f.ml.ci[t] == i) std::memcpy(&dinv[(size_t)i * nn], &f.ml.v[(size_t)t * nn], sizeof(double) * nn);
+    } else if (o.ml_kind == PS_MCGS) {
+        std::vector<int> ord;
+        d->lchunk_f.assign(1, 0);
+        for (size_t c = 0; c + 1 < f.sched.fwd_ptr.size(); ++c) {
+            for (int p = f.sched.fwd_ptr[c]; p < f.sched.fwd_ptr[c + 1]; ++p) ord.push_back(f.sched.fwd_rows[p]);
+            while (ord.size() % 64) ord.push_back(-1);
+            d->lchunk_f.push_back((int)(ord.size() / 64));
+        }
+        d->Lf = upload_sell<T>(d->arena, sell_from_bsr(f.Sff.rp, f.Sff.ci, f.Sff.v, nc, nf, nf, &ord));
+        dinv = f.ml.v;
     } else {
         dinv = f.ml.v;
     }
@@ -321,6 +331,22 @@ static void local_stage(const DFlow<T> &fl, PrecWork<T> &w, T *zf, hipStream_t s
                 LAUNCH((k::bjacobi<NF, T, false, true>), g, 0, st, fl.Sff, w.w, fl.dinv, din, dout, w.zs, w.zp, zf);
             else
                 LAUNCH((k::bjacobi<NF, T, false, false>), g, 0, st, fl.Sff, w.w, fl.dinv, din, dout, w.zs, w.zp, zf);
+        }
+        return;
+    }
+    if (fl.ml_kind == PS_MCGS) {
+        LAUNCH((k::fill<T>), grid_for((size_t)fl.nc * NF), 0, st, w.dz, T(0), (size_t)fl.nc * NF);
+        for (int s = 0; s < sweeps; ++s) {
+            bool final = s == sweeps - 1;
+            for (size_t c = 0; c + 1 < fl.lchunk_f.size(); ++c) {
+                int p0 = fl.lchunk_f[c] * 64, p1 = fl.lchunk_f[c + 1] * 64;
+                if (final)
+                    LAUNCH((k::mcgs<NF, T, true>), grid_for(p1 - p0), 0, st, fl.Lf, p0, p1, (const T *)w.w,
+                           fl.dinv, w.dz, w.zs, w.zp, zf);
+                else
+                    LAUNCH((k::mcgs<NF, T, false>), grid_for(p1 - p0), 0, st, fl.Lf, p0, p1, (const T *)w.w,
+                           fl.dinv, w.dz, w.zs, w.zp, zf);
+            }
         }
         return;
     }

@@ -6,11 +6,84 @@
 #include "host_setup.h"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
+#include <thread>
 
 namespace ps {
+
+namespace {
+bool trace_on() {
+    static const bool on = [] {
+        const char *e = std::getenv("PS_TRACE");
+        return e && *e && *e != '0';
+    }();
+    return on;
+}
+struct Tick {
+    const char *what;
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+    explicit Tick(const char *w) : what(w) {}
+    ~Tick() {
+        if (!trace_on()) return;
+        double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        std::fprintf(stderr, "[ps]   %-26s %8.2f ms\n", what, ms);
+    }
+};
+// Row-range parallelism for the setup: each row's arithmetic is independent of the
+// split, so results do not depend on the thread count.
+int setup_threads() {
+    static const int n = [] {
+        const char *e = std::getenv("PS_THREADS");
+        int v = e ? std::atoi(e) : (int)std::thread::hardware_concurrency();
+        return std::max(1, std::min(v, 16));
+    }();
+    return n;
+}
+
+template <class F>
+void parallel_rows(int n, F &&f) {           // f(begin, end, part)
+    int parts = std::min(setup_threads(), std::max(1, n / 8192));
+    if (parts <= 1) {
+        f(0, n, 0);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (int p = 0; p < parts; ++p) {
+        int b = (int)((long long)n * p / parts), e = (int)((long long)n * (p + 1) / parts);
+        th.emplace_back([&f, b, e, p] { f(b, e, p); });
+    }
+    for (auto &t : th) t.join();
+}
+
+// Concatenate per-part CSR pieces (row ranges in order) into one matrix.
+struct CsrPart {
+    std::vector<int> len, ci;
+    std::vector<double> v;
+};
+void concat_parts(std::vector<CsrPart> &parts, Csr &C) {
+    size_t nnz = 0;
+    for (auto &p : parts) nnz += p.ci.size();
+    C.ci.resize(nnz);
+    C.v.resize(nnz);
+    size_t off = 0;
+    int row = 0;
+    C.rp[0] = 0;
+    for (auto &p : parts) {
+        std::copy(p.ci.begin(), p.ci.end(), C.ci.begin() + off);
+        std::copy(p.v.begin(), p.v.end(), C.v.begin() + off);
+        off += p.ci.size();
+        for (int l : p.len) {
+            C.rp[row + 1] = C.rp[row] + l;
+            ++row;
+        }
+    }
+}
+}  // namespace
 
 Options options_from(const ps_options *o) {
     Options r;
@@ -29,7 +102,8 @@ Options options_from(const ps_options *o) {
     if (r.restart < 1 || r.restart > 200) throw Error(PS_EINVAL, "restart must be in 1..200");
     if (r.maxit < 1) throw Error(PS_EINVAL, "maxit must be positive");
     if (r.smoother != PS_CHEB2 && r.smoother != PS_L1JAC) throw Error(PS_EINVAL, "smoother");
-    if (r.ml_kind != PS_BILU0 && r.ml_kind != PS_BJACOBI) throw Error(PS_EINVAL, "ml_kind");
+    if (r.ml_kind != PS_BILU0 && r.ml_kind != PS_BJACOBI && r.ml_kind != PS_MCGS)
+        throw Error(PS_EINVAL, "ml_kind");
     if (r.ml_sweeps < 1 || r.ml_sweeps > 16) throw Error(PS_EINVAL, "ml_sweeps must be in 1..16");
     if (r.coarse_max < 1 || r.coarse_max > 6000) throw Error(PS_EINVAL, "coarse_max must be in 1..6000");
     if (r.max_levels < 1 || r.max_levels > 40) throw Error(PS_EINVAL, "max_levels must be in 1..40");
@@ -265,15 +339,17 @@ static inline double unit_hash(uint64_t i) {
 
 static std::vector<char> strength(const Csr &A, double theta) {
     std::vector<char> s(A.ci.size(), 0);
-    for (int i = 0; i < A.n; ++i) {
-        double m = -INFINITY;
-        for (int t = A.rp[i]; t < A.rp[i + 1]; ++t)
-            if (A.ci[t] != i) m = std::max(m, -A.v[t]);
-        if (!(m > 0.0)) continue;
-        double thr = theta * m;
-        for (int t = A.rp[i]; t < A.rp[i + 1]; ++t)
-            if (A.ci[t] != i && -A.v[t] >= thr) s[t] = 1;
-    }
+    parallel_rows(A.n, [&](int b, int e, int) {
+        for (int i = b; i < e; ++i) {
+            double m = -INFINITY;
+            for (int t = A.rp[i]; t < A.rp[i + 1]; ++t)
+                if (A.ci[t] != i) m = std::max(m, -A.v[t]);
+            if (!(m > 0.0)) continue;
+            double thr = theta * m;
+            for (int t = A.rp[i]; t < A.rp[i + 1]; ++t)
+                if (A.ci[t] != i && -A.v[t] >= thr) s[t] = 1;
+        }
+    });
     return s;
 }
 
@@ -361,10 +437,15 @@ static Csr direct_interpolation(const Csr &A, const std::vector<char> &smask,
     P.n = n;
     P.m = nc;
     P.rp.assign(n + 1, 0);
-    for (int i = 0; i < n; ++i) {
+    int nparts = std::min(setup_threads(), std::max(1, n / 8192));
+    std::vector<CsrPart> parts(nparts);
+    parallel_rows(n, [&](int b, int e, int part) {
+    CsrPart &out = parts[part];
+    for (int i = b; i < e; ++i) {
+        int before = (int)out.ci.size();
         if (cf[i] == 1) {
-            P.ci.push_back(cidx[i]);
-            P.v.push_back(1.0);
+            out.ci.push_back(cidx[i]);
+            out.v.push_back(1.0);
         } else {
             double diag = 0.0, pos = 0.0, negs = 0.0, den = 0.0;
             for (int t = A.rp[i]; t < A.rp[i + 1]; ++t) {
@@ -380,13 +461,15 @@ static Csr direct_interpolation(const Csr &A, const std::vector<char> &smask,
             for (int t = A.rp[i]; t < A.rp[i + 1]; ++t) {
                 int j = A.ci[t];
                 if (j != i && smask[t] && cf[j] == 1) {
-                    P.ci.push_back(cidx[j]);
-                    P.v.push_back(-(alpha * A.v[t]) / atil);
+                    out.ci.push_back(cidx[j]);
+                    out.v.push_back(-(alpha * A.v[t]) / atil);
                 }
             }
         }
-        P.rp[i + 1] = (int)P.ci.size();
+        out.len.push_back((int)out.ci.size() - before);
     }
+    });
+    concat_parts(parts, P);
     return P;
 }
 
@@ -416,24 +499,32 @@ static Csr spgemm(const Csr &A, const Csr &B) {
     C.n = A.n;
     C.m = B.m;
     C.rp.assign(A.n + 1, 0);
-    std::vector<double> acc(B.m, 0.0);
-    std::vector<int> mark(B.m, -1), cols;
-    for (int i = 0; i < A.n; ++i) {
-        cols.clear();
-        for (int t = A.rp[i]; t < A.rp[i + 1]; ++t) {
-            int l = A.ci[t];
-            double a = A.v[t];
-            for (int u = B.rp[l]; u < B.rp[l + 1]; ++u) {
-                int k = B.ci[u];
-                if (mark[k] != i) { mark[k] = i; acc[k] = 0.0; cols.push_back(k); }
-                acc[k] += a * B.v[u];
+    int nparts = std::min(setup_threads(), std::max(1, A.n / 8192));
+    std::vector<CsrPart> parts(nparts);
+    parallel_rows(A.n, [&](int b, int e, int p) {
+        CsrPart &out = parts[p];
+        std::vector<double> acc(B.m, 0.0);
+        std::vector<int> mark(B.m, -1), cols;
+        out.len.reserve(e - b);
+        for (int i = b; i < e; ++i) {
+            cols.clear();
+            for (int t = A.rp[i]; t < A.rp[i + 1]; ++t) {
+                int l = A.ci[t];
+                double a = A.v[t];
+                for (int u = B.rp[l]; u < B.rp[l + 1]; ++u) {
+                    int k = B.ci[u];
+                    if (mark[k] != i) { mark[k] = i; acc[k] = 0.0; cols.push_back(k); }
+                    acc[k] += a * B.v[u];
+                }
             }
+            std::sort(cols.begin(), cols.end());
+            int c = 0;
+            for (int k : cols)
+                if (acc[k] != 0.0) { out.ci.push_back(k); out.v.push_back(acc[k]); ++c; }
+            out.len.push_back(c);
         }
-        std::sort(cols.begin(), cols.end());
-        for (int k : cols)
-            if (acc[k] != 0.0) { C.ci.push_back(k); C.v.push_back(acc[k]); }
-        C.rp[i + 1] = (int)C.ci.size();
-    }
+    });
+    concat_parts(parts, C);
     return C;
 }
 
@@ -467,11 +558,13 @@ static void smoother_setup(Level &L, int kind) {
     for (int i = 0; i < n; ++i) v[i] = v[i] / nv;
     double lam = 0.0;
     for (int it = 0; it < 10; ++it) {
-        for (int i = 0; i < n; ++i) {
-            double s = 0.0;
-            for (int t = A.rp[i]; t < A.rp[i + 1]; ++t) s += A.v[t] * v[A.ci[t]];
-            wv[i] = s / L.diag[i];
-        }
+        parallel_rows(n, [&](int b, int e, int) {
+            for (int i = b; i < e; ++i) {
+                double s = 0.0;
+                for (int t = A.rp[i]; t < A.rp[i + 1]; ++t) s += A.v[t] * v[A.ci[t]];
+                wv[i] = s / L.diag[i];
+            }
+        });
         lam = norm2(wv);
         for (int i = 0; i < n; ++i) v[i] = wv[i] / lam;
     }
@@ -503,18 +596,30 @@ Hierarchy amg_build(const Csr &A0, const Options &o) {
     Hierarchy H;
     Csr A = A0;
     while (A.n > o.coarse_max && (int)H.lev.size() + 1 < o.max_levels) {
-        std::vector<char> smask = strength(A, o.theta);
-        std::vector<int8_t> cf = pmis(A, smask);
+        std::vector<char> smask;
+        std::vector<int8_t> cf;
+        {
+            Tick t("strength + PMIS");
+            smask = strength(A, o.theta);
+            cf = pmis(A, smask);
+        }
         int nc = 0;
         for (int8_t c : cf) nc += (c == 1);
         if (nc == 0 || (double)nc > 0.9 * (double)A.n) break;
         Level L;
-        L.P = direct_interpolation(A, smask, cf, nc);
-        L.R = transpose(L.P);
-        Csr Ac = spgemm(L.R, spgemm(A, L.P));
+        Csr Ac;
+        {
+            Tick t("interpolation + RAP");
+            L.P = direct_interpolation(A, smask, cf, nc);
+            L.R = transpose(L.P);
+            Ac = spgemm(L.R, spgemm(A, L.P));
+        }
         L.cf = std::move(cf);
         L.A = std::move(A);
-        smoother_setup(L, o.smoother);
+        {
+            Tick t("smoother setup");
+            smoother_setup(L, o.smoother);
+        }
         H.lev.push_back(std::move(L));
         A = std::move(Ac);
     }
@@ -620,13 +725,48 @@ BiluSchedule bilu_schedule(const Bsr &S) {
     return sc;
 }
 
+// Greedy colouring in increasing row order: each row takes the smallest colour not
+// used by a lower-index neighbour; rows grouped by colour, increasing index within.
+BiluSchedule color_schedule(const Bsr &S) {
+    const int n = S.nbr;
+    std::vector<int> col(n, -1), used;
+    int ncol = 0;
+    for (int i = 0; i < n; ++i) {
+        used.clear();
+        for (int t = S.rp[i]; t < S.rp[i + 1]; ++t)
+            if (S.ci[t] < i) used.push_back(col[S.ci[t]]);
+        int c = 0;
+        while (std::find(used.begin(), used.end(), c) != used.end()) ++c;
+        col[i] = c;
+        ncol = std::max(ncol, c + 1);
+    }
+    BiluSchedule sc;
+    sc.fwd_ptr.assign(ncol + 1, 0);
+    for (int i = 0; i < n; ++i) ++sc.fwd_ptr[col[i] + 1];
+    for (int c = 0; c < ncol; ++c) sc.fwd_ptr[c + 1] += sc.fwd_ptr[c];
+    sc.fwd_rows.resize(n);
+    std::vector<int> fill(sc.fwd_ptr.begin(), sc.fwd_ptr.end() - 1);
+    for (int i = 0; i < n; ++i) sc.fwd_rows[fill[col[i]]++] = i;
+    return sc;
+}
+
 void build_flow(const System &s, const Options &o, FlowSetup &f) {
-    f.Sff = fixed_stress(s);
-    quasi_impes(s, f.Sff, f.Spp, f.dss_inv);
-    f.pres = amg_build(f.Spp, o);
+    {
+        Tick t("fixed stress + qIMPES");
+        f.Sff = fixed_stress(s);
+        quasi_impes(s, f.Sff, f.Spp, f.dss_inv);
+    }
+    {
+        Tick t("pressure AMG");
+        f.pres = amg_build(f.Spp, o);
+    }
+    Tick t("local stage factor");
     if (o.ml_kind == PS_BILU0) {
         bilu0_factor(f.Sff, f.ml);
         f.sched = bilu_schedule(f.Sff);
+    } else if (o.ml_kind == PS_MCGS) {
+        block_jacobi_factor(f.Sff, f.ml);
+        f.sched = color_schedule(f.Sff);
     } else {
         block_jacobi_factor(f.Sff, f.ml);
         f.sched = BiluSchedule();

@@ -63,7 +63,7 @@ struct System {                   // validated host copy of a ps_system
 
 void validate_and_copy(const ps_system *s, System &out);   // throws Error(PS_EINVAL)
 
-struct BiluSchedule {             // level sets of the forward and backward sweeps
+struct BiluSchedule {             // level sets of the BILU sweeps (or colour groups)
     std::vector<int> fwd_ptr, fwd_rows, bwd_ptr, bwd_rows;
 };
 
@@ -84,6 +84,7 @@ Hierarchy amg_build(const Csr &A, const Options &o);
 void bilu0_factor(const Bsr &S, Bsr &F);                 // throws Error(PS_ESINGULAR)
 void block_jacobi_factor(const Bsr &S, Bsr &F);
 BiluSchedule bilu_schedule(const Bsr &S);
+BiluSchedule color_schedule(const Bsr &S);             // colour groups in fwd_ptr/fwd_rows
 void build_flow(const System &s, const Options &o, FlowSetup &f);
 
 // --- small dense helpers ----------------------------------------------------

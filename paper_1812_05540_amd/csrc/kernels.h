@@ -447,6 +447,51 @@ __global__ __launch_bounds__(WG) void bjacobi(Sell<T> S, const T *__restrict__ w
     }
 }
 
+// Multicolour block Gauss-Seidel, one colour: for rows of the colour (no two adjacent),
+// dz_i += D_i^{-1}(w_i - sum_j S_ij dz_j); FINAL: zout_i = [z_s; z_p]_i + dz_i.
+template <int NF, typename T, bool FINAL>
+__global__ __launch_bounds__(WG) void mcgs(Sell<T> S, int pos0, int pos1, const T *__restrict__ win,
+                                          const T *__restrict__ dinv, T *__restrict__ dz,
+                                          const T *__restrict__ zs, const T *__restrict__ zp,
+                                          T *__restrict__ zout) {
+    constexpr int M = NF - 1;
+    int pos = pos0 + blockIdx.x * WG + threadIdx.x;
+    if (pos >= pos1) return;
+    int row = S.rowmap[pos];
+    if (row < 0) return;
+    int lane = pos & 63, s0, w;
+    chunk_of(S, pos, s0, w);
+    const int *col = S.col + (size_t)s0 * 64 + lane;
+    const T *val = S.val + (size_t)s0 * 64 * (NF * NF) + lane;
+    T rv[NF];
+#pragma unroll
+    for (int r = 0; r < NF; ++r) rv[r] = win[(size_t)row * NF + r];
+    for (int k = 0; k < w; ++k) {
+        int c = col[(size_t)k * 64];
+        T xv[NF];
+#pragma unroll
+        for (int e = 0; e < NF; ++e) xv[e] = dz[(size_t)c * NF + e];
+#pragma unroll
+        for (int r = 0; r < NF; ++r)
+#pragma unroll
+            for (int e = 0; e < NF; ++e) rv[r] -= val[((size_t)k * (NF * NF) + r * NF + e) * 64] * xv[e];
+    }
+    const T *d = dinv + (size_t)row * NF * NF;
+#pragma unroll
+    for (int r = 0; r < NF; ++r) {
+        T s = T(0);
+#pragma unroll
+        for (int e = 0; e < NF; ++e) s += d[r * NF + e] * rv[e];
+        size_t o = (size_t)row * NF + r;
+        T v = dz[o] + s;
+        dz[o] = v;
+        if (FINAL) {
+            T zf = r < M ? zs[(size_t)row * M + r] : zp[row];
+            zout[o] = zf + v;
+        }
+    }
+}
+
 // ------------------------------------------------------------------ vector kernels
 template <typename TI, typename TO>
 __global__ __launch_bounds__(WG) void convert(const TI *__restrict__ in, TO *__restrict__ out, size_t n) {

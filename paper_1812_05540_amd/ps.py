@@ -18,7 +18,7 @@ PS_EINVAL, PS_ENOMEM, PS_EDEVICE, PS_ENOTSETUP, PS_ESINGULAR = -1, -2, -3, -4, -
 PS_EMAXIT, PS_EPRECISION, PS_EBUSY, PS_EBREAKDOWN = -6, -7, -8, -9
 PS_FP64, PS_FP32_PREC = 0, 1
 PS_CHEB2, PS_L1JAC = 0, 1
-PS_BILU0, PS_BJACOBI = 0, 1
+PS_BILU0, PS_BJACOBI, PS_MCGS = 0, 1, 2
 PS_H_SDC, PS_H_PRES = 0, 1
 
 _i32p = C.POINTER(C.c_int32)

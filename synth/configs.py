@@ -19,7 +19,7 @@ The paper's SPE10-derived and staircase benchmarks are not available; these
 synthetic fields with the paper's property ranges stand in for them.
 """
 import numpy as np
-from scipy.special import ndtr
+from scipy.special import erfc, ndtr
 
 from .grf import gaussian_field, gaussian_field_2d
 from .jacobian import build_system, make_rhs, two_phase, three_phase, GRAV
@@ -32,16 +32,30 @@ def _rng(seed):
     return np.random.Generator(np.random.PCG64(seed))
 
 
-def _state(rng, nx, ny, nz, h=H):
-    """Synthetic pressure state and reference pressure (hydrostatic part)."""
+def _state(rng, nx, ny, nz, h=H, drive=1.0):
+    """Synthetic pressure state and reference pressure (hydrostatic part).
+
+    drive = +1: pressure rises by 10 MPa along x; -1: falls along x (injection at x = 0).
+    """
     ci = np.tile(np.arange(nx), ny * nz)
     ck = np.repeat(np.arange(nz), nx * ny)
     xc = (ci + 0.5) * h
     zc = (ck + 0.5) * h
     ztop = nz * h
     p0 = 20e6 + 1035.0 * GRAV * (ztop - zc)
-    p = p0 + 10e6 * xc / (nx * h) + rng.normal(0.0, NOISE, nx * ny * nz)
+    ramp = xc / (nx * h) if drive > 0 else 1.0 - xc / (nx * h)
+    p = p0 + 10e6 * ramp + rng.normal(0.0, NOISE, nx * ny * nz)
     return p, p0
+
+
+def flood_saturation(nx, ny, nz, g, front=0.4, width=0.05, swr=0.2, snwr=0.2):
+    """Waterflood state: water injected across the x = 0 face from s = s_wr (the paper's
+    initial state, Sec. 6), front further along permeable streaks.  A time-of-flight
+    proxy tau = (x / L_x) exp(-g / 2) (g: standardised log-permeability) sets
+    s = s_wr + (1 - s_wr - s_nwr) * erfc((tau - front) / width) / 2."""
+    ci = np.tile(np.arange(nx), ny * nz)
+    tau = (ci + 0.5) / nx * np.exp(-0.5 * g)
+    return (swr + (1.0 - swr - snwr) * 0.5 * erfc((tau - front) / width))[:, None]
 
 
 def fields_iid(nx, ny, nz, seed):
@@ -55,7 +69,7 @@ def fields_iid(nx, ny, nz, seed):
     return dict(E=E, kperm=10.0 ** logk, phi=phi, S=S, p=p, p0=p0)
 
 
-def fields_grf(nx, ny, nz, seed, sigma=2.0, mean=-13.0, nph=2, e_seed=None):
+def fields_grf(nx, ny, nz, seed, sigma=2.0, mean=-13.0, nph=2, e_seed=None, sat="iid"):
     rng = _rng(seed)
     g = gaussian_field(rng, (nz, ny, nx), H, (20.0, 200.0, 200.0)).ravel()
     if e_seed is not None:
@@ -67,11 +81,15 @@ def fields_grf(nx, ny, nz, seed, sigma=2.0, mean=-13.0, nph=2, e_seed=None):
     logk = mean + sigma * g
     phi = 0.15 + 0.15 * ndtr(g)
     E = np.exp(np.log(10e9) - 0.5 * ge)
-    if nph == 2:
+    drive = 1.0
+    if nph == 2 and sat == "flood":
+        S = flood_saturation(nx, ny, nz, g)
+        drive = -1.0
+    elif nph == 2:
         S = rng.uniform(0.2, 0.8, (n, 1))
     else:
         S = 0.05 + 0.85 * rng.dirichlet(np.ones(3), n)[:, :2]
-    p, p0 = _state(rng, nx, ny, nz)
+    p, p0 = _state(rng, nx, ny, nz, drive=drive)
     return dict(E=E, kperm=10.0 ** logk, phi=phi, S=S, p=p, p0=p0)
 
 
@@ -105,17 +123,18 @@ WORKLOADS = {
 }
 
 
-def workload(name=None, grid=None, kind="iid", seed=1, rhs_seed=101, sigma=2.0, e_seed=None):
+def workload(name=None, grid=None, kind="iid", seed=1, rhs_seed=101, sigma=2.0, e_seed=None, sat="iid"):
     """Return (system, rhs) for a named workload or an explicit recipe."""
     if name is not None:
         spec = dict(WORKLOADS[name])
         grid, kind, seed, rhs_seed = spec["grid"], spec["kind"], spec["seed"], spec["rhs_seed"]
         sigma = spec.get("sigma", sigma)
+        sat = spec.get("sat", sat)
     nx, ny, nz = grid
     if kind == "iid":
         f, ph = fields_iid(nx, ny, nz, seed), two_phase()
     elif kind == "grf":
-        f, ph = fields_grf(nx, ny, nz, seed, sigma=sigma, e_seed=e_seed), two_phase()
+        f, ph = fields_grf(nx, ny, nz, seed, sigma=sigma, e_seed=e_seed, sat=sat), two_phase()
     elif kind == "layered":
         f, ph = fields_layered(nx, ny, nz, seed), two_phase()
     elif kind == "grf3":
@@ -128,7 +147,7 @@ def workload(name=None, grid=None, kind="iid", seed=1, rhs_seed=101, sigma=2.0, 
     else:
         raise ValueError(kind)
     system = build_system(nx, ny, nz, f, ph)
-    system.meta.update(dict(grid=(nx, ny, nz), kind=kind, seed=seed, rhs_seed=rhs_seed, sigma=sigma))
+    system.meta.update(dict(grid=(nx, ny, nz), kind=kind, seed=seed, rhs_seed=rhs_seed, sigma=sigma, sat=sat))
     return system, make_rhs(system, rhs_seed)
 
 

@@ -63,7 +63,8 @@ def make_solver(ctx, s, **opts):
 
 def oracle_opts(**opts):
     return Options(smoother={ps.PS_CHEB2: "cheb2", ps.PS_L1JAC: "l1jac"}[opts.get("smoother", ps.PS_CHEB2)],
-                   ml_kind={ps.PS_BILU0: "bilu0", ps.PS_BJACOBI: "bjacobi"}[opts.get("ml_kind", ps.PS_BILU0)],
+                   ml_kind={ps.PS_BILU0: "bilu0", ps.PS_BJACOBI: "bjacobi",
+                            ps.PS_MCGS: "mcgs"}[opts.get("ml_kind", ps.PS_BILU0)],
                    ml_sweeps=opts.get("ml_sweeps", 1), restart=opts.get("restart", 100),
                    maxit=opts.get("maxit", 1000))
 
@@ -89,6 +90,8 @@ PRECOND_CASES = [
     ("grf12", dict(ml_kind=ps.PS_BJACOBI, ml_sweeps=3)),
     ("iid3ph", dict()),
     ("iid3ph", dict(ml_kind=ps.PS_BJACOBI, ml_sweeps=2, smoother=ps.PS_L1JAC)),
+    ("grf12", dict(ml_kind=ps.PS_MCGS, ml_sweeps=3)),
+    ("iid3ph", dict(ml_kind=ps.PS_MCGS, ml_sweeps=2)),
 ]
 
 
@@ -123,7 +126,8 @@ def test_precond_fp32_close_to_fp64(ctx, name):
 
 
 @pytest.mark.parametrize("name,opts", [("iid8", dict()), ("grf12", dict(ml_sweeps=2)),
-                                       ("iid3ph", dict(smoother=ps.PS_L1JAC))])
+                                       ("iid3ph", dict(smoother=ps.PS_L1JAC)),
+                                       ("grf12", dict(ml_kind=ps.PS_MCGS, ml_sweeps=3))])
 def test_fp64_solve_matches_oracle(ctx, name, opts):
     s, b = small(name)
     out = oracle_solve(s, b, rtol=1e-8, opts=oracle_opts(**opts), record_iterates=True)
@@ -152,7 +156,9 @@ def test_fp32_solve_reaches_fp64_accuracy(ctx, name):
         xh = host(x)
         assert r["status"] == ps.PS_OK
         true_res = np.linalg.norm(b - A @ xh) / np.linalg.norm(b)
-        assert true_res <= 1.01e-8 and abs(true_res - r["rel_residual"]) <= 1e-3 * true_res + 1e-15
+        # the library's FP64 residual and a SciPy recomputation differ by the cancellation
+        # error of b - A x (~eps |A| |x| / |b|, up to ~1e-11 on these conditionings)
+        assert true_res <= 1.01e-8 and abs(true_res - r["rel_residual"]) <= 1e-10
         res[prec] = np.linalg.norm(xh - tight) / np.linalg.norm(tight)
         sv.close()
     assert res[ps.PS_FP32_PREC] <= max(1e-6, 10 * res[ps.PS_FP64])

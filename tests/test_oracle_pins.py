@@ -98,7 +98,7 @@ def _mat_of(fn, n):
     return np.stack([fn(e) for e in np.eye(n)], axis=1)
 
 
-@pytest.mark.parametrize("ml_kind,sweeps", [("bilu0", 1), ("bilu0", 2), ("bjacobi", 3)])
+@pytest.mark.parametrize("ml_kind,sweeps", [("bilu0", 1), ("bilu0", 2), ("bjacobi", 3), ("mcgs", 3)])
 def test_algorithm1_equals_multistage_formula(ml_kind, sweeps):
     """Steps 3-8 of Alg. 1 equal M_G^{-1} + M_L^{-1}(I - S M_G^{-1}) (eq. mult_prec_op) with
     M_G^{-1} the product of eq. S1_prec, and the whole of Alg. 1 equals the product form of
@@ -127,6 +127,8 @@ def test_algorithm1_equals_multistage_formula(ml_kind, sweeps):
         _, F, Dinv, diag = st.ml
         ML1 = _mat_of(lambda w: local.bilu0_apply(s.Aff.rowptr, s.Aff.colind, F, Dinv, diag,
                                                    w.reshape(-1, nf)).ravel(), nfl)
+    elif ml_kind == "mcgs":
+        ML1 = _mat_of(lambda w: local.mcgs_apply(st.Sff, st.ml[1], st.ml[2], w.reshape(-1, nf), 1).ravel(), nfl)
     else:
         ML1 = sla.block_diag(*st.ml[1])
     # k sweeps of a stationary iteration with B: M_L = sum_{i<k} (I - B S)^i B
@@ -473,3 +475,31 @@ def test_zero_rhs_returns_zero():
     s, _ = tiny()
     out = solve(s, np.zeros(s.N))
     assert out["iterations"] == 0 and not out["x"].any() and out["status"] == 0
+
+
+def test_multicolour_gs_is_block_gs_in_colour_order():
+    """One multicolour sweep equals a block Gauss-Seidel sweep, (D + L)^{-1} w, on the matrix
+    permuted to colour order; the greedy colouring of a 7-point stencil is a checkerboard."""
+    s, _ = tiny(grid=(4, 3, 3))
+    st = P.setup(s, Options(ml_kind="mcgs"))
+    colors = st.ml[2]
+    ci, cj, ck = np.meshgrid(np.arange(4), np.arange(3), np.arange(3), indexing="xy")
+    i = np.tile(np.arange(4), 9)
+    j = np.tile(np.repeat(np.arange(3), 4), 3)
+    k = np.repeat(np.arange(3), 12)
+    assert np.array_equal(colors, (i + j + k) % 2)
+    nf = s.nf
+    order = np.argsort(colors, kind="stable")
+    perm = (order[:, None] * nf + np.arange(nf)[None, :]).ravel()
+    S = dense(st.Sff)[np.ix_(perm, perm)]
+    # block lower triangle including the diagonal cell blocks
+    n = s.n_cells
+    DL = np.zeros_like(S)
+    for a in range(n):
+        for b in range(a + 1):
+            DL[a * nf:(a + 1) * nf, b * nf:(b + 1) * nf] = S[a * nf:(a + 1) * nf, b * nf:(b + 1) * nf]
+    w = np.random.default_rng(4).standard_normal(s.n_f)
+    z_ref = np.zeros(s.n_f)
+    z_ref[perm] = np.linalg.solve(DL, w[perm])
+    z = local.mcgs_apply(st.Sff, st.ml[1], colors, w.reshape(-1, nf), 1).ravel()
+    assert np.allclose(z, z_ref, rtol=1e-10, atol=1e-12 * np.abs(z_ref).max())
