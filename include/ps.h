@@ -80,13 +80,18 @@ typedef struct {
  * nf: 2 or 3.  p_index: which cell dof is the pressure (and which cell row the
  * pressure equation); this library requires p_index == nf - 1.
  * mech_key: non-zero -> handles created with the same key in one context have
- * identical A_uu and share one mechanics AMG hierarchy. */
+ * identical A_uu and share one mechanics AMG hierarchy.
+ * ml_part: optional (NULL = none) subdomain id of each cell.  With it the BILU(0)
+ * local stage is processor-local as in the paper's second example (Sec. 6): the
+ * factorisation drops the couplings between cells of different subdomains, which
+ * shortens the chain of dependent sweep levels; step 6 still uses all of S_ff^(fs). */
 typedef struct {
     int32_t n_nodes, n_cells, nf, p_index;
     ps_bsr Auu, Auf, Afu, Aff;
     const double *d_sp;
     const double *d_pp;
     uint64_t mech_key;
+    const int32_t *ml_part;
 } ps_system;
 
 typedef struct {
@@ -151,8 +156,10 @@ int  ps_spmv(ps_handle *h, const double *x, double *y, void *stream);
 
 /* Serving: enqueue a solve; rhs/x must stay valid until completion.  The
  * context's scheduler admits requests by device-memory footprint and advances
- * all admitted requests one FGMRES iteration per tick (continuous batching). */
-int  ps_submit(ps_handle *h, const double *rhs, double *x, double rtol, uint64_t *ticket);
+ * all admitted requests one FGMRES iteration per tick (continuous batching).
+ * Work already enqueued on `stream` (e.g. the copy that fills rhs) completes
+ * before the request starts; NULL = legacy default stream. */
+int  ps_submit(ps_handle *h, const double *rhs, double *x, double rtol, void *stream, uint64_t *ticket);
 /* PS_PENDING while running; the request's final status once done (result copied). */
 int  ps_poll(ps_ctx *ctx, uint64_t ticket, ps_result *res);
 /* Block until the request finishes; returns its status. */

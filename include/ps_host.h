@@ -52,8 +52,9 @@ int  ps_host_level_lambda(const ps_host_setup *s, int which, int lvl, double *la
 /* Quasi-IMPES pressure matrix values on the A_ff block pattern (Aff.nblocks values). */
 int  ps_host_spp(const ps_host_setup *s, double *vals);
 
-/* BILU(0) factor values on the A_ff block pattern (nblocks * nf * nf; strictly lower
- * blocks hold L_ik, upper blocks U_ij, diagonal blocks D_i^{-1}). */
+/* BILU(0) factor values on the factor's block pattern -- the A_ff pattern, or its
+ * restriction to same-subdomain blocks when ml_part is given -- (nblocks * nf * nf;
+ * strictly lower blocks hold L_ik, upper blocks U_ij, diagonal blocks D_i^{-1}). */
 int  ps_host_bilu(const ps_host_setup *s, double *vals);
 
 /* Level schedule of the BILU(0) forward sweep: number of levels (nf x nf block rows

@@ -14,6 +14,9 @@ hybrid block Gauss-Seidel sweeps or one sweep of pointwise ILU(0) on it.
             pointwise ILU(0) on the block-dense pattern (tested).  With k > 1 sweeps
             the factorisation is used as a stationary iteration:
             dz_1 = B^{-1} w, dz_{i+1} = dz_i + B^{-1}(w - S dz_i).
+            Processor-local form (the paper's second example, Sec. 6): with a cell
+            partition, B is the BILU(0) of S with the couplings between cells of
+            different subdomains removed (block Jacobi over subdomains).
   Jacobi    `sweeps` block-Jacobi sweeps dz += D^{-1}(w - S dz) from dz = 0 with the
             diagonal cell blocks D (a fully parallel relaxation option).
   block GS  the paper's option 1, hybrid block Gauss-Seidel (several sweeps), in its
@@ -82,6 +85,16 @@ def bilu0_apply(rowptr, colind, F, Dinv, diag, w):
             acc -= F[t] @ z[colind[t]]
         z[i] = Dinv[i] @ acc
     return z
+
+
+def restrict_to_parts(rowptr, colind, vals, part):
+    """Block CSR of S keeping only blocks (i, j) with part[i] == part[j]."""
+    n = rowptr.shape[0] - 1
+    rows = np.repeat(np.arange(n), np.diff(rowptr))
+    keep = part[rows] == part[colind]
+    rp = np.zeros(n + 1, np.int64)
+    np.cumsum(np.bincount(rows[keep], minlength=n), out=rp[1:])
+    return rp, colind[keep], vals[keep]
 
 
 def bilu0_sweeps(rowptr, colind, F, Dinv, diag, S, w, sweeps):

@@ -176,8 +176,13 @@ def setup(system, opts=None, mechanics=None):
               smoother=opts.smoother)
     sdc = mechanics if mechanics is not None else amg.build(sdc_matrix(system), **kw)
     pres = amg.build(Spp, **kw)
-    if opts.ml_kind == "bilu0":
-        ml = ("bilu0",) + local.bilu0_factor(system.Aff.rowptr, system.Aff.colind, sff_vals)
+    part = getattr(system, "ml_part", None)
+    if opts.ml_kind == "bilu0" and part is not None:
+        rp, ci, vals = local.restrict_to_parts(system.Aff.rowptr, system.Aff.colind, sff_vals, part)
+        ml = ("bilu0",) + local.bilu0_factor(rp, ci, vals) + (rp, ci)
+    elif opts.ml_kind == "bilu0":
+        ml = ("bilu0",) + local.bilu0_factor(system.Aff.rowptr, system.Aff.colind, sff_vals) + (
+            system.Aff.rowptr, system.Aff.colind)
     elif opts.ml_kind == "bjacobi":
         ml = ("bjacobi", local.block_diag_inv(system.Aff.rowptr, system.Aff.colind, sff_vals))
     elif opts.ml_kind == "mcgs":
@@ -224,11 +229,10 @@ def apply_precond(st, v):
         return amg.vcycle(st.pres, wp, o.smoother)
 
     if st.ml[0] == "bilu0":
-        _, F, Dinv, diag = st.ml
+        _, F, Dinv, diag, lrp, lci = st.ml
 
         def ML(w):
-            return local.bilu0_sweeps(s.Aff.rowptr, s.Aff.colind, F, Dinv, diag, st.Sff,
-                                      w.reshape(-1, nf), o.ml_sweeps).ravel()
+            return local.bilu0_sweeps(lrp, lci, F, Dinv, diag, st.Sff, w.reshape(-1, nf), o.ml_sweeps).ravel()
     elif st.ml[0] == "mcgs":
         Dinv, colors = st.ml[1], st.ml[2]
 

@@ -152,6 +152,7 @@ struct Request {
     size_t bytes = 0;
     double t_submit = 0.0, t_start = 0.0;
     hipStream_t st = nullptr;
+    hipEvent_t ready = nullptr;       // recorded on the caller's stream at submit
     std::unique_ptr<Krylov> K;
     std::unique_ptr<PrecFn> M;
     std::unique_ptr<Fgmres> run;
@@ -439,7 +440,7 @@ void ps_destroy(ps_handle *h) {
 }
 
 // ---------------------------------------------------------------- serving
-int ps_submit(ps_handle *h, const double *rhs, double *x, double rtol, uint64_t *ticket) {
+int ps_submit(ps_handle *h, const double *rhs, double *x, double rtol, void *stream, uint64_t *ticket) {
     return guard([&] {
         check_solve_args(h, rhs, x, rtol);
         if (!ticket) throw Error(PS_EINVAL, "ticket is NULL");
@@ -447,6 +448,14 @@ int ps_submit(ps_handle *h, const double *rhs, double *x, double rtol, uint64_t 
         if (!h->busy.compare_exchange_strong(expected, true)) throw Error(PS_EBUSY, "handle has a request in flight");
         ps_ctx *c = h->ctx;
         auto r = std::make_unique<Request>();
+        try {
+            set_device(c->device);
+            PS_HIP(hipEventCreateWithFlags(&r->ready, hipEventDisableTiming));
+            PS_HIP(hipEventRecord(r->ready, (hipStream_t)stream));
+        } catch (...) {
+            h->busy = false;
+            throw;
+        }
         r->ticket = c->next_ticket++;
         r->h = h;
         r->rhs = rhs;
@@ -515,6 +524,8 @@ void ps_ctx::scheduler() {
         r->res.solve_s = now_s() - r->t_submit;
         if (r->st) (void)hipStreamDestroy(r->st);
         r->st = nullptr;
+        if (r->ready) (void)hipEventDestroy(r->ready);
+        r->ready = nullptr;
         r->run.reset();
         r->M.reset();
         r->K.reset();
@@ -534,6 +545,8 @@ void ps_ctx::scheduler() {
                     r->status = PS_EBUSY;
                     r->res.status = PS_EBUSY;
                     r->h->busy = false;
+                    if (r->ready) (void)hipEventDestroy(r->ready);
+                    r->ready = nullptr;
                 }
                 queue.clear();
                 done_cv.notify_all();
@@ -551,6 +564,7 @@ void ps_ctx::scheduler() {
             int code = guard([&] {
                 bool f32 = use_fp32(r->h);
                 PS_HIP(hipStreamCreateWithFlags(&r->st, hipStreamNonBlocking));
+                PS_HIP(hipStreamWaitEvent(r->st, r->ready, 0));
                 r->K = std::make_unique<Krylov>();
                 alloc_krylov(*r->K, r->h->sys.N(), r->h->opt.restart, f32);
                 if (f32) r->M = std::make_unique<Prec32>(r->h);

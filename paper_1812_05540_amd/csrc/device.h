@@ -92,10 +92,19 @@ template <typename T>
 Sell<T> upload_sell(Arena &ar, const HostSell &h);
 
 // ---- preconditioner device data ------------------------------------------------
+// Scalar CSR on the device, processed by groups of G lanes per row (G a power of
+// two chosen from the mean row length when uploaded).
+template <typename T>
+struct DCsr {
+    int n = 0, G = 1;
+    const int *rp = nullptr, *ci = nullptr;
+    const T *v = nullptr;
+};
+
 template <typename T>
 struct DLevel {                   // matrices and per-row constants of one AMG level
     int n = 0;
-    Sell<T> A, P, R;
+    DCsr<T> A, P, R;
     const T *dinv = nullptr;      // l1-Jacobi: 1 / (a_ii + sum |a_ij|)
     const T *c0 = nullptr, *c1 = nullptr, *cm = nullptr;   // Chebyshev
 };
@@ -125,6 +134,7 @@ struct DFlow {                    // flow stage of Algorithm 1 (rebuilt every se
     // local stage
     Sell<T> Lf, Ub;               // BILU strict lower / upper blocks, rows in level order
     std::vector<int> lchunk_f, lchunk_b;   // chunk ranges per level
+    const int *d_lchunk_f = nullptr, *d_lchunk_b = nullptr;   // the same on the device
     const T *dinv = nullptr;      // BILU D_i^{-1} or block-Jacobi D^{-1}, nc * nf * nf
     Arena arena;
     size_t bytes() const { return arena.bytes() + (pres ? pres->bytes() : 0); }

@@ -1,8 +1,10 @@
 // Device data layout, uploads and the solve-phase drivers (Algorithm 1, FGMRES).
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
+#include <string>
 
 #include "kernels.h"
 
@@ -96,6 +98,21 @@ Sell<T> upload_sell(Arena &ar, const HostSell &h) {
 }
 
 template <typename T>
+static DCsr<T> upload_csr(Arena &ar, const Csr &A) {
+    DCsr<T> d;
+    d.n = A.n;
+    double avg = A.n ? (double)A.nnz() / A.n : 1.0;
+    int G = 1;
+    while (G < 32 && G * 3 < avg) G *= 2;
+    d.G = G;
+    d.rp = ar.upload(A.rp.data(), A.rp.size());
+    d.ci = ar.upload(A.ci.data(), A.ci.size());
+    std::vector<T> v(A.v.begin(), A.v.end());
+    d.v = ar.upload(v.data(), v.size());
+    return d;
+}
+
+template <typename T>
 static const T *upload_vec(Arena &ar, const std::vector<double> &v) {
     std::vector<T> t(v.begin(), v.end());
     return ar.upload(t.data(), t.size());
@@ -162,9 +179,9 @@ std::unique_ptr<DHierarchy<T>> upload_hierarchy(const Hierarchy &H, int smoother
         if (l == 0 && interleave3) interleave_level0(A, P, R, {&dl1, &c0, &c1, &cm});
         DLevel<T> &D = d->lev[l];
         D.n = A.n;
-        D.A = upload_sell<T>(d->arena, sell_from_csr(A));
-        D.P = upload_sell<T>(d->arena, sell_from_csr(P));
-        D.R = upload_sell<T>(d->arena, sell_from_csr(R));
+        D.A = upload_csr<T>(d->arena, A);
+        D.P = upload_csr<T>(d->arena, P);
+        D.R = upload_csr<T>(d->arena, R);
         if (smoother == PS_L1JAC) {
             std::vector<double> inv(dl1.size());
             for (size_t i = 0; i < dl1.size(); ++i) inv[i] = 1.0 / dl1[i];
@@ -212,6 +229,8 @@ std::unique_ptr<DFlow<T>> upload_flow(const FlowSetup &f, const System &s, const
         std::vector<int> ob = order(f.sched.bwd_ptr, f.sched.bwd_rows, d->lchunk_b);
         d->Lf = upload_sell<T>(d->arena, sell_from_bsr(f.ml.rp, f.ml.ci, f.ml.v, nc, nf, nf, &of, keep_lower));
         d->Ub = upload_sell<T>(d->arena, sell_from_bsr(f.ml.rp, f.ml.ci, f.ml.v, nc, nf, nf, &ob, keep_upper));
+        d->d_lchunk_f = d->arena.upload(d->lchunk_f.data(), d->lchunk_f.size());
+        d->d_lchunk_b = d->arena.upload(d->lchunk_b.data(), d->lchunk_b.size());
         for (int i = 0; i < nc; ++i)
             for (int t = f.ml.rp[i]; t < f.ml.rp[i + 1]; ++t)
                 if (f.ml.ci[t] == i) std::memcpy(&dinv[(size_t)i * nn], &f.ml.v[(size_t)t * nn], sizeof(double) * nn);
@@ -284,6 +303,27 @@ void alloc_prec_work(PrecWork<T> &w, const DHierarchy<T> &sdc, const DFlow<T> &f
 }
 
 // ------------------------------------------------------------------ V-cycle
+// Calls f with a compile-time group width equal to G.
+template <typename F>
+static void with_G(int G, F &&f) {
+    switch (G) {
+    case 1: f(std::integral_constant<int, 1>{}); break;
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    case 16: f(std::integral_constant<int, 16>{}); break;
+    default: f(std::integral_constant<int, 32>{}); break;
+    }
+}
+
+template <int MODE, typename T>
+static void csr_spmv(const DCsr<T> &A, const T *x, const T *b, T *y, hipStream_t st) {
+    with_G(A.G, [&](auto Gc) {
+        constexpr int G = decltype(Gc)::value;
+        LAUNCH((k::csr_spmv<G, MODE, T>), grid_for((size_t)A.n * G), 0, st, A, x, b, y);
+    });
+}
+
 template <typename T>
 static void vcycle(const DHierarchy<T> &H, HierWork<T> &W, int l, const T *b, T *out, hipStream_t st) {
     const int last = (int)H.lev.size() - 1;
@@ -293,26 +333,44 @@ static void vcycle(const DHierarchy<T> &H, HierWork<T> &W, int l, const T *b, T 
         return;
     }
     const DLevel<T> &L = H.lev[l];
-    unsigned g = grid_for(L.n);
-    if (H.smoother == PS_CHEB2) {
-        LAUNCH((k::cheb_pre<T>), g, 0, st, L.A, b, L.c0, L.c1, L.cm, W.x[l]);
-        LAUNCH((k::spmv<1, 1, T, T, T, 1>), g, 0, st, L.A, (const T *)W.x[l], b, W.r[l]);
-    } else {
-        LAUNCH((k::l1_pre<T>), g, 0, st, L.A, b, L.dinv, W.x[l], W.r[l]);
-    }
-    LAUNCH((k::spmv<1, 1, T, T, T, 0>), grid_for(H.lev[l + 1].n), 0, st, L.R, (const T *)W.r[l],
-           (const T *)nullptr, W.b[l + 1]);
+    const bool cheb = H.smoother == PS_CHEB2;
+    with_G(L.A.G, [&](auto Gc) {
+        constexpr int G = decltype(Gc)::value;
+        unsigned g = grid_for((size_t)L.n * G);
+        if (cheb) {
+            LAUNCH((k::csr_cheb_pre<G, T>), g, 0, st, L.A, b, L.c0, L.c1, L.cm, W.x[l]);
+            LAUNCH((k::csr_spmv<G, 1, T>), g, 0, st, L.A, (const T *)W.x[l], b, W.r[l]);
+        } else {
+            LAUNCH((k::csr_l1_pre<G, T>), g, 0, st, L.A, b, L.dinv, W.x[l], W.r[l]);
+        }
+    });
+    csr_spmv<0, T>(L.R, (const T *)W.r[l], (const T *)nullptr, W.b[l + 1], st);
     vcycle(H, W, l + 1, W.b[l + 1], W.e[l + 1], st);
-    LAUNCH((k::spmv<1, 1, T, T, T, 2>), g, 0, st, L.P, (const T *)W.e[l + 1], (const T *)nullptr, W.x[l]);
-    if (H.smoother == PS_CHEB2) {
-        LAUNCH((k::cheb_post1<T>), g, 0, st, L.A, b, (const T *)W.x[l], L.c0, W.x1[l], W.d[l]);
-        LAUNCH((k::cheb_post2<T>), g, 0, st, L.A, b, (const T *)W.x1[l], (const T *)W.d[l], L.c1, L.cm, out);
-    } else {
-        LAUNCH((k::l1_post<T>), g, 0, st, L.A, b, (const T *)W.x[l], L.dinv, out);
-    }
+    csr_spmv<2, T>(L.P, (const T *)W.e[l + 1], (const T *)nullptr, W.x[l], st);
+    with_G(L.A.G, [&](auto Gc) {
+        constexpr int G = decltype(Gc)::value;
+        unsigned g = grid_for((size_t)L.n * G);
+        if (cheb) {
+            LAUNCH((k::csr_cheb_post1<G, T>), g, 0, st, L.A, b, (const T *)W.x[l], L.c0, W.x1[l], W.d[l]);
+            LAUNCH((k::csr_cheb_post2<G, T>), g, 0, st, L.A, b, (const T *)W.x1[l], (const T *)W.d[l], L.c1,
+                   L.cm, out);
+        } else {
+            LAUNCH((k::csr_l1_post<G, T>), g, 0, st, L.A, b, (const T *)W.x[l], L.dinv, out);
+        }
+    });
 }
 
 // ------------------------------------------------------------------ Algorithm 1
+// BILU sweeps: one launch per level (default), or one workgroup walking all levels
+// (PS_BILU_LAUNCH=1wg; measured slower on MI355X, kept for comparison).
+static bool bilu_one_workgroup() {
+    static const bool v = [] {
+        const char *e = std::getenv("PS_BILU_LAUNCH");
+        return e && std::string(e) == "1wg";
+    }();
+    return v;
+}
+
 template <int NF, typename T>
 static void local_stage(const DFlow<T> &fl, PrecWork<T> &w, T *zf, hipStream_t st) {
     const int sweeps = fl.ml_sweeps;
@@ -350,11 +408,31 @@ static void local_stage(const DFlow<T> &fl, PrecWork<T> &w, T *zf, hipStream_t s
         }
         return;
     }
+    const bool one_wg = bilu_one_workgroup();
     for (int s = 0; s < sweeps; ++s) {
         const T *src = w.w;
         if (s > 0) {
             LAUNCH((k::spmv<NF, NF, T, T, T, 1>), g, 0, st, fl.Sff, (const T *)w.dz, (const T *)w.w, w.r2);
             src = w.r2;
+        }
+        if (one_wg) {
+            bool final = s == sweeps - 1;
+            int nlf = (int)fl.lchunk_f.size() - 1, nlb = (int)fl.lchunk_b.size() - 1;
+            hipLaunchKernelGGL((k::bilu_fwd_1wg<NF, T>), dim3(1), dim3(k::WG1), 0, st, fl.Lf, fl.d_lchunk_f, nlf,
+                               src, w.t);
+            if (s == 0 && final)
+                hipLaunchKernelGGL((k::bilu_bwd_1wg<NF, T, false, true>), dim3(1), dim3(k::WG1), 0, st, fl.Ub,
+                                   fl.d_lchunk_b, nlb, w.t, fl.dinv, w.dz, w.zs, w.zp, zf);
+            else if (s == 0)
+                hipLaunchKernelGGL((k::bilu_bwd_1wg<NF, T, false, false>), dim3(1), dim3(k::WG1), 0, st, fl.Ub,
+                                   fl.d_lchunk_b, nlb, w.t, fl.dinv, w.dz, w.zs, w.zp, zf);
+            else if (final)
+                hipLaunchKernelGGL((k::bilu_bwd_1wg<NF, T, true, true>), dim3(1), dim3(k::WG1), 0, st, fl.Ub,
+                                   fl.d_lchunk_b, nlb, w.t, fl.dinv, w.dz, w.zs, w.zp, zf);
+            else
+                hipLaunchKernelGGL((k::bilu_bwd_1wg<NF, T, true, false>), dim3(1), dim3(k::WG1), 0, st, fl.Ub,
+                                   fl.d_lchunk_b, nlb, w.t, fl.dinv, w.dz, w.zs, w.zp, zf);
+            continue;
         }
         for (size_t l = 0; l + 1 < fl.lchunk_f.size(); ++l) {
             int p0 = fl.lchunk_f[l] * 64, p1 = fl.lchunk_f[l + 1] * 64;

@@ -168,6 +168,12 @@ void validate_and_copy(const ps_system *s, System &out) {
         if (!std::isfinite(v)) throw Error(PS_EINVAL, "d_sp: non-finite value");
     for (double v : out.d_pp)
         if (!std::isfinite(v)) throw Error(PS_EINVAL, "d_pp: non-finite value");
+    out.ml_part.clear();
+    if (s->ml_part) {
+        out.ml_part.assign(s->ml_part, s->ml_part + s->n_cells);
+        for (int v : out.ml_part)
+            if (v < 0) throw Error(PS_EINVAL, "ml_part: negative subdomain id");
+    }
 }
 
 // ---------------------------------------------------------------- small dense
@@ -692,6 +698,25 @@ void block_jacobi_factor(const Bsr &S, Bsr &F) {
     F.rp[n] = n;
 }
 
+Bsr restrict_to_parts(const Bsr &S, const std::vector<int> &part) {
+    Bsr R;
+    R.nbr = S.nbr;
+    R.nbc = S.nbc;
+    R.br = S.br;
+    R.bc = S.bc;
+    const int nn = S.br * S.bc;
+    R.rp.assign(S.nbr + 1, 0);
+    for (int i = 0; i < S.nbr; ++i) {
+        for (int t = S.rp[i]; t < S.rp[i + 1]; ++t) {
+            if (part[S.ci[t]] != part[i]) continue;
+            R.ci.push_back(S.ci[t]);
+            R.v.insert(R.v.end(), S.v.begin() + (size_t)t * nn, S.v.begin() + (size_t)(t + 1) * nn);
+        }
+        R.rp[i + 1] = (int)R.ci.size();
+    }
+    return R;
+}
+
 BiluSchedule bilu_schedule(const Bsr &S) {
     const int n = S.nbr;
     std::vector<int> lf(n, 0), lb(n, 0);
@@ -761,7 +786,11 @@ void build_flow(const System &s, const Options &o, FlowSetup &f) {
         f.pres = amg_build(f.Spp, o);
     }
     Tick t("local stage factor");
-    if (o.ml_kind == PS_BILU0) {
+    if (o.ml_kind == PS_BILU0 && !s.ml_part.empty()) {
+        Bsr local = restrict_to_parts(f.Sff, s.ml_part);
+        bilu0_factor(local, f.ml);
+        f.sched = bilu_schedule(local);
+    } else if (o.ml_kind == PS_BILU0) {
         bilu0_factor(f.Sff, f.ml);
         f.sched = bilu_schedule(f.Sff);
     } else if (o.ml_kind == PS_MCGS) {

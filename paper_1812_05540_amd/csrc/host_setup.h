@@ -57,6 +57,7 @@ struct System {                   // validated host copy of a ps_system
     int n_nodes = 0, n_cells = 0, nf = 0;
     Bsr Auu, Auf, Afu, Aff;
     std::vector<double> d_sp, d_pp;
+    std::vector<int> ml_part;     // empty: global BILU(0)
     uint64_t mech_key = 0;
     size_t N() const { return (size_t)3 * n_nodes + (size_t)nf * n_cells; }
 };
@@ -82,6 +83,7 @@ void quasi_impes(const System &s, const Bsr &Sff, Csr &Spp, std::vector<double> 
 Csr sdc_matrix(const System &s);                         // component-major
 Hierarchy amg_build(const Csr &A, const Options &o);
 void bilu0_factor(const Bsr &S, Bsr &F);                 // throws Error(PS_ESINGULAR)
+Bsr restrict_to_parts(const Bsr &S, const std::vector<int> &part);   // drop inter-part blocks
 void block_jacobi_factor(const Bsr &S, Bsr &F);
 BiluSchedule bilu_schedule(const Bsr &S);
 BiluSchedule color_schedule(const Bsr &S);             // colour groups in fwd_ptr/fwd_rows

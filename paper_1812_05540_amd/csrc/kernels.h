@@ -228,6 +228,100 @@ __global__ __launch_bounds__(WG) void coarse_solve(const double *__restrict__ Ai
     if (lane == 0) x[row] = (T)s;
 }
 
+// ------------------------------------------------------------------ AMG levels in CSR
+// G consecutive lanes share one row (G = 1..64, a power of two): lane g of the group
+// accumulates entries rp[i]+g, rp[i]+g+G, ...; the group then reduces with shuffles
+// (fixed pattern, so the result is deterministic).  Consecutive groups take
+// consecutive rows, so a wavefront reads one contiguous stretch of ci/v.
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T a) {
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) a += __shfl_xor(a, off, G);
+    return a;
+}
+
+// sum_j a_ij x_j (or a_ij x_j s_j when S) for the calling group's row
+template <int G, bool S, typename T>
+__device__ __forceinline__ T csr_dot(const DCsr<T> &A, int i, int g, const T *__restrict__ x,
+                                     const T *__restrict__ s) {
+    T acc = T(0);
+    int e = A.rp[i + 1];
+    for (int t = A.rp[i] + g; t < e; t += G) {
+        int c = A.ci[t];
+        acc += A.v[t] * (S ? x[c] * s[c] : x[c]);
+    }
+    return group_sum<G>(acc);
+}
+
+#define PS_CSR_ROW(G)                                         \
+    int gid = blockIdx.x * WG + threadIdx.x;                  \
+    int i = gid / G, g = gid % G;                             \
+    if (i >= A.n) return;
+
+// y = A x (0), b - A x (1), y + A x (2)
+template <int G, int MODE, typename T>
+__global__ __launch_bounds__(WG) void csr_spmv(DCsr<T> A, const T *__restrict__ x, const T *__restrict__ b,
+                                              T *__restrict__ y) {
+    PS_CSR_ROW(G)
+    T a = csr_dot<G, false>(A, i, g, x, x);
+    if (g == 0) y[i] = MODE == 0 ? a : MODE == 1 ? b[i] - a : y[i] + a;
+}
+
+template <int G, typename T>
+__global__ __launch_bounds__(WG) void csr_l1_pre(DCsr<T> A, const T *__restrict__ b, const T *__restrict__ dinv,
+                                                T *__restrict__ x, T *__restrict__ r) {
+    PS_CSR_ROW(G)
+    T a = csr_dot<G, true>(A, i, g, b, dinv);
+    if (g == 0) {
+        T bi = b[i];
+        x[i] = bi * dinv[i];
+        r[i] = bi - a;
+    }
+}
+
+template <int G, typename T>
+__global__ __launch_bounds__(WG) void csr_cheb_pre(DCsr<T> A, const T *__restrict__ b, const T *__restrict__ c0,
+                                                  const T *__restrict__ c1, const T *__restrict__ cm,
+                                                  T *__restrict__ x) {
+    PS_CSR_ROW(G)
+    T a = csr_dot<G, true>(A, i, g, b, c0);
+    if (g == 0) {
+        T d0 = c0[i] * b[i];
+        T r1 = b[i] - a;
+        x[i] = d0 + (cm[i] * d0 + c1[i] * r1);
+    }
+}
+
+template <int G, typename T>
+__global__ __launch_bounds__(WG) void csr_cheb_post1(DCsr<T> A, const T *__restrict__ b, const T *__restrict__ x,
+                                                    const T *__restrict__ c0, T *__restrict__ x1,
+                                                    T *__restrict__ d0) {
+    PS_CSR_ROW(G)
+    T a = csr_dot<G, false>(A, i, g, x, x);
+    if (g == 0) {
+        T d = c0[i] * (b[i] - a);
+        d0[i] = d;
+        x1[i] = x[i] + d;
+    }
+}
+
+template <int G, typename T>
+__global__ __launch_bounds__(WG) void csr_cheb_post2(DCsr<T> A, const T *__restrict__ b, const T *__restrict__ x1,
+                                                    const T *__restrict__ d0, const T *__restrict__ c1,
+                                                    const T *__restrict__ cm, T *__restrict__ out) {
+    PS_CSR_ROW(G)
+    T a = csr_dot<G, false>(A, i, g, x1, x1);
+    if (g == 0) out[i] = x1[i] + (cm[i] * d0[i] + c1[i] * (b[i] - a));
+}
+
+template <int G, typename T>
+__global__ __launch_bounds__(WG) void csr_l1_post(DCsr<T> A, const T *__restrict__ b, const T *__restrict__ x,
+                                                 const T *__restrict__ dinv, T *__restrict__ out) {
+    PS_CSR_ROW(G)
+    T a = csr_dot<G, false>(A, i, g, x, x);
+    if (g == 0) out[i] = x[i] + (b[i] - a) * dinv[i];
+}
+
 // ------------------------------------------------------------------ Algorithm 1 kernels
 // Steps 2-3: y = v_f - A_fu z_u (per cell), z_s = D_ss^{-1} y_s.
 template <int NF, typename T>
@@ -398,6 +492,107 @@ __global__ __launch_bounds__(WG) void bilu_bwd(Sell<T> U, int pos0, int pos1, T 
             T zf = r < M ? zs[(size_t)row * M + r] : zp[row];
             zout[o] = zf + v;
         }
+    }
+}
+
+// The same sweeps with all levels in one workgroup of WG1 threads: one barrier per
+// level.  __syncthreads() makes the workgroup's global writes of a level visible to
+// its reads in the next, so no kernel boundary is needed between levels.
+constexpr int WG1 = 1024;
+
+template <int NF, typename T>
+__device__ __forceinline__ void bilu_row_fwd(const Sell<T> &L, int pos, const T *__restrict__ win, T *__restrict__ t) {
+    int row = L.rowmap[pos];
+    if (row < 0) return;
+    int lane = pos & 63, s0, w;
+    chunk_of(L, pos, s0, w);
+    const int *col = L.col + (size_t)s0 * 64 + lane;
+    const T *val = L.val + (size_t)s0 * 64 * (NF * NF) + lane;
+    T acc[NF];
+#pragma unroll
+    for (int r = 0; r < NF; ++r) acc[r] = T(0);
+    for (int k = 0; k < w; ++k) {
+        int c = col[(size_t)k * 64];
+        T xv[NF];
+#pragma unroll
+        for (int e = 0; e < NF; ++e) xv[e] = t[(size_t)c * NF + e];
+#pragma unroll
+        for (int r = 0; r < NF; ++r)
+#pragma unroll
+            for (int e = 0; e < NF; ++e) acc[r] += val[((size_t)k * (NF * NF) + r * NF + e) * 64] * xv[e];
+    }
+#pragma unroll
+    for (int r = 0; r < NF; ++r) t[(size_t)row * NF + r] = win[(size_t)row * NF + r] - acc[r];
+}
+
+template <int NF, typename T>
+__global__ __launch_bounds__(WG1) void bilu_fwd_1wg(Sell<T> L, const int *__restrict__ lchunk, int nlev,
+                                                   const T *__restrict__ win, T *__restrict__ t) {
+    for (int l = 0; l < nlev; ++l) {
+        int p0 = lchunk[l] * 64, p1 = lchunk[l + 1] * 64;
+        for (int pos = p0 + (int)threadIdx.x; pos < p1; pos += WG1) bilu_row_fwd<NF, T>(L, pos, win, t);
+        __syncthreads();
+    }
+}
+
+template <int NF, typename T, bool ACC, bool FINAL>
+__device__ __forceinline__ void bilu_row_bwd(const Sell<T> &U, int pos, T *__restrict__ t, const T *__restrict__ dinv,
+                                             T *__restrict__ dz, const T *__restrict__ zs,
+                                             const T *__restrict__ zp, T *__restrict__ zout) {
+    constexpr int M = NF - 1;
+    int row = U.rowmap[pos];
+    if (row < 0) return;
+    int lane = pos & 63, s0, w;
+    chunk_of(U, pos, s0, w);
+    const int *col = U.col + (size_t)s0 * 64 + lane;
+    const T *val = U.val + (size_t)s0 * 64 * (NF * NF) + lane;
+    T acc[NF];
+#pragma unroll
+    for (int r = 0; r < NF; ++r) acc[r] = T(0);
+    for (int k = 0; k < w; ++k) {
+        int c = col[(size_t)k * 64];
+        T xv[NF];
+#pragma unroll
+        for (int e = 0; e < NF; ++e) xv[e] = t[(size_t)c * NF + e];
+#pragma unroll
+        for (int r = 0; r < NF; ++r)
+#pragma unroll
+            for (int e = 0; e < NF; ++e) acc[r] += val[((size_t)k * (NF * NF) + r * NF + e) * 64] * xv[e];
+    }
+    T rv[NF], dl[NF];
+#pragma unroll
+    for (int r = 0; r < NF; ++r) rv[r] = t[(size_t)row * NF + r] - acc[r];
+    const T *d = dinv + (size_t)row * NF * NF;
+#pragma unroll
+    for (int r = 0; r < NF; ++r) {
+        T s = T(0);
+#pragma unroll
+        for (int e = 0; e < NF; ++e) s += d[r * NF + e] * rv[e];
+        dl[r] = s;
+    }
+#pragma unroll
+    for (int r = 0; r < NF; ++r) {
+        size_t o = (size_t)row * NF + r;
+        t[o] = dl[r];
+        T v = ACC ? dz[o] + dl[r] : dl[r];
+        if (!FINAL) dz[o] = v;
+        if (FINAL) {
+            T zf = r < M ? zs[(size_t)row * M + r] : zp[row];
+            zout[o] = zf + v;
+        }
+    }
+}
+
+template <int NF, typename T, bool ACC, bool FINAL>
+__global__ __launch_bounds__(WG1) void bilu_bwd_1wg(Sell<T> U, const int *__restrict__ lchunk, int nlev,
+                                                   T *__restrict__ t, const T *__restrict__ dinv,
+                                                   T *__restrict__ dz, const T *__restrict__ zs,
+                                                   const T *__restrict__ zp, T *__restrict__ zout) {
+    for (int l = 0; l < nlev; ++l) {
+        int p0 = lchunk[l] * 64, p1 = lchunk[l + 1] * 64;
+        for (int pos = p0 + (int)threadIdx.x; pos < p1; pos += WG1)
+            bilu_row_bwd<NF, T, ACC, FINAL>(U, pos, t, dinv, dz, zs, zp, zout);
+        __syncthreads();
     }
 }
 

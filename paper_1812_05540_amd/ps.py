@@ -33,7 +33,7 @@ class ps_bsr(C.Structure):
 class ps_system(C.Structure):
     _fields_ = [("n_nodes", C.c_int32), ("n_cells", C.c_int32), ("nf", C.c_int32), ("p_index", C.c_int32),
                 ("Auu", ps_bsr), ("Auf", ps_bsr), ("Afu", ps_bsr), ("Aff", ps_bsr),
-                ("d_sp", _f64p), ("d_pp", _f64p), ("mech_key", C.c_uint64)]
+                ("d_sp", _f64p), ("d_pp", _f64p), ("mech_key", C.c_uint64), ("ml_part", _i32p)]
 
 
 class ps_options(C.Structure):
@@ -61,7 +61,7 @@ _SIGS = {
     "ps_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.POINTER(ps_result)]),
     "ps_apply_precond": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "ps_spmv": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
-    "ps_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.POINTER(C.c_uint64)]),
+    "ps_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.POINTER(C.c_uint64)]),
     "ps_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(ps_result)]),
     "ps_wait": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(ps_result)]),
     "ps_footprint": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
@@ -153,9 +153,15 @@ def make_system(sysobj, mech_key=0):
     d_sp = np.ascontiguousarray(sysobj.d_sp, dtype=np.float64)
     d_pp = np.ascontiguousarray(sysobj.d_pp, dtype=np.float64)
     keep += [d_sp, d_pp]
+    part = getattr(sysobj, "ml_part", None)
+    part_ptr = None
+    if part is not None:
+        part = np.ascontiguousarray(part, dtype=np.int32)
+        keep.append(part)
+        part_ptr = part.ctypes.data_as(_i32p)
     s = ps_system(int(sysobj.n_nodes), int(sysobj.n_cells), int(sysobj.nf), int(sysobj.p_index),
                   _bsr(sysobj.Auu, keep), _bsr(sysobj.Auf, keep), _bsr(sysobj.Afu, keep), _bsr(sysobj.Aff, keep),
-                  d_sp.ctypes.data_as(_f64p), d_pp.ctypes.data_as(_f64p), int(mech_key))
+                  d_sp.ctypes.data_as(_f64p), d_pp.ctypes.data_as(_f64p), int(mech_key), part_ptr)
     return s, keep
 
 
@@ -221,9 +227,9 @@ def ps_spmv(h, x, y, stream=None):
     _check(load().ps_spmv(h, _ptr(x), _ptr(y), _stream(stream)), "ps_spmv")
 
 
-def ps_submit(h, rhs, x, rtol):
+def ps_submit(h, rhs, x, rtol, stream=None):
     t = C.c_uint64()
-    _check(load().ps_submit(h, _ptr(rhs), _ptr(x), float(rtol), C.byref(t)), "ps_submit")
+    _check(load().ps_submit(h, _ptr(rhs), _ptr(x), float(rtol), _stream(stream), C.byref(t)), "ps_submit")
     return t.value
 
 
@@ -353,8 +359,8 @@ class Solver:
     def spmv(self, x, y, stream=None):
         ps_spmv(self.h, x, y, stream)
 
-    def submit(self, rhs, x, rtol=1e-8):
-        return ps_submit(self.h, rhs, x, rtol)
+    def submit(self, rhs, x, rtol=1e-8, stream=None):
+        return ps_submit(self.h, rhs, x, rtol, stream)
 
     def footprint(self):
         return ps_footprint(self.h)

@@ -32,6 +32,10 @@ Readings where the paper is silent or inconsistent:
   * Synthetic state: p = 20 MPa + rho_w0 g (z_top - z) + 10 MPa x/L_x + N(0, 0.1 MPa),
     p0 = the hydrostatic part; upwind tie (zero potential) -> lower-index cell.
   * No wells (the configurations define none).
+  * The displacement block is constant over a simulation (Sec. 5.2: the elasticity
+    operator does not change), so its gravity term uses the mixture-density derivative
+    at a reference state (reference densities, equal phase saturations) rather than
+    the current state; systems on the same grid with the same moduli then share A_uu.
 """
 from dataclasses import dataclass, field
 import numpy as np
@@ -81,6 +85,7 @@ class PoroSystem:
     scale_u: float = 1.0
     scale_f: np.ndarray = None
     meta: dict = field(default_factory=dict)
+    ml_part: np.ndarray = None    # optional subdomain id per cell (processor-local BILU)
 
     @property
     def n_nodes(self):
@@ -397,8 +402,9 @@ def assemble(nx, ny, nz, fields, phases, h=10.0, dt=86400.0, nu=0.25, biot=1.0, 
 
     s = phases.saturations(S)
     rho = phases.rho0[None, :] * (1.0 + phases.comp[None, :] * (p - p0)[:, None])
-    # mixture-density derivatives (App. B.2), b = 1 and incompressible grains
-    drho_deps = (-rho_s + (s * rho).sum(1)) * biot
+    # mixture-density derivatives (App. B.2), b = 1 and incompressible grains; the one in
+    # A_uu at the reference state (equal saturations, reference densities)
+    drho_deps = np.full(nc, (-rho_s + phases.rho0.mean()) * biot)
     drho_dp = phi * (s * (phases.rho0 * phases.comp)[None, :]).sum(1)
     drho_dS = phi[:, None] * (rho @ phases.dsat())        # (n, nph-1)
 
@@ -532,3 +538,12 @@ def make_rhs(system, seed):
     b = rng.standard_normal(system.N)
     b[: system.n_u][system.constrained] = 0.0
     return b
+
+
+def box_partition(nx, ny, nz, bx, by, bz):
+    """Subdomain id per cell for a partition into bx x by x bz-cell boxes (x fastest)."""
+    i = np.tile(np.arange(nx), ny * nz)
+    j = np.tile(np.repeat(np.arange(ny), nx), nz)
+    k = np.repeat(np.arange(nz), nx * ny)
+    px, py = -(-nx // bx), -(-ny // by)
+    return ((i // bx) + px * ((j // by) + py * (k // bz))).astype(np.int32)

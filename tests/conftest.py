@@ -1,6 +1,11 @@
 import os
 import sys
 
+# The oracle's dense BLAS reductions are made single-threaded so that its rounding (and
+# thus its iteration counts on ill-conditioned systems) does not depend on the host.
+for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+    os.environ[_v] = "1"
+
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -17,3 +22,11 @@ def pytest_configure(config):
 def iid8():
     from synth import workload
     return workload("iid8")
+
+
+def pytest_sessionstart(session):
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except Exception:
+        pass

@@ -124,7 +124,7 @@ def test_algorithm1_equals_multistage_formula(ml_kind, sweeps):
     MG = np.zeros((nfl, nfl))
     MG[np.ix_(perm, perm)] = MG_part
     if ml_kind == "bilu0":
-        _, F, Dinv, diag = st.ml
+        _, F, Dinv, diag = st.ml[:4]
         ML1 = _mat_of(lambda w: local.bilu0_apply(s.Aff.rowptr, s.Aff.colind, F, Dinv, diag,
                                                    w.reshape(-1, nf)).ravel(), nfl)
     elif ml_kind == "mcgs":
@@ -503,3 +503,27 @@ def test_multicolour_gs_is_block_gs_in_colour_order():
     z_ref[perm] = np.linalg.solve(DL, w[perm])
     z = local.mcgs_apply(st.Sff, st.ml[1], colors, w.reshape(-1, nf), 1).ravel()
     assert np.allclose(z, z_ref, rtol=1e-10, atol=1e-12 * np.abs(z_ref).max())
+
+
+def test_processor_local_bilu_reduces_to_known_cases():
+    """One cell per subdomain: processor-local BILU(0) is block Jacobi.  One x-line per
+    subdomain: it is the exact inverse of each line's block-tridiagonal matrix."""
+    from synth.jacobian import box_partition
+    s, _ = tiny(grid=(5, 3, 2))
+    nf, n = s.nf, s.n_cells
+    w = np.random.default_rng(6).standard_normal(s.n_f)
+    for bx, expect in ((1, "jacobi"), (5, "lines")):
+        s.ml_part = box_partition(5, 3, 2, bx, 1, 1)
+        st = P.setup(s)
+        z = P.apply_precond(st, np.concatenate([np.zeros(s.n_u), w]))  # noqa: F841 (exercise)
+        _, F, Dinv, diag, lrp, lci = st.ml
+        dz = local.bilu0_apply(lrp, lci, F, Dinv, diag, w.reshape(-1, nf)).ravel()
+        S = dense(st.Sff)
+        keep = np.zeros_like(S, bool)
+        for i in range(n):
+            for j in range(n):
+                if s.ml_part[i] == s.ml_part[j]:
+                    keep[i * nf:(i + 1) * nf, j * nf:(j + 1) * nf] = True
+        ref = np.linalg.solve(np.where(keep, S, 0.0), w)
+        assert np.allclose(dz, ref, rtol=1e-10, atol=1e-12 * np.abs(ref).max()), expect
+    s.ml_part = None
