@@ -118,7 +118,7 @@ def run_gpu(args, s, b):
     return out
 
 
-def cpu_baseline(s, b, its_gpu, budget_s):
+def cpu_baseline(s, b, its_gpu, budget_s, args):
     """The oracle (FP64, NumPy/SciPy, one thread) on a bounded sample of the same
     workload: its flow-stage setup plus up to two FGMRES iterations (mechanics AMG
     built once beforehand, as on the GPU); solves/s extrapolated with the GPU's
@@ -126,9 +126,9 @@ def cpu_baseline(s, b, its_gpu, budget_s):
     os.environ.setdefault("OMP_NUM_THREADS", "1")
     from oracle import precond as P, amg, Options
     from oracle.fgmres import fgmres
-    o = Options()
+    o = Options(smoother=args.smoother, ml_kind=args.ml_kind, ml_sweeps=args.ml_sweeps)
     t0 = time.perf_counter()
-    sdc = amg.build(P.sdc_matrix(s))
+    sdc = amg.build(P.sdc_matrix(s), smoother=args.smoother)
     t_mech = time.perf_counter() - t0
     t0 = time.perf_counter()
     st = P.setup(s, o, mechanics=sdc)
@@ -155,7 +155,9 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--ml-sweeps", type=int, default=1)
     ap.add_argument("--smoother", default="cheb2", choices=["cheb2", "l1jac"])
-    ap.add_argument("--ml-kind", default="bilu0", choices=["bilu0", "bjacobi"])
+    ap.add_argument("--ml-kind", default="bilu0", choices=["bilu0", "bjacobi", "mcgs"])
+    ap.add_argument("--ml-part", default="",
+                    help="processor-local local stage: subdomain box size in cells, e.g. 16,16,16")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=30.0)
@@ -164,11 +166,15 @@ def main():
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     args.smoother_code = 0 if args.smoother == "cheb2" else 1
-    args.ml_kind_code = 0 if args.ml_kind == "bilu0" else 1
+    args.ml_kind_code = {"bilu0": 0, "bjacobi": 1, "mcgs": 2}[args.ml_kind]
 
     from synth import workload
     t0 = time.perf_counter()
     s, b = workload(args.workload)
+    if args.ml_part:
+        from synth.jacobian import box_partition
+        bx, by, bz = (int(v) for v in args.ml_part.split(","))
+        s.ml_part = box_partition(*s.meta["grid"], bx, by, bz)
     log("workload %s: N=%d generated in %.1fs" % (args.workload, s.N, time.perf_counter() - t0))
     g = run_gpu(args, s, b)
     head = g.get("fp32") or g.get("fp64")
@@ -189,7 +195,8 @@ def main():
                                "two-stage preconditioner, rtol %g; step = flow-stage setup + solve"
                                % (args.workload, *s.meta["grid"], s.N, args.rtol),
                    "precision": "fp32-preconditioner" if "fp32" in g else "fp64",
-                   "ml_sweeps": args.ml_sweeps, "smoother": args.smoother, "ml_kind": args.ml_kind},
+                   "ml_sweeps": args.ml_sweeps, "smoother": args.smoother, "ml_kind": args.ml_kind,
+                   "ml_part": args.ml_part or "global"},
         "paths": {k: v for k, v in g.items() if k in ("fp32", "fp64")},
         "roofline": g["roofline"],
     }
@@ -197,7 +204,7 @@ def main():
         line["fp32_over_fp64_speedup"] = round(g["fp32"]["solves_per_s"] / g["fp64"]["solves_per_s"], 3)
         line["fp32_vs_fp64_solution_rel_diff"] = g.get("fp32_vs_fp64_solution_rel_diff")
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(s, b, head["iterations"], args.cpu_budget_s)
+        line["cpu_baseline"] = cpu_baseline(s, b, head["iterations"], args.cpu_budget_s, args)
     print(json.dumps(line), flush=True)
 
 

@@ -104,6 +104,8 @@ struct ps_handle {
     FlowSetup flow;
     std::unique_ptr<DFlow<double>> fl64;
     std::unique_ptr<DFlow<float>> fl32;
+    Staging staging;
+    bool afu_changed = true;          // A_fu values changed since the last upload
     PrecWork<double> w64;
     PrecWork<float> w32;
     std::unique_ptr<Krylov> K;
@@ -284,6 +286,7 @@ int ps_update_flow(ps_handle *h, const double *afu, const double *aff, const dou
             std::memcpy(dst.data(), src, dst.size() * sizeof(double));
         };
         take(s.Afu.v, afu);
+        if (afu) h->afu_changed = true;
         take(s.Aff.v, aff);
         take(s.d_sp, d_sp);
         take(s.d_pp, d_pp);
@@ -321,16 +324,17 @@ int ps_setup(ps_handle *h) {
             build_flow(h->sys, h->opt, h->flow);
         }
         PhaseTimer pt("flow upload + work");
-        h->fl64.reset();
-        h->fl32.reset();
         if (f64) {
-            h->fl64 = upload_flow<double>(h->flow, h->sys, h->opt);
+            if (!h->fl64) h->fl64 = std::make_unique<DFlow<double>>();
+            update_flow<double>(*h->fl64, h->flow, h->sys, h->opt, h->staging, h->afu_changed);
             alloc_prec_work(h->w64, *h->mech->d64, *h->fl64, h->sys.n_nodes);
         }
         if (f32) {
-            h->fl32 = upload_flow<float>(h->flow, h->sys, h->opt);
+            if (!h->fl32) h->fl32 = std::make_unique<DFlow<float>>();
+            update_flow<float>(*h->fl32, h->flow, h->sys, h->opt, h->staging, h->afu_changed);
             alloc_prec_work(h->w32, *h->mech->d32, *h->fl32, h->sys.n_nodes);
         }
+        h->afu_changed = false;
         PS_HIP(hipDeviceSynchronize());
         h->setup_s = now_s() - t0;
         h->ready = true;

@@ -13,34 +13,44 @@ namespace ps {
 void hip_check(hipError_t e, const char *what);
 #define PS_HIP(x) ::ps::hip_check((x), #x)
 
-// Device allocations owned by one object; freed together.
+// Device allocations owned by one object; freed together.  recycle() keeps the
+// blocks for reuse by later alloc() calls of the same or slightly smaller size, so a
+// setup that is repeated with new values does not go back to hipMalloc/hipFree.
 class Arena {
   public:
     Arena() = default;
     Arena(const Arena &) = delete;
     Arena &operator=(const Arena &) = delete;
-    Arena(Arena &&o) noexcept : ptrs_(std::move(o.ptrs_)), bytes_(o.bytes_) { o.bytes_ = 0; }
+    Arena(Arena &&o) noexcept : used_(std::move(o.used_)), free_(std::move(o.free_)) {}
     Arena &operator=(Arena &&o) noexcept {
         if (this != &o) {
             release();
-            ptrs_ = std::move(o.ptrs_);
-            bytes_ = o.bytes_;
-            o.bytes_ = 0;
+            used_ = std::move(o.used_);
+            free_ = std::move(o.free_);
         }
         return *this;
     }
     ~Arena() { release(); }
     template <typename T>
     T *alloc(size_t n) {
-        if (n == 0) n = 1;
+        size_t bytes = ((n ? n : 1) * sizeof(T) + 255) / 256 * 256;
+        size_t best = free_.size();
+        for (size_t i = 0; i < free_.size(); ++i)
+            if (free_[i].bytes >= bytes && free_[i].bytes <= 2 * bytes &&
+                (best == free_.size() || free_[i].bytes < free_[best].bytes))
+                best = i;
+        if (best != free_.size()) {
+            used_.push_back(free_[best]);
+            free_.erase(free_.begin() + best);
+            return static_cast<T *>(used_.back().p);
+        }
         void *p = nullptr;
-        hipError_t e = hipMalloc(&p, n * sizeof(T));
+        hipError_t e = hipMalloc(&p, bytes);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             throw Error(PS_ENOMEM, "hipMalloc failed");
         }
-        ptrs_.push_back(p);
-        bytes_ += n * sizeof(T);
+        used_.push_back({p, bytes});
         return static_cast<T *>(p);
     }
     template <typename T>
@@ -49,16 +59,29 @@ class Arena {
         if (n) PS_HIP(hipMemcpy(d, h, n * sizeof(T), hipMemcpyHostToDevice));
         return d;
     }
-    void release() {
-        for (void *p : ptrs_) (void)hipFree(p);
-        ptrs_.clear();
-        bytes_ = 0;
+    void recycle() {
+        free_.insert(free_.end(), used_.begin(), used_.end());
+        used_.clear();
     }
-    size_t bytes() const { return bytes_; }
+    void release() {
+        for (auto &b : used_) (void)hipFree(b.p);
+        for (auto &b : free_) (void)hipFree(b.p);
+        used_.clear();
+        free_.clear();
+    }
+    size_t bytes() const {
+        size_t t = 0;
+        for (auto &b : used_) t += b.bytes;
+        for (auto &b : free_) t += b.bytes;
+        return t;
+    }
 
   private:
-    std::vector<void *> ptrs_;
-    size_t bytes_ = 0;
+    struct Blk {
+        void *p;
+        size_t bytes;
+    };
+    std::vector<Blk> used_, free_;
 };
 
 // Sliced ELLPACK with 64-row chunks (one wavefront per chunk) over br x bc blocks.
@@ -81,12 +104,13 @@ struct HostSell {                 // host image of a Sell before upload
     int nrows = 0, nchunks = 0, br = 1, bc = 1;
     std::vector<int> cptr, col, rowmap;
     std::vector<double> val;
+    std::vector<int> src;         // per slot and lane: source block index, -1 = padding
 };
 
 HostSell sell_from_bsr(const std::vector<int> &rp, const std::vector<int> &ci,
                        const std::vector<double> &v, int nbr, int br, int bc,
                        const std::vector<int> *row_order = nullptr,
-                       bool (*keep)(int row, int col) = nullptr);
+                       bool (*keep)(int row, int col) = nullptr, bool values = true);
 HostSell sell_from_csr(const Csr &A);
 template <typename T>
 Sell<T> upload_sell(Arena &ar, const HostSell &h);
@@ -126,22 +150,35 @@ struct HierWork {                 // per-handle vectors of one hierarchy
 };
 
 template <typename T>
-struct DFlow {                    // flow stage of Algorithm 1 (rebuilt every setup)
+struct DFlow {                    // flow stage of Algorithm 1 on the device
     int nc = 0, nf = 0, ml_kind = PS_BILU0, ml_sweeps = 1;
+    bool layout = false;          // patterns fixed for the life of a handle
     Sell<T> Afu, Sff;             // nf x 3 and nf x nf
-    const T *dss_inv = nullptr;   // nc * (nf-1)^2
+    Sell<T> Lf, Ub;               // BILU strict lower / upper blocks in level order (block GS:
+                                  // Lf = all S_ff blocks in colour order)
+    T *afu_val = nullptr, *sff_val = nullptr, *lf_val = nullptr, *ub_val = nullptr;
+    std::vector<int> src_afu, src_sff, src_lf, src_ub;   // value source maps (host)
+    std::vector<int> lchunk_f, lchunk_b;                 // chunk ranges per level / colour
+    const int *d_lchunk_f = nullptr, *d_lchunk_b = nullptr;
+    T *dss_inv = nullptr;         // nc * (nf-1)^2
+    T *dinv = nullptr;            // BILU D_i^{-1} or block-diagonal inverse, nc * nf * nf
     std::unique_ptr<DHierarchy<T>> pres;
-    // local stage
-    Sell<T> Lf, Ub;               // BILU strict lower / upper blocks, rows in level order
-    std::vector<int> lchunk_f, lchunk_b;   // chunk ranges per level
-    const int *d_lchunk_f = nullptr, *d_lchunk_b = nullptr;   // the same on the device
-    const T *dinv = nullptr;      // BILU D_i^{-1} or block-Jacobi D^{-1}, nc * nf * nf
-    Arena arena;
+    Arena arena;                  // fixed-layout arrays
     size_t bytes() const { return arena.bytes() + (pres ? pres->bytes() : 0); }
+};
+
+// Pinned host buffer for value uploads.
+struct Staging {
+    void *p = nullptr;
+    size_t bytes = 0;
+    void *get(size_t n);
+    ~Staging();
 };
 
 template <typename T>
 struct PrecWork {                 // per-handle work vectors for Algorithm 1
+    bool fixed = false;           // sizes of everything but the pressure levels are fixed
+    Arena pres_arena;             // pressure-level vectors (sizes change with each setup)
     HierWork<T> sdc, pres;
     T *vconv = nullptr;           // v_u rounded to T (FP32 path)
     T *y = nullptr, *zs = nullptr, *wp = nullptr, *zp = nullptr;   // steps 2-5
@@ -175,7 +212,10 @@ struct Krylov {                   // FGMRES workspace (FP64 basis, Z in the prec
 template <typename T>
 std::unique_ptr<DHierarchy<T>> upload_hierarchy(const Hierarchy &H, int smoother, bool interleave3);
 template <typename T>
-std::unique_ptr<DFlow<T>> upload_flow(const FlowSetup &f, const System &s, const Options &o);
+void upload_hierarchy_into(DHierarchy<T> &d, const Hierarchy &H, int smoother, bool interleave3);
+template <typename T>
+void update_flow(DFlow<T> &d, const FlowSetup &f, const System &s, const Options &o, Staging &stg,
+                 bool afu_changed);
 void upload_system(const System &s, DSystem &d);
 template <typename T>
 void alloc_prec_work(PrecWork<T> &w, const DHierarchy<T> &sdc, const DFlow<T> &fl, int n_nodes);

@@ -29,7 +29,7 @@ static inline unsigned grid_for(size_t n) { return (unsigned)((n + WG - 1) / WG)
 // ------------------------------------------------------------------ SELL
 HostSell sell_from_bsr(const std::vector<int> &rp, const std::vector<int> &ci, const std::vector<double> &v,
                        int nbr, int br, int bc, const std::vector<int> *row_order,
-                       bool (*keep)(int, int)) {
+                       bool (*keep)(int, int), bool values) {
     HostSell h;
     h.br = br;
     h.bc = bc;
@@ -61,7 +61,8 @@ HostSell sell_from_bsr(const std::vector<int> &rp, const std::vector<int> &ci, c
     }
     size_t nslots = (size_t)h.cptr[h.nchunks];
     h.col.assign(nslots * 64, 0);
-    h.val.assign(nslots * 64 * rc, 0.0);
+    h.src.assign(nslots * 64, -1);
+    if (values) h.val.assign(nslots * 64 * rc, 0.0);
     for (int pos = 0; pos < h.nrows; ++pos) {
         int row = order[pos];
         if (row < 0) continue;
@@ -71,7 +72,9 @@ HostSell sell_from_bsr(const std::vector<int> &rp, const std::vector<int> &ci, c
         for (int t = rp[row]; t < rp[row + 1]; ++t) {
             if (keep && !keep(row, ci[t])) continue;
             h.col[(s0 + kk) * 64 + lane] = ci[t];
-            for (int e = 0; e < rc; ++e) h.val[((s0 + kk) * rc + e) * 64 + lane] = v[(size_t)t * rc + e];
+            h.src[(s0 + kk) * 64 + lane] = t;
+            if (values)
+                for (int e = 0; e < rc; ++e) h.val[((s0 + kk) * rc + e) * 64 + lane] = v[(size_t)t * rc + e];
             ++kk;
         }
     }
@@ -167,54 +170,138 @@ static void interleave_level0(Csr &A, Csr &P, Csr &R, std::vector<std::vector<do
 }
 
 template <typename T>
-std::unique_ptr<DHierarchy<T>> upload_hierarchy(const Hierarchy &H, int smoother, bool interleave3) {
-    auto d = std::make_unique<DHierarchy<T>>();
+void upload_hierarchy_into(DHierarchy<T> &dh, const Hierarchy &H, int smoother, bool interleave3) {
+    DHierarchy<T> *d = &dh;
+    d->arena.recycle();
     d->smoother = smoother;
     int nl = (int)H.lev.size();
-    d->lev.resize(nl);
+    d->lev.assign(nl, DLevel<T>());
     for (int l = 0; l + 1 < nl; ++l) {
         const Level &L = H.lev[l];
-        Csr A = L.A, P = L.P, R = L.R;
-        std::vector<double> dl1 = L.dl1, c0 = L.c0, c1 = L.c1, cm = L.cm;
-        if (l == 0 && interleave3) interleave_level0(A, P, R, {&dl1, &c0, &c1, &cm});
         DLevel<T> &D = d->lev[l];
-        D.n = A.n;
-        D.A = upload_csr<T>(d->arena, A);
-        D.P = upload_csr<T>(d->arena, P);
-        D.R = upload_csr<T>(d->arena, R);
+        if (l == 0 && interleave3) {
+            Csr A = L.A, P = L.P, R = L.R;
+            std::vector<double> dl1 = L.dl1, c0 = L.c0, c1 = L.c1, cm = L.cm;
+            interleave_level0(A, P, R, {&dl1, &c0, &c1, &cm});
+            D.n = A.n;
+            D.A = upload_csr<T>(d->arena, A);
+            D.P = upload_csr<T>(d->arena, P);
+            D.R = upload_csr<T>(d->arena, R);
+            if (smoother == PS_L1JAC) {
+                std::vector<double> inv(dl1.size());
+                for (size_t i = 0; i < dl1.size(); ++i) inv[i] = 1.0 / dl1[i];
+                D.dinv = upload_vec<T>(d->arena, inv);
+            } else {
+                D.c0 = upload_vec<T>(d->arena, c0);
+                D.c1 = upload_vec<T>(d->arena, c1);
+                D.cm = upload_vec<T>(d->arena, cm);
+            }
+            continue;
+        }
+        D.n = L.A.n;
+        D.A = upload_csr<T>(d->arena, L.A);
+        D.P = upload_csr<T>(d->arena, L.P);
+        D.R = upload_csr<T>(d->arena, L.R);
         if (smoother == PS_L1JAC) {
-            std::vector<double> inv(dl1.size());
-            for (size_t i = 0; i < dl1.size(); ++i) inv[i] = 1.0 / dl1[i];
+            std::vector<double> inv(L.dl1.size());
+            for (size_t i = 0; i < L.dl1.size(); ++i) inv[i] = 1.0 / L.dl1[i];
             D.dinv = upload_vec<T>(d->arena, inv);
         } else {
-            D.c0 = upload_vec<T>(d->arena, c0);
-            D.c1 = upload_vec<T>(d->arena, c1);
-            D.cm = upload_vec<T>(d->arena, cm);
+            D.c0 = upload_vec<T>(d->arena, L.c0);
+            D.c1 = upload_vec<T>(d->arena, L.c1);
+            D.cm = upload_vec<T>(d->arena, L.cm);
         }
     }
     d->lev[nl - 1].n = H.coarse_n;
     d->cn = H.coarse_n;
     d->cinv = d->arena.upload(H.coarse_inv.data(), H.coarse_inv.size());
+}
+
+template <typename T>
+std::unique_ptr<DHierarchy<T>> upload_hierarchy(const Hierarchy &H, int smoother, bool interleave3) {
+    auto d = std::make_unique<DHierarchy<T>>();
+    upload_hierarchy_into(*d, H, smoother, interleave3);
     return d;
 }
 
 static bool keep_lower(int row, int col) { return col < row; }
 static bool keep_upper(int row, int col) { return col > row; }
 
+void *Staging::get(size_t n) {
+    if (n > bytes) {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        bytes = 0;
+        PS_HIP(hipHostMalloc(&p, n, hipHostMallocDefault));
+        bytes = n;
+    }
+    return p;
+}
+
+Staging::~Staging() {
+    if (p) (void)hipHostFree(p);
+}
+
+// Scatter block values into the SELL slot layout (src: source block per slot lane),
+// converting to T, in a pinned buffer, then copy to the device array.
 template <typename T>
-std::unique_ptr<DFlow<T>> upload_flow(const FlowSetup &f, const System &s, const Options &o) {
-    auto d = std::make_unique<DFlow<T>>();
+static void upload_values(T *dev, const std::vector<int> &src, int rc, const std::vector<double> &v,
+                          Staging &stg) {
+    size_t nslots = src.size() / 64;
+    if (nslots == 0) return;
+    T *out = static_cast<T *>(stg.get(nslots * 64 * rc * sizeof(T)));
+    parallel_for((int)nslots, [&](int b, int e, int) {
+        for (int s = b; s < e; ++s)
+            for (int l = 0; l < 64; ++l) {
+                int t = src[(size_t)s * 64 + l];
+                for (int q = 0; q < rc; ++q)
+                    out[((size_t)s * rc + q) * 64 + l] = t < 0 ? T(0) : (T)v[(size_t)t * rc + q];
+            }
+    });
+    PS_HIP(hipMemcpy(dev, out, nslots * 64 * rc * sizeof(T), hipMemcpyHostToDevice));
+}
+
+template <typename T>
+static void upload_dense(T *dev, const std::vector<double> &v, Staging &stg) {
+    if (v.empty()) return;
+    T *out = static_cast<T *>(stg.get(v.size() * sizeof(T)));
+    parallel_for((int)v.size(), [&](int b, int e, int) {
+        for (int i = b; i < e; ++i) out[i] = (T)v[i];
+    });
+    PS_HIP(hipMemcpy(dev, out, v.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+template <typename T>
+static Sell<T> layout_sell(Arena &ar, const HostSell &h, T *&val, std::vector<int> &src) {
+    Sell<T> s;
+    s.nrows = h.nrows;
+    s.nchunks = h.nchunks;
+    s.br = h.br;
+    s.bc = h.bc;
+    s.nslots = h.cptr.empty() ? 0 : (size_t)h.cptr.back();
+    s.cptr = ar.upload(h.cptr.data(), h.cptr.size());
+    s.col = ar.upload(h.col.data(), h.col.size());
+    if (!h.rowmap.empty()) s.rowmap = ar.upload(h.rowmap.data(), h.rowmap.size());
+    val = ar.template alloc<T>(s.nslots * 64 * h.br * h.bc);
+    s.val = val;
+    src = h.src;
+    return s;
+}
+
+template <typename T>
+void update_flow(DFlow<T> &d, const FlowSetup &f, const System &s, const Options &o, Staging &stg,
+                 bool afu_changed) {
     const int nf = s.nf, nc = s.n_cells, nn = nf * nf;
-    d->nc = nc;
-    d->nf = nf;
-    d->ml_kind = o.ml_kind;
-    d->ml_sweeps = o.ml_sweeps;
-    d->Afu = upload_sell<T>(d->arena, sell_from_bsr(s.Afu.rp, s.Afu.ci, s.Afu.v, nc, nf, 3));
-    d->Sff = upload_sell<T>(d->arena, sell_from_bsr(f.Sff.rp, f.Sff.ci, f.Sff.v, nc, nf, nf));
-    d->dss_inv = upload_vec<T>(d->arena, f.dss_inv);
-    d->pres = upload_hierarchy<T>(f.pres, o.smoother, false);
-    std::vector<double> dinv((size_t)nc * nn);
-    if (o.ml_kind == PS_BILU0) {
+    static const std::vector<double> none;
+    if (!d.layout) {
+        d.nc = nc;
+        d.nf = nf;
+        d.ml_kind = o.ml_kind;
+        d.ml_sweeps = o.ml_sweeps;
+        d.Afu = layout_sell<T>(d.arena, sell_from_bsr(s.Afu.rp, s.Afu.ci, none, nc, nf, 3, nullptr, nullptr, false),
+                               d.afu_val, d.src_afu);
+        d.Sff = layout_sell<T>(d.arena, sell_from_bsr(f.Sff.rp, f.Sff.ci, none, nc, nf, nf, nullptr, nullptr, false),
+                               d.sff_val, d.src_sff);
         auto order = [&](const std::vector<int> &ptr, const std::vector<int> &rows, std::vector<int> &lchunk) {
             std::vector<int> ord;
             lchunk.assign(1, 0);
@@ -225,30 +312,44 @@ std::unique_ptr<DFlow<T>> upload_flow(const FlowSetup &f, const System &s, const
             }
             return ord;
         };
-        std::vector<int> of = order(f.sched.fwd_ptr, f.sched.fwd_rows, d->lchunk_f);
-        std::vector<int> ob = order(f.sched.bwd_ptr, f.sched.bwd_rows, d->lchunk_b);
-        d->Lf = upload_sell<T>(d->arena, sell_from_bsr(f.ml.rp, f.ml.ci, f.ml.v, nc, nf, nf, &of, keep_lower));
-        d->Ub = upload_sell<T>(d->arena, sell_from_bsr(f.ml.rp, f.ml.ci, f.ml.v, nc, nf, nf, &ob, keep_upper));
-        d->d_lchunk_f = d->arena.upload(d->lchunk_f.data(), d->lchunk_f.size());
-        d->d_lchunk_b = d->arena.upload(d->lchunk_b.data(), d->lchunk_b.size());
-        for (int i = 0; i < nc; ++i)
-            for (int t = f.ml.rp[i]; t < f.ml.rp[i + 1]; ++t)
-                if (f.ml.ci[t] == i) std::memcpy(&dinv[(size_t)i * nn], &f.ml.v[(size_t)t * nn], sizeof(double) * nn);
-    } else if (o.ml_kind == PS_MCGS) {
-        std::vector<int> ord;
-        d->lchunk_f.assign(1, 0);
-        for (size_t c = 0; c + 1 < f.sched.fwd_ptr.size(); ++c) {
-            for (int p = f.sched.fwd_ptr[c]; p < f.sched.fwd_ptr[c + 1]; ++p) ord.push_back(f.sched.fwd_rows[p]);
-            while (ord.size() % 64) ord.push_back(-1);
-            d->lchunk_f.push_back((int)(ord.size() / 64));
+        if (o.ml_kind == PS_BILU0) {
+            std::vector<int> of = order(f.sched.fwd_ptr, f.sched.fwd_rows, d.lchunk_f);
+            std::vector<int> ob = order(f.sched.bwd_ptr, f.sched.bwd_rows, d.lchunk_b);
+            d.Lf = layout_sell<T>(d.arena, sell_from_bsr(f.ml.rp, f.ml.ci, none, nc, nf, nf, &of, keep_lower, false),
+                                  d.lf_val, d.src_lf);
+            d.Ub = layout_sell<T>(d.arena, sell_from_bsr(f.ml.rp, f.ml.ci, none, nc, nf, nf, &ob, keep_upper, false),
+                                  d.ub_val, d.src_ub);
+            d.d_lchunk_f = d.arena.upload(d.lchunk_f.data(), d.lchunk_f.size());
+            d.d_lchunk_b = d.arena.upload(d.lchunk_b.data(), d.lchunk_b.size());
+        } else if (o.ml_kind == PS_MCGS) {
+            std::vector<int> oc = order(f.sched.fwd_ptr, f.sched.fwd_rows, d.lchunk_f);
+            d.Lf = layout_sell<T>(d.arena, sell_from_bsr(f.Sff.rp, f.Sff.ci, none, nc, nf, nf, &oc, nullptr, false),
+                                  d.lf_val, d.src_lf);
         }
-        d->Lf = upload_sell<T>(d->arena, sell_from_bsr(f.Sff.rp, f.Sff.ci, f.Sff.v, nc, nf, nf, &ord));
-        dinv = f.ml.v;
+        d.dss_inv = d.arena.template alloc<T>(f.dss_inv.size());
+        d.dinv = d.arena.template alloc<T>((size_t)nc * nn);
+        d.pres = std::make_unique<DHierarchy<T>>();
+        d.layout = true;
+        afu_changed = true;
+    }
+    if (afu_changed) upload_values(d.afu_val, d.src_afu, nf * 3, s.Afu.v, stg);
+    upload_values(d.sff_val, d.src_sff, nn, f.Sff.v, stg);
+    upload_dense(d.dss_inv, f.dss_inv, stg);
+    std::vector<double> dinv((size_t)nc * nn);
+    if (o.ml_kind == PS_BILU0) {
+        upload_values(d.lf_val, d.src_lf, nn, f.ml.v, stg);
+        upload_values(d.ub_val, d.src_ub, nn, f.ml.v, stg);
+        parallel_for(nc, [&](int b, int e, int) {
+            for (int i = b; i < e; ++i)
+                for (int t = f.ml.rp[i]; t < f.ml.rp[i + 1]; ++t)
+                    if (f.ml.ci[t] == i) std::memcpy(&dinv[(size_t)i * nn], &f.ml.v[(size_t)t * nn], sizeof(double) * nn);
+        });
     } else {
+        if (o.ml_kind == PS_MCGS) upload_values(d.lf_val, d.src_lf, nn, f.Sff.v, stg);
         dinv = f.ml.v;
     }
-    d->dinv = upload_vec<T>(d->arena, dinv);
-    return d;
+    upload_dense(d.dinv, dinv, stg);
+    upload_hierarchy_into(*d.pres, f.pres, o.smoother, false);
 }
 
 void upload_system(const System &s, DSystem &d) {
@@ -287,19 +388,22 @@ static void alloc_hier_work(HierWork<T> &w, const DHierarchy<T> &H, Arena &ar) {
 
 template <typename T>
 void alloc_prec_work(PrecWork<T> &w, const DHierarchy<T> &sdc, const DFlow<T> &fl, int n_nodes) {
-    w.arena.release();
-    alloc_hier_work(w.sdc, sdc, w.arena);
-    alloc_hier_work(w.pres, *fl.pres, w.arena);
-    size_t nfl = (size_t)fl.nc * fl.nf;
-    if (sizeof(T) == 4) w.vconv = w.arena.template alloc<T>((size_t)3 * n_nodes);
-    w.y = w.arena.template alloc<T>(nfl);
-    w.zs = w.arena.template alloc<T>((size_t)fl.nc * (fl.nf - 1));
-    w.wp = w.arena.template alloc<T>(fl.nc);
-    w.zp = w.arena.template alloc<T>(fl.nc);
-    w.w = w.arena.template alloc<T>(nfl);
-    w.t = w.arena.template alloc<T>(nfl);
-    w.dz = w.arena.template alloc<T>(nfl);
-    w.r2 = w.arena.template alloc<T>(nfl);
+    if (!w.fixed) {
+        alloc_hier_work(w.sdc, sdc, w.arena);
+        size_t nfl = (size_t)fl.nc * fl.nf;
+        if (sizeof(T) == 4) w.vconv = w.arena.template alloc<T>((size_t)3 * n_nodes);
+        w.y = w.arena.template alloc<T>(nfl);
+        w.zs = w.arena.template alloc<T>((size_t)fl.nc * (fl.nf - 1));
+        w.wp = w.arena.template alloc<T>(fl.nc);
+        w.zp = w.arena.template alloc<T>(fl.nc);
+        w.w = w.arena.template alloc<T>(nfl);
+        w.t = w.arena.template alloc<T>(nfl);
+        w.dz = w.arena.template alloc<T>(nfl);
+        w.r2 = w.arena.template alloc<T>(nfl);
+        w.fixed = true;
+    }
+    w.pres_arena.recycle();
+    alloc_hier_work(w.pres, *fl.pres, w.pres_arena);
 }
 
 // ------------------------------------------------------------------ V-cycle
@@ -717,8 +821,10 @@ template Sell<double> upload_sell<double>(Arena &, const HostSell &);
 template Sell<float> upload_sell<float>(Arena &, const HostSell &);
 template std::unique_ptr<DHierarchy<double>> upload_hierarchy<double>(const Hierarchy &, int, bool);
 template std::unique_ptr<DHierarchy<float>> upload_hierarchy<float>(const Hierarchy &, int, bool);
-template std::unique_ptr<DFlow<double>> upload_flow<double>(const FlowSetup &, const System &, const Options &);
-template std::unique_ptr<DFlow<float>> upload_flow<float>(const FlowSetup &, const System &, const Options &);
+template void update_flow<double>(DFlow<double> &, const FlowSetup &, const System &, const Options &, Staging &,
+                                  bool);
+template void update_flow<float>(DFlow<float> &, const FlowSetup &, const System &, const Options &, Staging &,
+                                 bool);
 template void alloc_prec_work<double>(PrecWork<double> &, const DHierarchy<double> &, const DFlow<double> &, int);
 template void alloc_prec_work<float>(PrecWork<float> &, const DHierarchy<float> &, const DFlow<float> &, int);
 template void apply_precond<double>(const DHierarchy<double> &, const DFlow<double> &, PrecWork<double> &, int,

@@ -60,6 +60,12 @@ void parallel_rows(int n, F &&f) {           // f(begin, end, part)
     for (auto &t : th) t.join();
 }
 
+}  // namespace
+
+void parallel_for(int n, const std::function<void(int, int, int)> &f) { parallel_rows(n, f); }
+int setup_thread_count() { return setup_threads(); }
+
+namespace {
 // Concatenate per-part CSR pieces (row ranges in order) into one matrix.
 struct CsrPart {
     std::vector<int> len, ci;

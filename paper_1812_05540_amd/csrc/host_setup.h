@@ -2,6 +2,7 @@
 #pragma once
 
 #include <cstdint>
+#include <functional>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -88,6 +89,10 @@ void block_jacobi_factor(const Bsr &S, Bsr &F);
 BiluSchedule bilu_schedule(const Bsr &S);
 BiluSchedule color_schedule(const Bsr &S);             // colour groups in fwd_ptr/fwd_rows
 void build_flow(const System &s, const Options &o, FlowSetup &f);
+
+// Run f(begin, end, part) over [0, n) split into contiguous parts on host threads.
+void parallel_for(int n, const std::function<void(int, int, int)> &f);
+int setup_thread_count();
 
 // --- small dense helpers ----------------------------------------------------
 bool invert_small(const double *a, double *inv, int n);  // Gauss-Jordan, partial pivoting
