@@ -110,6 +110,19 @@ def run_gpu(args, s, b):
                                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
                                    kernel="system SpMV y = A x (FP64 SELL-64, node rows + cell rows)",
                                    ms=round(t_ms, 4), algorithmic_bytes=nbytes)
+            # plain copy of known size (1 GiB read + 1 GiB written): the box's attainable
+            # stream bandwidth, and the calibration kernel for the HBM traffic counters
+            src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+            dst = torch.empty_like(src)
+            torch.mul(src, 1.0, out=dst)
+            start.record(stream)
+            for _ in range(5):
+                torch.mul(src, 1.0, out=dst)
+            end.record(stream)
+            end.synchronize()
+            t_copy = start.elapsed_time(end) / 5
+            out["roofline"]["copy_GBs"] = round(2 * src.numel() * 8 / (t_copy * 1e-3) / 1e9, 1)
+            del src, dst
         sv.close()
     if "fp32" in xs and "fp64" in xs:
         d = (xs["fp32"] - xs["fp64"]).norm() / xs["fp64"].norm()
@@ -154,10 +167,10 @@ def main():
     ap.add_argument("--precision", default="both", choices=["fp32", "fp64", "both"])
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--ml-sweeps", type=int, default=1)
-    ap.add_argument("--smoother", default="cheb2", choices=["cheb2", "l1jac"])
+    ap.add_argument("--smoother", default="l1jac", choices=["cheb2", "l1jac"])
     ap.add_argument("--ml-kind", default="bilu0", choices=["bilu0", "bjacobi", "mcgs"])
-    ap.add_argument("--ml-part", default="",
-                    help="processor-local local stage: subdomain box size in cells, e.g. 16,16,16")
+    ap.add_argument("--ml-part", default="32,32,16",
+                    help="processor-local local stage: subdomain box size in cells ('global': one domain)")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=30.0)
@@ -171,7 +184,7 @@ def main():
     from synth import workload
     t0 = time.perf_counter()
     s, b = workload(args.workload)
-    if args.ml_part:
+    if args.ml_part and args.ml_part != "global":
         from synth.jacobian import box_partition
         bx, by, bz = (int(v) for v in args.ml_part.split(","))
         s.ml_part = box_partition(*s.meta["grid"], bx, by, bz)
@@ -196,7 +209,7 @@ def main():
                                % (args.workload, *s.meta["grid"], s.N, args.rtol),
                    "precision": "fp32-preconditioner" if "fp32" in g else "fp64",
                    "ml_sweeps": args.ml_sweeps, "smoother": args.smoother, "ml_kind": args.ml_kind,
-                   "ml_part": args.ml_part or "global"},
+                   "ml_part": args.ml_part if args.ml_part else "global"},
         "paths": {k: v for k, v in g.items() if k in ("fp32", "fp64")},
         "roofline": g["roofline"],
     }

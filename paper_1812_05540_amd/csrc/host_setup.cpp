@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <atomic>
 #include <numeric>
 #include <thread>
 
@@ -58,6 +59,48 @@ void parallel_rows(int n, F &&f) {           // f(begin, end, part)
         th.emplace_back([&f, b, e, p] { f(b, e, p); });
     }
     for (auto &t : th) t.join();
+}
+
+// A team of host threads that runs f(tid, nthreads, team) once per thread; team.sync()
+// is a barrier (spins briefly, then yields).  Used for level-by-level work where the
+// levels are too small to pay for a thread launch each.
+class Team {
+    std::atomic<int> count_{0}, phase_{0};
+    int n_;
+
+public:
+    explicit Team(int n) : n_(n) {}
+    void sync() {
+        int ph = phase_.load(std::memory_order_acquire);
+        if (count_.fetch_add(1, std::memory_order_acq_rel) + 1 == n_) {
+            count_.store(0, std::memory_order_relaxed);
+            phase_.store(ph + 1, std::memory_order_release);
+            return;
+        }
+        for (int spin = 0; phase_.load(std::memory_order_acquire) == ph; ++spin)
+            if (spin > 256) std::this_thread::yield();
+    }
+    template <class F>
+    static void run(int n, F &&f) {
+        Team team(n);
+        if (n <= 1) {
+            f(0, 1, team);
+            return;
+        }
+        std::vector<std::thread> th;
+        for (int t = 1; t < n; ++t) th.emplace_back([&f, &team, t, n] { f(t, n, team); });
+        f(0, n, team);
+        for (auto &x : th) x.join();
+    }
+};
+
+// Copy a vector of trivially copyable values on the setup threads.
+template <class T>
+void parallel_copy(const std::vector<T> &src, std::vector<T> &dst) {
+    dst.resize(src.size());
+    parallel_rows((int)std::min<size_t>(src.size(), 1u << 30), [&](int b, int e, int) {
+        std::memcpy(dst.data() + b, src.data() + b, sizeof(T) * (size_t)(e - b));
+    });
 }
 
 }  // namespace
@@ -259,21 +302,36 @@ bool invert_dense(std::vector<double> a, std::vector<double> &inv, int n) {
 // ---------------------------------------------------------------- operators
 static std::vector<int> diag_positions(const Bsr &b) {
     std::vector<int> d(b.nbr, -1);
-    for (int i = 0; i < b.nbr; ++i)
-        for (int t = b.rp[i]; t < b.rp[i + 1]; ++t)
-            if (b.ci[t] == i) d[i] = t;
+    parallel_rows(b.nbr, [&](int lo, int hi, int) {
+        for (int i = lo; i < hi; ++i)
+            for (int t = b.rp[i]; t < b.rp[i + 1]; ++t)
+                if (b.ci[t] == i) d[i] = t;
+    });
     return d;
 }
 
-Bsr fixed_stress(const System &s) {
-    Bsr S = s.Aff;
+void fixed_stress(const System &s, Bsr &S) {
+    S.nbr = s.Aff.nbr;
+    S.nbc = s.Aff.nbc;
+    S.br = s.Aff.br;
+    S.bc = s.Aff.bc;
+    if (S.rp != s.Aff.rp) S.rp = s.Aff.rp;
+    if (S.ci != s.Aff.ci) S.ci = s.Aff.ci;
+    parallel_copy(s.Aff.v, S.v);
     int nf = s.nf, nn = nf * nf;
     std::vector<int> dpos = diag_positions(S);
-    for (int i = 0; i < s.n_cells; ++i) {
-        double *blk = &S.v[(size_t)dpos[i] * nn];
-        for (int l = 0; l < nf - 1; ++l) blk[l * nf + nf - 1] += s.d_sp[(size_t)i * (nf - 1) + l];
-        blk[(nf - 1) * nf + nf - 1] += s.d_pp[i];
-    }
+    parallel_rows(s.n_cells, [&](int b, int e, int) {
+        for (int i = b; i < e; ++i) {
+            double *blk = &S.v[(size_t)dpos[i] * nn];
+            for (int l = 0; l < nf - 1; ++l) blk[l * nf + nf - 1] += s.d_sp[(size_t)i * (nf - 1) + l];
+            blk[(nf - 1) * nf + nf - 1] += s.d_pp[i];
+        }
+    });
+}
+
+Bsr fixed_stress(const System &s) {
+    Bsr S;
+    fixed_stress(s, S);
     return S;
 }
 
@@ -282,41 +340,47 @@ void quasi_impes(const System &s, const Bsr &Sff, Csr &Spp, std::vector<double> 
     std::vector<int> dpos = diag_positions(s.Aff);
     std::vector<double> t((size_t)nc * m);
     dss_inv.assign((size_t)nc * m * m, 0.0);
-    for (int i = 0; i < nc; ++i) {
-        const double *blk = &s.Aff.v[(size_t)dpos[i] * nn];   // original A_ff: A_ss, A_ps unmodified
-        if (nf == 2) {
-            double dss = blk[0], dps = blk[nf * (nf - 1) + 0];
-            if (dss == 0.0) throw Error(PS_ESINGULAR, "zero D_ss entry");
-            t[i] = dps / dss;
-            dss_inv[i] = 1.0 / dss;
-        } else {
-            double a = blk[0 * nf + 0], b = blk[0 * nf + 1], c = blk[1 * nf + 0], d = blk[1 * nf + 1];
-            double det = a * d - b * c;
-            if (det == 0.0 || !std::isfinite(det)) throw Error(PS_ESINGULAR, "singular D_ss block");
-            double i00 = d / det, i01 = -b / det, i10 = -c / det, i11 = a / det;
-            double p0 = blk[(nf - 1) * nf + 0], p1 = blk[(nf - 1) * nf + 1];
-            t[(size_t)i * 2 + 0] = p0 * i00 + p1 * i10;
-            t[(size_t)i * 2 + 1] = p0 * i01 + p1 * i11;
-            double *o = &dss_inv[(size_t)i * 4];
-            o[0] = i00; o[1] = i01; o[2] = i10; o[3] = i11;
-        }
-    }
-    Spp.n = Spp.m = nc;
-    Spp.rp = Sff.rp;
-    Spp.ci = Sff.ci;
-    Spp.v.resize(Sff.ci.size());
-    for (int i = 0; i < nc; ++i)
-        for (int k = Sff.rp[i]; k < Sff.rp[i + 1]; ++k) {
-            const double *blk = &Sff.v[(size_t)k * nn];
-            double app = blk[(nf - 1) * nf + nf - 1];
+    std::atomic<int> singular{0};
+    parallel_rows(nc, [&](int lo, int hi, int) {
+        for (int i = lo; i < hi; ++i) {
+            const double *blk = &s.Aff.v[(size_t)dpos[i] * nn];   // original A_ff: A_ss, A_ps unmodified
             if (nf == 2) {
-                Spp.v[k] = app - t[i] * blk[0 * nf + nf - 1];
+                double dss = blk[0], dps = blk[nf * (nf - 1) + 0];
+                if (dss == 0.0) { singular = 1; continue; }
+                t[i] = dps / dss;
+                dss_inv[i] = 1.0 / dss;
             } else {
-                double s0 = t[(size_t)i * 2 + 0] * blk[0 * nf + nf - 1];
-                double s1 = t[(size_t)i * 2 + 1] * blk[1 * nf + nf - 1];
-                Spp.v[k] = app - (s0 + s1);
+                double a = blk[0 * nf + 0], b = blk[0 * nf + 1], c = blk[1 * nf + 0], d = blk[1 * nf + 1];
+                double det = a * d - b * c;
+                if (det == 0.0 || !std::isfinite(det)) { singular = 1; continue; }
+                double i00 = d / det, i01 = -b / det, i10 = -c / det, i11 = a / det;
+                double p0 = blk[(nf - 1) * nf + 0], p1 = blk[(nf - 1) * nf + 1];
+                t[(size_t)i * 2 + 0] = p0 * i00 + p1 * i10;
+                t[(size_t)i * 2 + 1] = p0 * i01 + p1 * i11;
+                double *o = &dss_inv[(size_t)i * 4];
+                o[0] = i00; o[1] = i01; o[2] = i10; o[3] = i11;
             }
         }
+    });
+    if (singular) throw Error(PS_ESINGULAR, nf == 2 ? "zero D_ss entry" : "singular D_ss block");
+    Spp.n = Spp.m = nc;
+    if (Spp.rp != Sff.rp) Spp.rp = Sff.rp;
+    if (Spp.ci != Sff.ci) Spp.ci = Sff.ci;
+    Spp.v.resize(Sff.ci.size());
+    parallel_rows(nc, [&](int lo, int hi, int) {
+        for (int i = lo; i < hi; ++i)
+            for (int k = Sff.rp[i]; k < Sff.rp[i + 1]; ++k) {
+                const double *blk = &Sff.v[(size_t)k * nn];
+                double app = blk[(nf - 1) * nf + nf - 1];
+                if (nf == 2) {
+                    Spp.v[k] = app - t[i] * blk[0 * nf + nf - 1];
+                } else {
+                    double s0 = t[(size_t)i * 2 + 0] * blk[0 * nf + nf - 1];
+                    double s1 = t[(size_t)i * 2 + 1] * blk[1 * nf + nf - 1];
+                    Spp.v[k] = app - (s0 + s1);
+                }
+            }
+    });
 }
 
 Csr sdc_matrix(const System &s) {
@@ -365,29 +429,39 @@ static std::vector<char> strength(const Csr &A, double theta) {
     return s;
 }
 
+static Csr transpose(const Csr &P);
+
 static std::vector<int8_t> pmis(const Csr &A, const std::vector<char> &smask) {
     const int n = A.n;
-    // S rows (i depends on j), S^T counts and lists
-    std::vector<int> srp(n + 1, 0), lam(n, 0);
-    for (int i = 0; i < n; ++i) {
-        int c = 0;
-        for (int t = A.rp[i]; t < A.rp[i + 1]; ++t)
-            if (smask[t]) { ++c; ++lam[A.ci[t]]; }
-        srp[i + 1] = srp[i] + c;
-    }
-    std::vector<int> sci(srp[n]);
-    for (int i = 0, k = 0; i < n; ++i)
-        for (int t = A.rp[i]; t < A.rp[i + 1]; ++t)
-            if (smask[t]) sci[k++] = A.ci[t];
-    std::vector<int> trp(n + 1, 0), tci(srp[n]);
-    for (int i = 0; i < n; ++i) trp[i + 1] = trp[i] + lam[i];
-    {
-        std::vector<int> fill(trp.begin(), trp.end() - 1);
-        for (int i = 0; i < n; ++i)
-            for (int k = srp[i]; k < srp[i + 1]; ++k) tci[fill[sci[k]]++] = i;
-    }
+    // S rows (i depends on j) and their transpose
+    Csr S;
+    S.n = S.m = n;
+    S.rp.assign(n + 1, 0);
+    parallel_rows(n, [&](int b, int e, int) {
+        for (int i = b; i < e; ++i) {
+            int c = 0;
+            for (int t = A.rp[i]; t < A.rp[i + 1]; ++t) c += smask[t] != 0;
+            S.rp[i + 1] = c;
+        }
+    });
+    for (int i = 0; i < n; ++i) S.rp[i + 1] += S.rp[i];
+    S.ci.resize(S.rp[n]);
+    S.v.assign(S.rp[n], 0.0);
+    parallel_rows(n, [&](int b, int e, int) {
+        for (int i = b; i < e; ++i)
+            for (int t = A.rp[i], k = S.rp[i]; t < A.rp[i + 1]; ++t)
+                if (smask[t]) S.ci[k++] = A.ci[t];
+    });
+    Csr T = transpose(S);
+    const std::vector<int> &srp = S.rp, &sci = S.ci, &trp = T.rp, &tci = T.ci;
+    std::vector<int> lam(n);
     std::vector<double> w(n);
-    for (int i = 0; i < n; ++i) w[i] = (double)lam[i] + unit_hash((uint64_t)i);
+    parallel_rows(n, [&](int b, int e, int) {
+        for (int i = b; i < e; ++i) {
+            lam[i] = trp[i + 1] - trp[i];
+            w[i] = (double)lam[i] + unit_hash((uint64_t)i);
+        }
+    });
     std::vector<int8_t> st(n, 0);
     size_t undecided = 0;
     for (int i = 0; i < n; ++i) {
@@ -400,26 +474,35 @@ static std::vector<int8_t> pmis(const Csr &A, const std::vector<char> &smask) {
     for (int i = 0; i < n; ++i)
         if (st[i] == 0) und.push_back(i);
     auto beats = [&](int j, int i) { return w[j] > w[i] || (w[j] == w[i] && j > i); };
+    // Each round reads the state at its start only, so rows are independent within
+    // a round and the result does not depend on the split.
     while (!und.empty()) {
-        for (int i : und) {
-            bool beaten = false;
-            for (int k = srp[i]; k < srp[i + 1] && !beaten; ++k) {
-                int j = sci[k];
-                if (st[j] == 0 && beats(j, i)) beaten = true;
+        const int nu = (int)und.size();
+        parallel_rows(nu, [&](int b, int e, int) {
+            for (int q = b; q < e; ++q) {
+                int i = und[q];
+                bool beaten = false;
+                for (int k = srp[i]; k < srp[i + 1] && !beaten; ++k) {
+                    int j = sci[k];
+                    if (st[j] == 0 && beats(j, i)) beaten = true;
+                }
+                for (int k = trp[i]; k < trp[i + 1] && !beaten; ++k) {
+                    int j = tci[k];
+                    if (st[j] == 0 && beats(j, i)) beaten = true;
+                }
+                newc[i] = !beaten;
             }
-            for (int k = trp[i]; k < trp[i + 1] && !beaten; ++k) {
-                int j = tci[k];
-                if (st[j] == 0 && beats(j, i)) beaten = true;
-            }
-            newc[i] = !beaten;
-        }
+        });
         for (int i : und)
             if (newc[i]) st[i] = 1;
-        for (int i : und) {
-            if (st[i] != 0) continue;
-            for (int k = srp[i]; k < srp[i + 1]; ++k)
-                if (newc[sci[k]]) { st[i] = -1; break; }
-        }
+        parallel_rows(nu, [&](int b, int e, int) {
+            for (int q = b; q < e; ++q) {
+                int i = und[q];
+                if (st[i] != 0) continue;
+                for (int k = srp[i]; k < srp[i + 1]; ++k)
+                    if (newc[sci[k]]) { st[i] = -1; break; }
+            }
+        });
         for (int i : und) newc[i] = 0;
         std::vector<int> next;
         next.reserve(und.size());
@@ -490,17 +573,50 @@ static Csr transpose(const Csr &P) {
     R.n = P.m;
     R.m = P.n;
     R.rp.assign(R.n + 1, 0);
-    for (int c : P.ci) ++R.rp[c + 1];
-    for (int i = 0; i < R.n; ++i) R.rp[i + 1] += R.rp[i];
     R.ci.resize(P.ci.size());
     R.v.resize(P.ci.size());
-    std::vector<int> fill(R.rp.begin(), R.rp.end() - 1);
-    for (int i = 0; i < P.n; ++i)
-        for (int t = P.rp[i]; t < P.rp[i + 1]; ++t) {
-            int k = fill[P.ci[t]]++;
-            R.ci[k] = i;
-            R.v[k] = P.v[t];
+    const int parts = std::min(setup_threads(), std::max(1, P.n / 8192));
+    // cnt[p][c]: entries of column c in row range p; prefix over (c, p) gives each
+    // part its write position, so rows stay in increasing order within each column
+    std::vector<std::vector<int>> cnt(parts, std::vector<int>(R.n, 0));
+    auto range = [&](int p, int &b, int &e) {
+        b = (int)((long long)P.n * p / parts);
+        e = (int)((long long)P.n * (p + 1) / parts);
+    };
+    std::vector<std::thread> th;
+    auto count = [&](int p) {
+        int b, e;
+        range(p, b, e);
+        for (int t = P.rp[b]; t < P.rp[e]; ++t) ++cnt[p][P.ci[t]];
+    };
+    for (int p = 1; p < parts; ++p) th.emplace_back(count, p);
+    count(0);
+    for (auto &x : th) x.join();
+    th.clear();
+    int off = 0;
+    for (int c = 0; c < R.n; ++c) {
+        R.rp[c] = off;
+        for (int p = 0; p < parts; ++p) {
+            int k = cnt[p][c];
+            cnt[p][c] = off;
+            off += k;
         }
+    }
+    R.rp[R.n] = off;
+    auto fill = [&](int p) {
+        int b, e;
+        range(p, b, e);
+        std::vector<int> &pos = cnt[p];
+        for (int i = b; i < e; ++i)
+            for (int t = P.rp[i]; t < P.rp[i + 1]; ++t) {
+                int k = pos[P.ci[t]]++;
+                R.ci[k] = i;
+                R.v[k] = P.v[t];
+            }
+    };
+    for (int p = 1; p < parts; ++p) th.emplace_back(fill, p);
+    fill(0);
+    for (auto &x : th) x.join();
     return R;
 }
 
@@ -552,16 +668,20 @@ static void smoother_setup(Level &L, int kind) {
     L.diag.assign(n, 0.0);
     L.dl1.assign(n, 0.0);
     std::vector<char> iso(n, 1);
-    for (int i = 0; i < n; ++i) {
-        double s = 0.0;
-        for (int t = A.rp[i]; t < A.rp[i + 1]; ++t) {
-            if (A.ci[t] == i) { L.diag[i] = A.v[t]; continue; }
-            s += std::fabs(A.v[t]);
-            if (A.v[t] != 0.0) iso[i] = 0;
+    std::atomic<int> zero{0};
+    parallel_rows(n, [&](int b, int e, int) {
+        for (int i = b; i < e; ++i) {
+            double s = 0.0;
+            for (int t = A.rp[i]; t < A.rp[i + 1]; ++t) {
+                if (A.ci[t] == i) { L.diag[i] = A.v[t]; continue; }
+                s += std::fabs(A.v[t]);
+                if (A.v[t] != 0.0) iso[i] = 0;
+            }
+            L.dl1[i] = L.diag[i] + s;
+            if (L.diag[i] == 0.0) zero = 1;
         }
-        L.dl1[i] = L.diag[i] + s;
-        if (L.diag[i] == 0.0) throw Error(PS_ESINGULAR, "zero diagonal in an AMG level");
-    }
+    });
+    if (zero) throw Error(PS_ESINGULAR, "zero diagonal in an AMG level");
     if (kind == PS_L1JAC) return;
     // power iteration for the largest eigenvalue of D^-1 A
     std::vector<double> v(n), wv(n);
@@ -658,33 +778,52 @@ static inline void mm(const double *a, const double *b, double *c, int n) {
         }
 }
 
+// IKJ block ILU(0) of F in place.  A row of one forward level depends only on rows of
+// earlier levels, so each level is factored by the whole thread team; the arithmetic
+// of every row is the same as in row-by-row order.
+void bilu0_factor_inplace(Bsr &F, const BiluSchedule &sc) {
+    const int n = F.nbr, nf = F.br, nn = nf * nf;
+    std::vector<int> dpos = diag_positions(F);
+    std::atomic<int> singular{0};
+    const int nt = std::min(setup_threads(), std::max(1, n / 4096));
+    Team::run(nt, [&](int tid, int nthr, Team &team) {
+        std::vector<int> pos(n, -1);
+        double tmp[9], prod[9];
+        for (size_t l = 0; l + 1 < sc.fwd_ptr.size(); ++l) {
+            const int lb = sc.fwd_ptr[l], le = sc.fwd_ptr[l + 1];
+            const int b = lb + (int)((long long)(le - lb) * tid / nthr);
+            const int e = lb + (int)((long long)(le - lb) * (tid + 1) / nthr);
+            for (int q = b; q < e; ++q) {
+                const int i = sc.fwd_rows[q];
+                for (int t = F.rp[i]; t < F.rp[i + 1]; ++t) pos[F.ci[t]] = t;
+                for (int t = F.rp[i]; t < F.rp[i + 1]; ++t) {
+                    int k = F.ci[t];
+                    if (k >= i) break;
+                    double *lik = &F.v[(size_t)t * nn];
+                    mm(lik, &F.v[(size_t)dpos[k] * nn], tmp, nf);       // L_ik = A_ik D_k^-1
+                    std::memcpy(lik, tmp, sizeof(double) * nn);
+                    for (int u = dpos[k] + 1; u < F.rp[k + 1]; ++u) {
+                        int qq = pos[F.ci[u]];
+                        if (qq < 0) continue;
+                        mm(lik, &F.v[(size_t)u * nn], prod, nf);          // A_ij -= L_ik U_kj
+                        double *aij = &F.v[(size_t)qq * nn];
+                        for (int x = 0; x < nn; ++x) aij[x] -= prod[x];
+                    }
+                }
+                double *dblk = &F.v[(size_t)dpos[i] * nn];
+                if (!invert_small(dblk, tmp, nf)) singular = 1;
+                else std::memcpy(dblk, tmp, sizeof(double) * nn);     // store D_i^-1
+                for (int t = F.rp[i]; t < F.rp[i + 1]; ++t) pos[F.ci[t]] = -1;
+            }
+            team.sync();
+        }
+    });
+    if (singular) throw Error(PS_ESINGULAR, "singular BILU(0) pivot block");
+}
+
 void bilu0_factor(const Bsr &S, Bsr &F) {
     F = S;
-    const int n = S.nbr, nf = S.br, nn = nf * nf;
-    std::vector<int> dpos = diag_positions(S);
-    std::vector<int> pos(n, -1);
-    double tmp[9], prod[9];
-    for (int i = 0; i < n; ++i) {
-        for (int t = F.rp[i]; t < F.rp[i + 1]; ++t) pos[F.ci[t]] = t;
-        for (int t = F.rp[i]; t < F.rp[i + 1]; ++t) {
-            int k = F.ci[t];
-            if (k >= i) break;
-            double *lik = &F.v[(size_t)t * nn];
-            mm(lik, &F.v[(size_t)dpos[k] * nn], tmp, nf);       // L_ik = A_ik D_k^-1
-            std::memcpy(lik, tmp, sizeof(double) * nn);
-            for (int u = dpos[k] + 1; u < F.rp[k + 1]; ++u) {
-                int q = pos[F.ci[u]];
-                if (q < 0) continue;
-                mm(lik, &F.v[(size_t)u * nn], prod, nf);          // A_ij -= L_ik U_kj
-                double *aij = &F.v[(size_t)q * nn];
-                for (int e = 0; e < nn; ++e) aij[e] -= prod[e];
-            }
-        }
-        double *dblk = &F.v[(size_t)dpos[i] * nn];
-        if (!invert_small(dblk, tmp, nf)) throw Error(PS_ESINGULAR, "singular BILU(0) pivot block");
-        std::memcpy(dblk, tmp, sizeof(double) * nn);              // store D_i^-1
-        for (int t = F.rp[i]; t < F.rp[i + 1]; ++t) pos[F.ci[t]] = -1;
-    }
+    bilu0_factor_inplace(F, bilu_schedule(S));
 }
 
 void block_jacobi_factor(const Bsr &S, Bsr &F) {
@@ -695,31 +834,51 @@ void block_jacobi_factor(const Bsr &S, Bsr &F) {
     F.rp.resize(n + 1);
     F.ci.resize(n);
     F.v.resize((size_t)n * nn);
-    for (int i = 0; i < n; ++i) {
-        F.rp[i] = i;
-        F.ci[i] = i;
-        if (!invert_small(&S.v[(size_t)dpos[i] * nn], &F.v[(size_t)i * nn], nf))
-            throw Error(PS_ESINGULAR, "singular diagonal cell block");
-    }
+    std::atomic<int> singular{0};
+    parallel_rows(n, [&](int b, int e, int) {
+        for (int i = b; i < e; ++i) {
+            F.rp[i] = i;
+            F.ci[i] = i;
+            if (!invert_small(&S.v[(size_t)dpos[i] * nn], &F.v[(size_t)i * nn], nf)) singular = 1;
+        }
+    });
+    if (singular) throw Error(PS_ESINGULAR, "singular diagonal cell block");
     F.rp[n] = n;
 }
 
-Bsr restrict_to_parts(const Bsr &S, const std::vector<int> &part) {
-    Bsr R;
+void restrict_to_parts(const Bsr &S, const std::vector<int> &part, Bsr &R) {
     R.nbr = S.nbr;
     R.nbc = S.nbc;
     R.br = S.br;
     R.bc = S.bc;
-    const int nn = S.br * S.bc;
+    const size_t nn = (size_t)S.br * S.bc;
     R.rp.assign(S.nbr + 1, 0);
-    for (int i = 0; i < S.nbr; ++i) {
-        for (int t = S.rp[i]; t < S.rp[i + 1]; ++t) {
-            if (part[S.ci[t]] != part[i]) continue;
-            R.ci.push_back(S.ci[t]);
-            R.v.insert(R.v.end(), S.v.begin() + (size_t)t * nn, S.v.begin() + (size_t)(t + 1) * nn);
+    parallel_rows(S.nbr, [&](int b, int e, int) {
+        for (int i = b; i < e; ++i) {
+            int c = 0;
+            for (int t = S.rp[i]; t < S.rp[i + 1]; ++t) c += part[S.ci[t]] == part[i];
+            R.rp[i + 1] = c;
         }
-        R.rp[i + 1] = (int)R.ci.size();
-    }
+    });
+    for (int i = 0; i < S.nbr; ++i) R.rp[i + 1] += R.rp[i];
+    R.ci.resize(R.rp[S.nbr]);
+    R.v.resize(R.ci.size() * nn);
+    parallel_rows(S.nbr, [&](int b, int e, int) {
+        for (int i = b; i < e; ++i) {
+            int o = R.rp[i];
+            for (int t = S.rp[i]; t < S.rp[i + 1]; ++t) {
+                if (part[S.ci[t]] != part[i]) continue;
+                R.ci[o] = S.ci[t];
+                std::memcpy(&R.v[(size_t)o * nn], &S.v[(size_t)t * nn], sizeof(double) * nn);
+                ++o;
+            }
+        }
+    });
+}
+
+Bsr restrict_to_parts(const Bsr &S, const std::vector<int> &part) {
+    Bsr R;
+    restrict_to_parts(S, part, R);
     return R;
 }
 
@@ -784,7 +943,7 @@ BiluSchedule color_schedule(const Bsr &S) {
 void build_flow(const System &s, const Options &o, FlowSetup &f) {
     {
         Tick t("fixed stress + qIMPES");
-        f.Sff = fixed_stress(s);
+        fixed_stress(s, f.Sff);
         quasi_impes(s, f.Sff, f.Spp, f.dss_inv);
     }
     {
@@ -792,16 +951,24 @@ void build_flow(const System &s, const Options &o, FlowSetup &f) {
         f.pres = amg_build(f.Spp, o);
     }
     Tick t("local stage factor");
-    if (o.ml_kind == PS_BILU0 && !s.ml_part.empty()) {
-        Bsr local = restrict_to_parts(f.Sff, s.ml_part);
-        bilu0_factor(local, f.ml);
-        f.sched = bilu_schedule(local);
-    } else if (o.ml_kind == PS_BILU0) {
-        bilu0_factor(f.Sff, f.ml);
-        f.sched = bilu_schedule(f.Sff);
+    if (o.ml_kind == PS_BILU0) {
+        if (!s.ml_part.empty()) {
+            restrict_to_parts(f.Sff, s.ml_part, f.ml);
+        } else {
+            f.ml.nbr = f.Sff.nbr;
+            f.ml.nbc = f.Sff.nbc;
+            f.ml.br = f.Sff.br;
+            f.ml.bc = f.Sff.bc;
+            if (f.ml.rp != f.Sff.rp) f.ml.rp = f.Sff.rp;
+            if (f.ml.ci != f.Sff.ci) f.ml.ci = f.Sff.ci;
+            parallel_copy(f.Sff.v, f.ml.v);
+        }
+        if (f.sched.fwd_ptr.empty()) f.sched = bilu_schedule(f.ml);    // pattern-only, kept across setups
+        Tick t2("BILU(0) factor");
+        bilu0_factor_inplace(f.ml, f.sched);
     } else if (o.ml_kind == PS_MCGS) {
         block_jacobi_factor(f.Sff, f.ml);
-        f.sched = color_schedule(f.Sff);
+        if (f.sched.fwd_ptr.empty()) f.sched = color_schedule(f.Sff);
     } else {
         block_jacobi_factor(f.Sff, f.ml);
         f.sched = BiluSchedule();

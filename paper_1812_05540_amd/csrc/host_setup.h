@@ -80,11 +80,14 @@ struct FlowSetup {                // recomputed at every ps_setup (Sec. 5.4)
 
 // --- setup steps ------------------------------------------------------------
 Bsr fixed_stress(const System &s);
+void fixed_stress(const System &s, Bsr &S);              // into S, reusing its storage
 void quasi_impes(const System &s, const Bsr &Sff, Csr &Spp, std::vector<double> &dss_inv);
 Csr sdc_matrix(const System &s);                         // component-major
 Hierarchy amg_build(const Csr &A, const Options &o);
 void bilu0_factor(const Bsr &S, Bsr &F);                 // throws Error(PS_ESINGULAR)
+void bilu0_factor_inplace(Bsr &F, const BiluSchedule &sc);  // sc: forward levels of F's pattern
 Bsr restrict_to_parts(const Bsr &S, const std::vector<int> &part);   // drop inter-part blocks
+void restrict_to_parts(const Bsr &S, const std::vector<int> &part, Bsr &R);
 void block_jacobi_factor(const Bsr &S, Bsr &F);
 BiluSchedule bilu_schedule(const Bsr &S);
 BiluSchedule color_schedule(const Bsr &S);             // colour groups in fwd_ptr/fwd_rows
