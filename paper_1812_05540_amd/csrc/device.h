@@ -149,6 +149,19 @@ struct HierWork {                 // per-handle vectors of one hierarchy
     std::vector<T *> b, e;        // right-hand side and result of level l >= 1
 };
 
+// Processor-local BILU(0) with each subdomain's vector resident in LDS (one workgroup per
+// subdomain; see the bilu_sub kernel for the layout).
+template <typename T>
+struct SubBilu {
+    int N = 0, nsub = 0, W = 0, bs = 0, lev_cap = 0;
+    size_t lds = 0;
+    T *ygl = nullptr;                     // vectors in HBM when a subdomain's does not fit in LDS
+    const int *sub_off = nullptr, *flev_off = nullptr, *blev_off = nullptr, *flev = nullptr, *blev = nullptr,
+              *bpos = nullptr, *ncell = nullptr, *npos = nullptr, *fcol = nullptr, *bcol = nullptr;
+    T *fval = nullptr, *bval = nullptr, *bdinv = nullptr;
+    std::vector<int> fsrc, bsrc, dsrc;    // value source blocks (host), -1 = padding
+};
+
 template <typename T>
 struct DFlow {                    // flow stage of Algorithm 1 on the device
     int nc = 0, nf = 0, ml_kind = PS_BILU0, ml_sweeps = 1;
@@ -162,6 +175,8 @@ struct DFlow {                    // flow stage of Algorithm 1 on the device
     const int *d_lchunk_f = nullptr, *d_lchunk_b = nullptr;
     T *dss_inv = nullptr;         // nc * (nf-1)^2
     T *dinv = nullptr;            // BILU D_i^{-1} or block-diagonal inverse, nc * nf * nf
+    bool sub = false;             // BILU applied by the subdomain-resident kernel
+    SubBilu<T> sb;
     std::unique_ptr<DHierarchy<T>> pres;
     Arena arena;                  // fixed-layout arrays
     size_t bytes() const { return arena.bytes() + (pres ? pres->bytes() : 0); }

@@ -288,6 +288,185 @@ static Sell<T> layout_sell(Arena &ar, const HostSell &h, T *&val, std::vector<in
     return s;
 }
 
+// Scatter block values into an ELL layout val[(s*rc + q)*N + r] (src[s*N + r]: source block).
+template <typename T>
+static void upload_ell(T *dev, const std::vector<int> &src, int W, int N, int rc, const std::vector<double> &v,
+                       Staging &stg) {
+    size_t n = (size_t)W * rc * N;
+    if (n == 0) return;
+    T *out = static_cast<T *>(stg.get(n * sizeof(T)));
+    parallel_for(N, [&](int b, int e, int) {
+        for (int s = 0; s < W; ++s)
+            for (int q = 0; q < rc; ++q)
+                for (int r = b; r < e; ++r) {
+                    int t = src[(size_t)s * N + r];
+                    out[((size_t)s * rc + q) * N + r] = t < 0 ? T(0) : (T)v[(size_t)t * rc + q];
+                }
+    });
+    PS_HIP(hipMemcpy(dev, out, n * sizeof(T), hipMemcpyHostToDevice));
+}
+
+static bool bilu_levels_forced() {
+    const char *e = std::getenv("PS_BILU_LAUNCH");
+    return e && (std::string(e) == "levels" || std::string(e) == "1wg");
+}
+
+// Layout of the subdomain-resident BILU(0) kernel, built once per handle from the
+// factor's pattern (restricted to subdomains) and its level schedule.  Returns false
+// (and the per-level kernels are used) when a subdomain's vector does not fit in LDS
+// or a row has more than 8 blocks on one side of the diagonal.
+template <typename T>
+static bool layout_sub_bilu(DFlow<T> &d, const FlowSetup &f, const System &s) {
+    if (s.ml_part.empty() || bilu_levels_forced()) return false;
+    const int N = s.n_cells, nf = s.nf;
+    const Bsr &F = f.ml;
+    const BiluSchedule &sc = f.sched;
+    // dense subdomain ids in increasing order of the caller's ids
+    std::vector<int> ids(s.ml_part.begin(), s.ml_part.end());
+    std::sort(ids.begin(), ids.end());
+    ids.erase(std::unique(ids.begin(), ids.end()), ids.end());
+    const int D = (int)ids.size();
+    std::vector<int> sid(N);
+    for (int i = 0; i < N; ++i) sid[i] = (int)(std::lower_bound(ids.begin(), ids.end(), s.ml_part[i]) - ids.begin());
+    std::vector<int> size(D, 0);
+    for (int i = 0; i < N; ++i) ++size[sid[i]];
+    int nmax = *std::max_element(size.begin(), size.end());
+    int dev = 0, lds_max = 0;
+    PS_HIP(hipGetDevice(&dev));
+    PS_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    // per-subdomain rows in level order, with level boundaries
+    auto group = [&](const std::vector<int> &ptr, const std::vector<int> &rows, std::vector<int> &order,
+                     std::vector<int> &lev, std::vector<int> &lev_off, int &maxw) {
+        std::vector<std::vector<int>> r(D), b(D);
+        std::vector<int> last(D, -1);
+        for (size_t l = 0; l + 1 < ptr.size(); ++l)
+            for (int q = ptr[l]; q < ptr[l + 1]; ++q) {
+                int i = rows[q], g = sid[i];
+                if (last[g] != (int)l) {
+                    b[g].push_back((int)r[g].size());
+                    last[g] = (int)l;
+                }
+                r[g].push_back(i);
+            }
+        order.clear();
+        lev.clear();
+        lev_off.assign(D + 1, 0);
+        maxw = 0;
+        for (int g = 0; g < D; ++g) {
+            int base = (int)order.size();
+            b[g].push_back((int)r[g].size());
+            for (size_t k = 0; k < b[g].size(); ++k) {
+                lev.push_back(base + b[g][k]);
+                if (k + 1 < b[g].size()) maxw = std::max(maxw, b[g][k + 1] - b[g][k]);
+            }
+            lev_off[g + 1] = (int)lev.size();
+            order.insert(order.end(), r[g].begin(), r[g].end());
+        }
+    };
+    std::vector<int> ford, flev, flev_off, bord, blev, blev_off;
+    int wf = 0, wb = 0;
+    group(sc.fwd_ptr, sc.fwd_rows, ford, flev, flev_off, wf);
+    group(sc.bwd_ptr, sc.bwd_rows, bord, blev, blev_off, wb);
+    std::vector<int> sub_off(D + 1, 0);
+    for (int g = 0; g < D; ++g) sub_off[g + 1] = sub_off[g] + size[g];
+    std::vector<int> lpos(N);
+    for (int r = 0; r < N; ++r) lpos[ford[r]] = r - sub_off[sid[ford[r]]];
+    int W = 0;
+    for (int i = 0; i < N; ++i) {
+        int lo = 0, hi = 0;
+        for (int t = F.rp[i]; t < F.rp[i + 1]; ++t) {
+            if (F.ci[t] < i) ++lo;
+            if (F.ci[t] > i) ++hi;
+        }
+        W = std::max(W, std::max(lo, hi));
+    }
+    if (W > 8) return false;
+    W = W <= 3 ? 3 : 8;        // 3: seven-point cell stencil
+    int lev_cap = 0;
+    for (int g = 0; g < D; ++g)
+        lev_cap = std::max(lev_cap, std::max(flev_off[g + 1] - flev_off[g], blev_off[g + 1] - blev_off[g]));
+    lev_cap = (lev_cap + 3) / 4 * 4;
+    size_t lds_lev = (size_t)2 * lev_cap * sizeof(int);
+    size_t lds_vec = (size_t)(nmax + 1) * nf * sizeof(T);        // + one dummy row
+    if (lds_lev > (size_t)lds_max / 2) return false;
+    const bool vec_in_lds = lds_lev + lds_vec <= (size_t)lds_max;
+    SubBilu<T> &b = d.sb;
+    b.N = N;
+    b.nsub = D;
+    b.W = W;
+    b.lev_cap = lev_cap;
+    b.lds = lds_lev + (vec_in_lds ? lds_vec : 0);
+    b.bs = std::min(512, std::max(256, (std::max(wf, wb) + 63) / 64 * 64));
+    std::vector<int> fcol((size_t)W * N, -1), bcol((size_t)W * N, -1), bpos(N), dsrc(N, -1);
+    b.fsrc.assign((size_t)W * N, -1);
+    b.bsrc.assign((size_t)W * N, -1);
+    for (int r = 0; r < N; ++r) {
+        int i = ford[r], k = 0;
+        for (int t = F.rp[i]; t < F.rp[i + 1] && F.ci[t] < i; ++t, ++k) {
+            fcol[(size_t)k * N + r] = lpos[F.ci[t]];
+            b.fsrc[(size_t)k * N + r] = t;
+        }
+        i = bord[r];
+        bpos[r] = lpos[i];
+        k = 0;
+        for (int t = F.rp[i]; t < F.rp[i + 1]; ++t) {
+            if (F.ci[t] == i) dsrc[r] = t;
+            if (F.ci[t] <= i) continue;
+            bcol[(size_t)k * N + r] = lpos[F.ci[t]];
+            b.bsrc[(size_t)k * N + r] = t;
+            ++k;
+        }
+    }
+    b.dsrc = dsrc;
+    std::vector<int> ncell(N), npos(N);
+    for (int g = 0; g < D; ++g) {
+        std::vector<int> cells(ford.begin() + sub_off[g], ford.begin() + sub_off[g + 1]);
+        std::sort(cells.begin(), cells.end());
+        for (int j = 0; j < size[g]; ++j) {
+            ncell[sub_off[g] + j] = cells[j];
+            npos[sub_off[g] + j] = lpos[cells[j]];
+        }
+    }
+    // every index the kernel forms must stay inside its subdomain and its arrays
+    auto check = [](bool ok, const char *what) {
+        if (!ok) throw Error(PS_EDEVICE, std::string("subdomain BILU layout: ") + what);
+    };
+    check((int)flev_off.size() == D + 1 && (int)blev_off.size() == D + 1, "offset arrays");
+    for (int g = 0; g < D; ++g) {
+        for (auto *lv : {&flev_off, &blev_off}) {
+            const std::vector<int> &lev = lv == &flev_off ? flev : blev;
+            int a = (*lv)[g], z = (*lv)[g + 1];
+            check(z > a && z <= (int)lev.size(), "level offsets");
+            check(lev[a] == sub_off[g] && lev[z - 1] == sub_off[g + 1], "level bounds");
+            for (int l = a; l + 1 < z; ++l) check(lev[l] < lev[l + 1], "empty level");
+        }
+        for (int r = sub_off[g]; r < sub_off[g + 1]; ++r) {
+            check(bpos[r] >= 0 && bpos[r] < size[g], "bpos");
+            check(ncell[r] >= 0 && ncell[r] < N && npos[r] >= 0 && npos[r] < size[g], "cell maps");
+            for (int k = 0; k < W; ++k) {
+                int fc = fcol[(size_t)k * N + r], bc = bcol[(size_t)k * N + r];
+                check(fc >= -1 && fc < size[g] && bc >= -1 && bc < size[g], "column positions");
+            }
+        }
+    }
+    Arena &ar = d.arena;
+    b.sub_off = ar.upload(sub_off.data(), sub_off.size());
+    b.flev_off = ar.upload(flev_off.data(), flev_off.size());
+    b.blev_off = ar.upload(blev_off.data(), blev_off.size());
+    b.flev = ar.upload(flev.data(), flev.size());
+    b.blev = ar.upload(blev.data(), blev.size());
+    b.bpos = ar.upload(bpos.data(), bpos.size());
+    b.ncell = ar.upload(ncell.data(), ncell.size());
+    b.npos = ar.upload(npos.data(), npos.size());
+    b.fcol = ar.upload(fcol.data(), fcol.size());
+    b.bcol = ar.upload(bcol.data(), bcol.size());
+    b.fval = ar.template alloc<T>((size_t)W * nf * nf * N);
+    b.bval = ar.template alloc<T>((size_t)W * nf * nf * N);
+    b.bdinv = ar.template alloc<T>((size_t)nf * nf * N);
+    b.ygl = vec_in_lds ? nullptr : ar.template alloc<T>((size_t)nf * (N + D));   // + one dummy row each
+    return true;
+}
+
 template <typename T>
 void update_flow(DFlow<T> &d, const FlowSetup &f, const System &s, const Options &o, Staging &stg,
                  bool afu_changed) {
@@ -312,7 +491,9 @@ void update_flow(DFlow<T> &d, const FlowSetup &f, const System &s, const Options
             }
             return ord;
         };
-        if (o.ml_kind == PS_BILU0) {
+        if (o.ml_kind == PS_BILU0 && layout_sub_bilu(d, f, s)) {
+            d.sub = true;
+        } else if (o.ml_kind == PS_BILU0) {
             std::vector<int> of = order(f.sched.fwd_ptr, f.sched.fwd_rows, d.lchunk_f);
             std::vector<int> ob = order(f.sched.bwd_ptr, f.sched.bwd_rows, d.lchunk_b);
             d.Lf = layout_sell<T>(d.arena, sell_from_bsr(f.ml.rp, f.ml.ci, none, nc, nf, nf, &of, keep_lower, false),
@@ -336,7 +517,13 @@ void update_flow(DFlow<T> &d, const FlowSetup &f, const System &s, const Options
     upload_values(d.sff_val, d.src_sff, nn, f.Sff.v, stg);
     upload_dense(d.dss_inv, f.dss_inv, stg);
     std::vector<double> dinv((size_t)nc * nn);
-    if (o.ml_kind == PS_BILU0) {
+    if (d.sub) {
+        const SubBilu<T> &b = d.sb;
+        upload_ell(b.fval, b.fsrc, b.W, nc, nn, f.ml.v, stg);
+        upload_ell(b.bval, b.bsrc, b.W, nc, nn, f.ml.v, stg);
+        upload_ell(b.bdinv, b.dsrc, 1, nc, nn, f.ml.v, stg);
+        dinv.clear();
+    } else if (o.ml_kind == PS_BILU0) {
         upload_values(d.lf_val, d.src_lf, nn, f.ml.v, stg);
         upload_values(d.ub_val, d.src_ub, nn, f.ml.v, stg);
         parallel_for(nc, [&](int b, int e, int) {
@@ -348,7 +535,7 @@ void update_flow(DFlow<T> &d, const FlowSetup &f, const System &s, const Options
         if (o.ml_kind == PS_MCGS) upload_values(d.lf_val, d.src_lf, nn, f.Sff.v, stg);
         dinv = f.ml.v;
     }
-    upload_dense(d.dinv, dinv, stg);
+    if (!dinv.empty()) upload_dense(d.dinv, dinv, stg);
     upload_hierarchy_into(*d.pres, f.pres, o.smoother, false);
 }
 
@@ -475,6 +662,31 @@ static bool bilu_one_workgroup() {
     return v;
 }
 
+template <int NF, int W, typename T, bool ACC, bool FINAL, bool GY>
+static void launch_sub_y(const SubBilu<T> &b, const T *src, PrecWork<T> &w, T *zf, hipStream_t st) {
+    auto kern = k::bilu_sub<NF, W, T, ACC, FINAL, GY>;
+    if (b.lds > 65536) {
+        static bool raised = false;          // per instantiation: allow the device's LDS maximum
+        if (!raised) {
+            int dev = 0, mx = 0;
+            PS_HIP(hipGetDevice(&dev));
+            PS_HIP(hipDeviceGetAttribute(&mx, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+            PS_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, mx));
+            raised = true;
+        }
+    }
+    k::SubLayout L{b.N, b.sub_off, b.flev_off, b.blev_off, b.flev, b.blev, b.bpos, b.ncell, b.npos, b.fcol, b.bcol};
+    hipLaunchKernelGGL(kern, dim3(b.nsub), dim3(b.bs), b.lds, st, L, (const T *)b.fval, (const T *)b.bval,
+                       (const T *)b.bdinv, src, w.dz, (const T *)w.zs, (const T *)w.zp, zf, b.ygl, b.lev_cap);
+}
+
+template <int NF, int W, typename T, bool ACC, bool FINAL>
+static void launch_sub(const SubBilu<T> &b, const T *src, PrecWork<T> &w, T *zf, hipStream_t st) {
+    if (b.ygl) launch_sub_y<NF, W, T, ACC, FINAL, true>(b, src, w, zf, st);
+    else launch_sub_y<NF, W, T, ACC, FINAL, false>(b, src, w, zf, st);
+}
+
 template <int NF, typename T>
 static void local_stage(const DFlow<T> &fl, PrecWork<T> &w, T *zf, hipStream_t st) {
     const int sweeps = fl.ml_sweeps;
@@ -518,6 +730,21 @@ static void local_stage(const DFlow<T> &fl, PrecWork<T> &w, T *zf, hipStream_t s
         if (s > 0) {
             LAUNCH((k::spmv<NF, NF, T, T, T, 1>), g, 0, st, fl.Sff, (const T *)w.dz, (const T *)w.w, w.r2);
             src = w.r2;
+        }
+        if (fl.sub) {
+            bool first = s == 0, final = s == sweeps - 1;
+            if (fl.sb.W == 3) {
+                if (first && final) launch_sub<NF, 3, T, false, true>(fl.sb, src, w, zf, st);
+                else if (first) launch_sub<NF, 3, T, false, false>(fl.sb, src, w, zf, st);
+                else if (final) launch_sub<NF, 3, T, true, true>(fl.sb, src, w, zf, st);
+                else launch_sub<NF, 3, T, true, false>(fl.sb, src, w, zf, st);
+            } else {
+                if (first && final) launch_sub<NF, 8, T, false, true>(fl.sb, src, w, zf, st);
+                else if (first) launch_sub<NF, 8, T, false, false>(fl.sb, src, w, zf, st);
+                else if (final) launch_sub<NF, 8, T, true, true>(fl.sb, src, w, zf, st);
+                else launch_sub<NF, 8, T, true, false>(fl.sb, src, w, zf, st);
+            }
+            continue;
         }
         if (one_wg) {
             bool final = s == sweeps - 1;

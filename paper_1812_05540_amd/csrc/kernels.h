@@ -596,6 +596,215 @@ __global__ __launch_bounds__(WG1) void bilu_bwd_1wg(Sell<T> U, const int *__rest
     }
 }
 
+// Processor-local BILU(0) sweep pair with the subdomain's vector resident in LDS: one
+// workgroup per subdomain runs the forward levels, then the backward levels, with a
+// barrier between levels and no HBM traffic for the vector in between.
+//
+// Layout (N = n_cells; rows of the forward order are grouped by subdomain and, inside
+// it, by forward level; p = the row's position inside its subdomain):
+//   fcol[s*N + r], fval[(s*NF*NF + q)*N + r]   strict-lower blocks of forward row r,
+//                                              slot s in increasing global column order,
+//                                              column given as a subdomain position (-1: pad)
+//   bpos[r], bcol/bval, bdinv[q*N + r]         the same for the backward order (bpos: the
+//                                              row's position), with D_i^{-1}
+//   flev/blev                                  level boundaries (row indices), per subdomain
+//                                              from flev[flev_off[d]] to flev[flev_off[d+1]]
+//   ncell[j], npos[j]                          the subdomain's cells in increasing index and
+//                                              their positions (for coalesced gathers/scatters)
+// Per row the arithmetic is that of bilu_fwd/bilu_bwd, in the same order.
+template <typename T, int NF, int W>
+struct SubRow {
+    int c[W];
+    T v[W][NF * NF];
+};
+
+// Loads are unconditional (row 0 stands in for rows past the level's end, whose
+// results are not used): a load whose result may be replaced on another path forces
+// the compiler to wait for it at once, which would serialise the prefetch.
+template <typename T, int NF, int W>
+__device__ __forceinline__ void sub_load(SubRow<T, NF, W> &d, const int *__restrict__ col,
+                                         const T *__restrict__ val, size_t N, int r, bool ok) {
+    const size_t rr = ok ? (size_t)r : 0;
+#pragma unroll
+    for (int s = 0; s < W; ++s) {
+        d.c[s] = col[(size_t)s * N + rr];
+#pragma unroll
+        for (int q = 0; q < NF * NF; ++q) d.v[s][q] = val[((size_t)s * NF * NF + q) * N + rr];
+    }
+}
+
+// acc = sum over the row's blocks of block * y[column]; padding slots (column -1) hold
+// zero blocks and read y[0].  Columns are clamped into the subdomain so that threads
+// past the level's end (which hold another row's data) read inside it too.
+template <typename T, int NF, int W>
+__device__ __forceinline__ void sub_acc(const SubRow<T, NF, W> &d, const T *y, int n, T *acc) {
+#pragma unroll
+    for (int r = 0; r < NF; ++r) acc[r] = T(0);
+#pragma unroll
+    for (int s = 0; s < W; ++s) {
+        const int c = min(max(d.c[s], 0), n - 1);
+        T xv[NF];
+#pragma unroll
+        for (int e = 0; e < NF; ++e) xv[e] = y[c * NF + e];
+#pragma unroll
+        for (int r = 0; r < NF; ++r)
+#pragma unroll
+            for (int e = 0; e < NF; ++e) acc[r] += d.v[s][r * NF + e] * xv[e];
+    }
+}
+
+struct SubLayout {
+    int N;
+    const int *sub_off, *flev_off, *blev_off, *flev, *blev, *bpos, *ncell, *npos;
+    const int *fcol, *bcol;
+};
+
+template <typename T, int NF, int W>
+struct SubRowB {
+    SubRow<T, NF, W> u;
+    T dv[NF * NF];
+    int p;
+};
+
+template <typename T, int NF, int W>
+__device__ __forceinline__ void sub_load_b(SubRowB<T, NF, W> &d, const SubLayout &L, const T *__restrict__ bval,
+                                           const T *__restrict__ bdinv, size_t N, int r, bool ok) {
+    sub_load(d.u, L.bcol, bval, N, r, ok);
+    const size_t rr = ok ? (size_t)r : 0;
+#pragma unroll
+    for (int q = 0; q < NF * NF; ++q) d.dv[q] = bdinv[(size_t)q * N + rr];
+    d.p = L.bpos[rr];
+}
+
+// LDS holds the subdomain's level boundaries and, unless GY (subdomains too large for
+// LDS), its vector; with GY, ygl + (off+d)*NF is the subdomain's slice in HBM, which
+// __syncthreads() makes visible across the workgroup as it does for LDS.
+template <int NF, int W, typename T, bool ACC, bool FINAL, bool GY>
+__global__ __launch_bounds__(512) void bilu_sub(SubLayout L, const T *__restrict__ fval,
+                                                const T *__restrict__ bval, const T *__restrict__ bdinv,
+                                                const T *__restrict__ win, T *__restrict__ dz,
+                                                const T *__restrict__ zs, const T *__restrict__ zp,
+                                                T *__restrict__ zout, T *__restrict__ ygl, int lev_cap) {
+    constexpr int M = NF - 1;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    int *lf = reinterpret_cast<int *>(lds_raw);
+    int *lb = lf + lev_cap;
+    const int d = blockIdx.x, tid = threadIdx.x, bs = blockDim.x;
+    const int off = L.sub_off[d], n = L.sub_off[d + 1] - off;
+    // y[n] is a dummy slot written by threads that have no row in a level, so that a
+    // level runs with no divergent branch (which would make the compiler wait for
+    // every load in flight)
+    // (GY is a template parameter so that the compiler sees which memory y is in and
+    // issues LDS instructions, not flat ones that would wait on every global load)
+    T *y;
+    if constexpr (GY) y = ygl + ((size_t)off + d) * NF;
+    else y = reinterpret_cast<T *>(lds_raw + (size_t)2 * lev_cap * sizeof(int));
+    const size_t N = (size_t)L.N;
+    const int fb = L.flev_off[d], nfl = L.flev_off[d + 1] - fb;     // nfl boundaries: nfl-1 levels
+    const int bb = L.blev_off[d], nbl = L.blev_off[d + 1] - bb;
+    for (int j = tid; j < nfl; j += bs) lf[j] = L.flev[fb + j];
+    for (int j = tid; j < nbl; j += bs) lb[j] = L.blev[bb + j];
+    for (int j = tid; j < n; j += bs) {
+        int c = L.ncell[off + j], p = L.npos[off + j];
+#pragma unroll
+        for (int e = 0; e < NF; ++e) y[p * NF + e] = win[(size_t)c * NF + e];
+    }
+    __syncthreads();
+    // forward: t_p = w_p - sum_k L_pk t_k, in place.  Three register buffers rotate
+    // without copies (the loop is unrolled by three), so a level's loads have two
+    // levels' time to arrive.
+    {
+        const int nl = nfl - 1;
+        SubRow<T, NF, W> c0, c1, c2;
+        auto load = [&](SubRow<T, NF, W> &x, int l) {
+            int r = l < nl ? lf[l] + tid : 0;
+            sub_load(x, L.fcol, fval, N, r, l < nl && r < lf[l + 1]);
+        };
+        auto step = [&](int l, const SubRow<T, NF, W> &cur, SubRow<T, NF, W> &ahead) {
+            const int r0 = lf[l], r1 = lf[l + 1];
+            load(ahead, l + 2);
+            {
+                T acc[NF];
+                sub_acc(cur, y, n, acc);
+                const int p = r0 + tid < r1 ? r0 + tid - off : n;
+#pragma unroll
+                for (int e = 0; e < NF; ++e) y[p * NF + e] = y[p * NF + e] - acc[e];
+            }
+            for (int rr = r0 + tid + bs; rr < r1; rr += bs) {
+                SubRow<T, NF, W> x;
+                sub_load(x, L.fcol, fval, N, rr, true);
+                T acc[NF];
+                sub_acc(x, y, n, acc);
+                const int p = rr - off;
+#pragma unroll
+                for (int e = 0; e < NF; ++e) y[p * NF + e] = y[p * NF + e] - acc[e];
+            }
+            __syncthreads();
+        };
+        load(c0, 0);
+        load(c1, 1);
+        for (int l = 0; l < nl; l += 3) {
+            step(l, c0, c2);
+            if (l + 1 < nl) step(l + 1, c1, c0);
+            if (l + 2 < nl) step(l + 2, c2, c1);
+        }
+    }
+    // backward: delta_p = D_p^{-1} (t_p - sum_j U_pj delta_j), in place
+    {
+        const int nl = nbl - 1;
+        SubRowB<T, NF, W> c0, c1, c2;
+        auto load = [&](SubRowB<T, NF, W> &x, int l) {
+            int r = l < nl ? lb[l] + tid : 0;
+            sub_load_b(x, L, bval, bdinv, N, r, l < nl && r < lb[l + 1]);
+        };
+        auto row = [&](const SubRowB<T, NF, W> &x, bool act) {
+            T acc[NF], rv[NF];
+            sub_acc(x.u, y, n, acc);
+            const int p = act ? x.p : n;
+#pragma unroll
+            for (int e = 0; e < NF; ++e) rv[e] = y[p * NF + e] - acc[e];
+#pragma unroll
+            for (int a2 = 0; a2 < NF; ++a2) {
+                T sm = T(0);
+#pragma unroll
+                for (int e = 0; e < NF; ++e) sm += x.dv[a2 * NF + e] * rv[e];
+                y[p * NF + a2] = sm;
+            }
+        };
+        auto step = [&](int l, const SubRowB<T, NF, W> &cur, SubRowB<T, NF, W> &ahead) {
+            const int r0 = lb[l], r1 = lb[l + 1];
+            load(ahead, l + 2);
+            row(cur, r0 + tid < r1);
+            for (int rr = r0 + tid + bs; rr < r1; rr += bs) {
+                SubRowB<T, NF, W> x;
+                sub_load_b(x, L, bval, bdinv, N, rr, true);
+                row(x, true);
+            }
+            __syncthreads();
+        };
+        load(c0, 0);
+        load(c1, 1);
+        for (int l = 0; l < nl; l += 3) {
+            step(l, c0, c2);
+            if (l + 1 < nl) step(l + 1, c1, c0);
+            if (l + 2 < nl) step(l + 2, c2, c1);
+        }
+    }
+    for (int j = tid; j < n; j += bs) {
+        int c = L.ncell[off + j], p = L.npos[off + j];
+#pragma unroll
+        for (int e = 0; e < NF; ++e) {
+            size_t o = (size_t)c * NF + e;
+            T v = ACC ? dz[o] + y[p * NF + e] : y[p * NF + e];
+            if (!FINAL) dz[o] = v;
+            if (FINAL) {
+                T zf = e < M ? zs[(size_t)c * M + e] : zp[c];
+                zout[o] = zf + v;
+            }
+        }
+    }
+}
+
 // Block-Jacobi sweep: delta = D^{-1}(w - S dz_in) (FIRST: D^{-1} w); dz_out = dz_in + delta;
 // FINAL: zout = [z_s; z_p] + dz_out.
 template <int NF, typename T, bool FIRST, bool FINAL>

@@ -204,6 +204,48 @@ def test_processor_local_bilu_matches_oracle(ctx):
     sv.close()
 
 
+SUB_CASES = {
+    "grf_boxes": (dict(grid=(12, 11, 10), kind="grf", seed=2, rhs_seed=102, sigma=1.0), (6, 6, 5), 1),
+    "grf_ragged_2sweeps": (dict(grid=(12, 11, 10), kind="grf", seed=4, rhs_seed=104, sigma=1.0), (5, 4, 3), 2),
+    "three_phase": (dict(grid=(7, 6, 5), kind="iid3", seed=3, rhs_seed=103), (4, 3, 5), 1),
+    "one_cell_parts": (dict(grid=(5, 4, 3), kind="iid", seed=6, rhs_seed=106), (1, 1, 1), 1),
+}
+
+
+@pytest.mark.parametrize("precision", [ps.PS_FP64, ps.PS_FP32_PREC])
+@pytest.mark.parametrize("case", list(SUB_CASES))
+def test_subdomain_bilu_kernel_matches_level_kernels(ctx, case, precision, monkeypatch):
+    """The LDS-resident subdomain kernel (default with ml_part) and the one-launch-per-
+    level kernels compute every row with the same operations in the same order."""
+    from synth.jacobian import box_partition
+    spec, box, sweeps = SUB_CASES[case]
+    s, b = workload(**spec)
+    s.ml_part = box_partition(*spec["grid"], *box)
+    v = dev(np.random.default_rng(7).standard_normal(s.N))
+    out = []
+    for mode in (None, "levels"):
+        if mode:
+            monkeypatch.setenv("PS_BILU_LAUNCH", mode)
+        else:
+            monkeypatch.delenv("PS_BILU_LAUNCH", raising=False)
+        sv = make_solver(ctx, s, precision=precision, ml_sweeps=sweeps)
+        z = dev(np.zeros(s.N))
+        sv.apply_precond(v, z)
+        x = dev(np.zeros(s.N))
+        r = sv.solve(dev(b), x, 1e-8)
+        out.append((host(z), r, host(x)))
+        sv.close()
+    monkeypatch.delenv("PS_BILU_LAUNCH", raising=False)
+    (za, ra, xa), (zb, rb, xb) = out
+    assert np.array_equal(za, zb)
+    assert ra["status"] == rb["status"] == ps.PS_OK and ra["iterations"] == rb["iterations"]
+    assert np.array_equal(xa, xb)
+    if precision == ps.PS_FP64:
+        st = P.setup(s, Options(ml_sweeps=sweeps))
+        ref = P.apply_precond(st, host(v))
+        assert np.linalg.norm(za - ref) / np.linalg.norm(ref) <= 1e-10
+
+
 def test_solves_are_deterministic(ctx):
     s, b = small("grf12")
     sv = make_solver(ctx, s)
