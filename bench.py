@@ -41,6 +41,35 @@ def spmv_bytes(s):
     return b + 2 * 8 * s.N
 
 
+def kernel_fingerprint(name):
+    """SHA-256 of a kernel template's source text in kernels.h (from its template line
+    to the next one): recorded with HBM counters so that they are reported only while
+    the kernel is unchanged."""
+    import hashlib
+    import re
+    text = open(os.path.join(ROOT, "paper_1812_05540_amd", "csrc", "kernels.h")).read()
+    m = re.search(r"\ntemplate <[^\n]*>\n__global__[^\n]*\bvoid %s\(" % name, text)
+    if not m:
+        return None
+    end = text.find("\ntemplate <", m.end())
+    return hashlib.sha256(text[m.start():end].encode()).hexdigest()[:16]
+
+
+def recorded_traffic(kernel, profile):
+    """HBM bytes per launch recorded in a profile summary, if its fingerprint matches."""
+    path = os.path.join(ROOT, "profiles", profile)
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "kernel_fingerprint"):
+            k, v = line.split(":", 1)
+            rec[k.strip()] = v.strip()
+    if rec.get("kernel_fingerprint") != kernel_fingerprint(kernel):
+        return None
+    return int(rec["traffic_bytes_per_launch"]) if "traffic_bytes_per_launch" in rec else None
+
+
 def run_gpu(args, s, b):
     import torch
     from paper_1812_05540_amd import ps
@@ -106,8 +135,9 @@ def run_gpu(args, s, b):
             t_ms = start.elapsed_time(end) / args.kernel_reps
             nbytes = spmv_bytes(s)
             achieved = nbytes / (t_ms * 1e-3) / 1e9
+            traffic = recorded_traffic("spmv2", "system_spmv_grf64_traffic.md") if args.workload == "grf64" else None
             out["roofline"] = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                                   frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                                   frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                                    kernel="system SpMV y = A x (FP64 SELL-64, node rows + cell rows)",
                                    ms=round(t_ms, 4), algorithmic_bytes=nbytes)
             # plain copy of known size (1 GiB read + 1 GiB written): the box's attainable

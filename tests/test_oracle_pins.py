@@ -527,3 +527,20 @@ def test_processor_local_bilu_reduces_to_known_cases():
         ref = np.linalg.solve(np.where(keep, S, 0.0), w)
         assert np.allclose(dz, ref, rtol=1e-10, atol=1e-12 * np.abs(ref).max()), expect
     s.ml_part = None
+
+
+def test_power_iteration_estimate_brute_force_and_bound():
+    """Chebyshev's eigenvalue estimate: ten normalised power steps on D^{-1} A from
+    v_0 = 1 + u equal |B^10 v_0| / |B^9 v_0| (B = D^{-1} A, dense brute force), and on
+    tridiag(-1, 2, -1) stay below the closed-form spectral radius 1 + cos(pi/(n+1))."""
+    n = 15
+    A = sp.diags([-np.ones(n - 1), 2 * np.ones(n), -np.ones(n - 1)], [-1, 0, 1], format="csr")
+    d = A.diagonal()
+    lam = amg.power_lambda(A, d)
+    B = np.diag(1.0 / d) @ A.toarray()
+    from oracle.rng import unit
+    v0 = 1.0 + unit(np.arange(n, dtype=np.uint64))
+    w9 = np.linalg.matrix_power(B, 9) @ v0
+    assert abs(lam - np.linalg.norm(B @ w9) / np.linalg.norm(w9)) <= 1e-13 * lam
+    rho = 1.0 + np.cos(np.pi / (n + 1))
+    assert lam <= rho * (1 + 1e-12) and lam > 0.5 * rho
