@@ -168,6 +168,16 @@ int  ps_wait(ps_ctx *ctx, uint64_t ticket, ps_result *res);
 /* Device bytes held by the handle (system matrix, hierarchy, Krylov space). */
 int  ps_footprint(ps_handle *h, size_t *bytes);
 
+/* Level `lvl` of the quasi-IMPES pressure AMG hierarchy built by the last ps_setup
+ * (Sec. 5.3, M_pp = amg(S_pp)); its coarse operators R (A P) are formed on the device
+ * (PS_GALERKIN=host in the environment: on host threads; the two agree bit for bit).
+ * Copies into caller buffers, NULL to skip: *nlevels, the level's operator (n x n,
+ * nnz entries, CSR with sorted columns: rowptr[n+1], colind[nnz], vals[nnz]) and its
+ * C/F splitting cf[n] (1 = C, -1 = F, 0 on the coarsest level).  For inspection and
+ * tests; PS_ENOTSETUP before the first ps_setup, PS_EINVAL for a level out of range. */
+int  ps_pressure_level(ps_handle *h, int lvl, int32_t *nlevels, int32_t *n, int32_t *nnz, int32_t *rowptr,
+                       int32_t *colind, double *vals, int8_t *cf);
+
 void ps_destroy(ps_handle *h);
 const char *ps_strerror(int status);
 /* Message of the last error raised on the calling thread ("" if none). */

@@ -22,6 +22,7 @@ SOURCES = [
     # its floating-point sums are reproducible in a fixed order
     ("host_setup.cpp", ["-x", "c++", "-ffp-contract=off"]),
     ("device.hip", HIP_FLAGS),
+    ("galerkin.hip", HIP_FLAGS),
     ("api.cpp", HIP_FLAGS),
 ]
 
@@ -41,7 +42,7 @@ def build(verbose=False):
         obj = os.path.join(OBJ, name + ".o")
         objs.append(obj)
         cmds.append([HIPCC] + COMMON + flags + ["-c", os.path.join(SRC, name), "-o", obj])
-    with ThreadPoolExecutor(max_workers=3) as ex:
+    with ThreadPoolExecutor(max_workers=4) as ex:
         for out in ex.map(_run, cmds):
             if verbose and out.strip():
                 print(out)

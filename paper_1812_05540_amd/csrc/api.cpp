@@ -7,6 +7,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <exception>
 #include <mutex>
 #include <thread>
 
@@ -105,6 +106,7 @@ struct ps_handle {
     std::unique_ptr<DFlow<double>> fl64;
     std::unique_ptr<DFlow<float>> fl32;
     Staging staging;
+    PresStore pstore;                 // device copies of the pressure hierarchy (device RAP)
     bool afu_changed = true;          // A_fu values changed since the last upload
     PrecWork<double> w64;
     PrecWork<float> w32;
@@ -121,7 +123,8 @@ struct ps_handle {
     size_t bytes() const {
         return dsys.arena.bytes() + (mech ? mech->bytes() : 0) + (fl64 ? fl64->bytes() : 0) +
                (fl32 ? fl32->bytes() : 0) + w64.arena.bytes() + w32.arena.bytes() +
-               (K ? K->arena.bytes() : 0) + aux.bytes();
+               (K ? K->arena.bytes() : 0) + aux.bytes() + pstore.arena.bytes() + pstore.work.bytes() +
+               pstore.tmp.bytes();
     }
 };
 
@@ -161,6 +164,13 @@ struct Request {
 };
 
 void set_device(int dev) { PS_HIP(hipSetDevice(dev)); }
+
+// Galerkin products of the pressure AMG on the device (default) or on host threads
+// (PS_GALERKIN=host); both give the same hierarchy bit for bit.
+bool galerkin_on_device() {
+    const char *e = std::getenv("PS_GALERKIN");
+    return !(e && std::string(e) == "host");
+}
 
 bool use_fp32(const ps_handle *h) { return h->opt.precision == PS_FP32_PREC; }
 
@@ -319,19 +329,48 @@ int ps_setup(ps_handle *h) {
             PhaseTimer pt("mechanics (if not built)");
             ensure_mech_device(h, f64, f32);
         }
+        const bool dev_rap = galerkin_on_device();
         {
-            PhaseTimer pt("flow setup (host)");
-            build_flow(h->sys, h->opt, h->flow);
+            PhaseTimer pt("flow setup");
+            build_flow_operators(h->sys, h->flow);
+            if (dev_rap) {
+                // local-stage factors on a host thread while the pressure hierarchy is built
+                // (host coarsening, device Galerkin products)
+                std::exception_ptr err;
+                std::thread local([&] {
+                    try {
+                        build_flow_local(h->sys, h->opt, h->flow);
+                    } catch (...) {
+                        err = std::current_exception();
+                    }
+                });
+                try {
+                    PhaseTimer pt2("pressure AMG (device RAP)");
+                    build_pressure(h->flow.Spp, h->opt, h->flow.pres, h->pstore);
+                } catch (...) {
+                    local.join();
+                    throw;
+                }
+                local.join();
+                if (err) std::rethrow_exception(err);
+            } else {
+                {
+                    PhaseTimer pt2("pressure AMG (host)");
+                    h->flow.pres = amg_build(h->flow.Spp, h->opt);
+                }
+                build_flow_local(h->sys, h->opt, h->flow);
+            }
         }
+        const PresStore *ps = dev_rap ? &h->pstore : nullptr;
         PhaseTimer pt("flow upload + work");
         if (f64) {
             if (!h->fl64) h->fl64 = std::make_unique<DFlow<double>>();
-            update_flow<double>(*h->fl64, h->flow, h->sys, h->opt, h->staging, h->afu_changed);
+            update_flow<double>(*h->fl64, h->flow, h->sys, h->opt, h->staging, h->afu_changed, ps);
             alloc_prec_work(h->w64, *h->mech->d64, *h->fl64, h->sys.n_nodes);
         }
         if (f32) {
             if (!h->fl32) h->fl32 = std::make_unique<DFlow<float>>();
-            update_flow<float>(*h->fl32, h->flow, h->sys, h->opt, h->staging, h->afu_changed);
+            update_flow<float>(*h->fl32, h->flow, h->sys, h->opt, h->staging, h->afu_changed, ps);
             alloc_prec_work(h->w32, *h->mech->d32, *h->fl32, h->sys.n_nodes);
         }
         h->afu_changed = false;
@@ -499,6 +538,25 @@ int ps_poll(ps_ctx *c, uint64_t ticket, ps_result *res) {
     return guard([&] {
         if (!c) throw Error(PS_EINVAL, "ctx is NULL");
         return take_result(c, ticket, res, false);
+    });
+}
+
+int ps_pressure_level(ps_handle *h, int lvl, int32_t *nlevels, int32_t *n, int32_t *nnz, int32_t *rowptr,
+                      int32_t *colind, double *vals, int8_t *cf) {
+    return guard([&] {
+        if (!h) throw Error(PS_EINVAL, "handle is NULL");
+        if (!h->ready) throw Error(PS_ENOTSETUP, "ps_setup has not run");
+        const Hierarchy &H = h->flow.pres;
+        if (nlevels) *nlevels = (int32_t)H.lev.size();
+        if (lvl < 0 || lvl >= (int)H.lev.size()) throw Error(PS_EINVAL, "level out of range");
+        const Level &L = H.lev[lvl];
+        if (n) *n = L.A.n;
+        if (nnz) *nnz = L.A.nnz();
+        if (rowptr) std::memcpy(rowptr, L.A.rp.data(), L.A.rp.size() * sizeof(int32_t));
+        if (colind) std::memcpy(colind, L.A.ci.data(), L.A.ci.size() * sizeof(int32_t));
+        if (vals) std::memcpy(vals, L.A.v.data(), L.A.v.size() * sizeof(double));
+        if (cf) std::memcpy(cf, L.cf.data(), L.cf.size());
+        return PS_OK;
     });
 }
 

@@ -59,6 +59,10 @@ class Arena {
         if (n) PS_HIP(hipMemcpy(d, h, n * sizeof(T), hipMemcpyHostToDevice));
         return d;
     }
+    void trim() {                                  // free the blocks not reused since recycle()
+        for (auto &b : free_) (void)hipFree(b.p);
+        free_.clear();
+    }
     void recycle() {
         free_.insert(free_.end(), used_.begin(), used_.end());
         used_.clear();
@@ -118,6 +122,25 @@ Sell<T> upload_sell(Arena &ar, const HostSell &h);
 // ---- preconditioner device data ------------------------------------------------
 // Scalar CSR on the device, processed by groups of G lanes per row (G a power of
 // two chosen from the mean row length when uploaded).
+// FP64 CSR in device memory (the Galerkin builder's matrices).
+struct DevCsr {
+    int n = 0, m = 0, nnz = 0;
+    int *rp = nullptr, *ci = nullptr;
+    double *v = nullptr;
+};
+
+// C = A B on the device, bitwise equal to the host product (galerkin.hip).
+void spgemm_device(const DevCsr &A, const DevCsr &B, DevCsr &C, Arena &out, Arena &tmp, hipStream_t st);
+
+// Pressure hierarchy whose Galerkin products are formed on the device: host levels in H
+// (operators copied back for the next coarsening and for inspection), FP64 device copies of
+// every A_l, P_l, R_l here, shared by the FP64 and FP32 preconditioners.
+struct PresStore {
+    Arena arena, work, tmp;
+    std::vector<DevCsr> A, P, R;
+};
+void build_pressure(const Csr &Spp, const Options &o, Hierarchy &H, PresStore &S);
+
 template <typename T>
 struct DCsr {
     int n = 0, G = 1;
@@ -228,9 +251,10 @@ template <typename T>
 std::unique_ptr<DHierarchy<T>> upload_hierarchy(const Hierarchy &H, int smoother, bool interleave3);
 template <typename T>
 void upload_hierarchy_into(DHierarchy<T> &d, const Hierarchy &H, int smoother, bool interleave3);
+// ps: device copies of the pressure hierarchy (adopted, not uploaded), or nullptr.
 template <typename T>
 void update_flow(DFlow<T> &d, const FlowSetup &f, const System &s, const Options &o, Staging &stg,
-                 bool afu_changed);
+                 bool afu_changed, const PresStore *ps);
 void upload_system(const System &s, DSystem &d);
 template <typename T>
 void alloc_prec_work(PrecWork<T> &w, const DHierarchy<T> &sdc, const DFlow<T> &fl, int n_nodes);

@@ -467,9 +467,61 @@ static bool layout_sub_bilu(DFlow<T> &d, const FlowSetup &f, const System &s) {
     return true;
 }
 
+// A level matrix of the device-built pressure hierarchy as a kernel operand: index arrays
+// shared, values shared (FP64) or converted (FP32).
+template <typename T>
+static DCsr<T> adopt_csr(Arena &ar, const DevCsr &c) {
+    DCsr<T> d;
+    d.n = c.n;
+    double avg = c.n ? (double)c.nnz / c.n : 1.0;
+    int G = 1;
+    while (G < 32 && G * 3 < avg) G *= 2;
+    d.G = G;
+    d.rp = c.rp;
+    d.ci = c.ci;
+    if constexpr (sizeof(T) == 8) {
+        d.v = c.v;
+    } else {
+        T *v = ar.template alloc<T>(c.nnz);
+        LAUNCH((k::convert<double, T>), grid_for((size_t)c.nnz), 0, 0, c.v, v, (size_t)c.nnz);
+        d.v = v;
+    }
+    return d;
+}
+
+template <typename T>
+static void adopt_hierarchy(DHierarchy<T> &d, const Hierarchy &H, const PresStore &S, int smoother) {
+    d.arena.recycle();
+    d.smoother = smoother;
+    const int nl = (int)H.lev.size();
+    if ((int)S.A.size() != nl || (int)S.P.size() != nl - 1) throw Error(PS_EDEVICE, "pressure hierarchy mismatch");
+    d.lev.assign(nl, DLevel<T>());
+    for (int l = 0; l + 1 < nl; ++l) {
+        const Level &L = H.lev[l];
+        DLevel<T> &D = d.lev[l];
+        D.n = L.A.n;
+        D.A = adopt_csr<T>(d.arena, S.A[l]);
+        D.P = adopt_csr<T>(d.arena, S.P[l]);
+        D.R = adopt_csr<T>(d.arena, S.R[l]);
+        if (smoother == PS_L1JAC) {
+            std::vector<double> inv(L.dl1.size());
+            for (size_t i = 0; i < L.dl1.size(); ++i) inv[i] = 1.0 / L.dl1[i];
+            D.dinv = upload_vec<T>(d.arena, inv);
+        } else {
+            D.c0 = upload_vec<T>(d.arena, L.c0);
+            D.c1 = upload_vec<T>(d.arena, L.c1);
+            D.cm = upload_vec<T>(d.arena, L.cm);
+        }
+    }
+    d.lev[nl - 1].n = H.coarse_n;
+    d.cn = H.coarse_n;
+    d.cinv = d.arena.upload(H.coarse_inv.data(), H.coarse_inv.size());
+    PS_HIP(hipStreamSynchronize(0));
+}
+
 template <typename T>
 void update_flow(DFlow<T> &d, const FlowSetup &f, const System &s, const Options &o, Staging &stg,
-                 bool afu_changed) {
+                 bool afu_changed, const PresStore *ps) {
     const int nf = s.nf, nc = s.n_cells, nn = nf * nf;
     static const std::vector<double> none;
     if (!d.layout) {
@@ -536,7 +588,8 @@ void update_flow(DFlow<T> &d, const FlowSetup &f, const System &s, const Options
         dinv = f.ml.v;
     }
     if (!dinv.empty()) upload_dense(d.dinv, dinv, stg);
-    upload_hierarchy_into(*d.pres, f.pres, o.smoother, false);
+    if (ps) adopt_hierarchy(*d.pres, f.pres, *ps, o.smoother);
+    else upload_hierarchy_into(*d.pres, f.pres, o.smoother, false);
 }
 
 void upload_system(const System &s, DSystem &d) {
@@ -934,17 +987,21 @@ void Fgmres::enqueue_iteration() {
     launch_mdot(K_, K_.V, nv, w, true, st_);
     LAUNCH(k::reduce_rows, nv + 1, 0, st_, (const double *)K_.partial, K_.nblk, K_.h1, (const double *)nullptr,
            (double *)nullptr);
-    LAUNCH((k::gemv_sub<false>), K_.nblk, 0, st_, (const double *)K_.V, N, nv, (const double *)K_.h1, w, N,
-           K_.chunk, K_.partial);
-    launch_mdot(K_, K_.V, nv, w, false, st_);
+    if (nv >= 22 && nv <= k::SUBDOT_MAXV) {          // below ~22 vectors two passes are faster
+        LAUNCH(k::gemv_sub_mdot, K_.nblk, (size_t)nv * 65 * sizeof(double), st_, (const double *)K_.V, N, nv,
+               (const double *)K_.h1, w, N, K_.chunk, K_.partial, K_.nblk);
+    } else {
+        LAUNCH((k::gemv_sub<false>), K_.nblk, 0, st_, (const double *)K_.V, N, nv, (const double *)K_.h1, w, N,
+               K_.chunk, K_.partial);
+        launch_mdot(K_, K_.V, nv, w, false, st_);
+    }
     LAUNCH(k::reduce_rows, nv, 0, st_, (const double *)K_.partial, K_.nblk, K_.h2, (const double *)K_.h1, K_.hsum);
     LAUNCH((k::gemv_sub<true>), K_.nblk, 0, st_, (const double *)K_.V, N, nv, (const double *)K_.h2, w, N,
            K_.chunk, K_.partial);
     LAUNCH(k::reduce_rows, 1, 0, st_, (const double *)K_.partial, K_.nblk, K_.nw2, (const double *)nullptr,
            (double *)nullptr);
     LAUNCH(k::givens, 1, 0, st_, j, m, (const double *)K_.hsum, (const double *)(K_.h1 + nv),
-           (const double *)K_.nw2, K_.H, K_.cs, K_.sn, K_.g, K_.scal);
-    copy_scal();
+           (const double *)K_.nw2, K_.H, K_.cs, K_.sn, K_.g, K_.scal, K_.hostscal);
     phase_ = ITER;
 }
 
@@ -1049,9 +1106,9 @@ template Sell<float> upload_sell<float>(Arena &, const HostSell &);
 template std::unique_ptr<DHierarchy<double>> upload_hierarchy<double>(const Hierarchy &, int, bool);
 template std::unique_ptr<DHierarchy<float>> upload_hierarchy<float>(const Hierarchy &, int, bool);
 template void update_flow<double>(DFlow<double> &, const FlowSetup &, const System &, const Options &, Staging &,
-                                  bool);
+                                  bool, const PresStore *);
 template void update_flow<float>(DFlow<float> &, const FlowSetup &, const System &, const Options &, Staging &,
-                                 bool);
+                                 bool, const PresStore *);
 template void alloc_prec_work<double>(PrecWork<double> &, const DHierarchy<double> &, const DFlow<double> &, int);
 template void alloc_prec_work<float>(PrecWork<float> &, const DHierarchy<float> &, const DFlow<float> &, int);
 template void apply_precond<double>(const DHierarchy<double> &, const DFlow<double> &, PrecWork<double> &, int,

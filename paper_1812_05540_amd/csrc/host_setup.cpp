@@ -724,37 +724,30 @@ static void smoother_setup(Level &L, int kind) {
     }
 }
 
-Hierarchy amg_build(const Csr &A0, const Options &o) {
-    Hierarchy H;
-    Csr A = A0;
-    while (A.n > o.coarse_max && (int)H.lev.size() + 1 < o.max_levels) {
-        std::vector<char> smask;
-        std::vector<int8_t> cf;
-        {
-            Tick t("strength + PMIS");
-            smask = strength(A, o.theta);
-            cf = pmis(A, smask);
-        }
-        int nc = 0;
-        for (int8_t c : cf) nc += (c == 1);
-        if (nc == 0 || (double)nc > 0.9 * (double)A.n) break;
-        Level L;
-        Csr Ac;
-        {
-            Tick t("interpolation + RAP");
-            L.P = direct_interpolation(A, smask, cf, nc);
-            L.R = transpose(L.P);
-            Ac = spgemm(L.R, spgemm(A, L.P));
-        }
-        L.cf = std::move(cf);
-        L.A = std::move(A);
-        {
-            Tick t("smoother setup");
-            smoother_setup(L, o.smoother);
-        }
-        H.lev.push_back(std::move(L));
-        A = std::move(Ac);
+bool coarsen_level(const Csr &A, const Options &o, Level &L) {
+    std::vector<char> smask;
+    {
+        Tick t("strength + PMIS");
+        smask = strength(A, o.theta);
+        L.cf = pmis(A, smask);
     }
+    int nc = 0;
+    for (int8_t c : L.cf) nc += (c == 1);
+    if (nc == 0 || (double)nc > 0.9 * (double)A.n) return false;
+    Tick t("interpolation");
+    L.P = direct_interpolation(A, smask, L.cf, nc);
+    L.R = transpose(L.P);
+    return true;
+}
+
+Csr galerkin(const Level &L, const Csr &A) { return spgemm(L.R, spgemm(A, L.P)); }
+
+void finish_level(Level &L, int smoother) {
+    Tick t("smoother setup");
+    smoother_setup(L, smoother);
+}
+
+void coarse_level(Csr A, Hierarchy &H) {
     if (A.n > 6000) throw Error(PS_ESINGULAR, "AMG coarsening stagnated above the dense-solve limit");
     Level C;
     C.cf.assign(A.n, 0);
@@ -765,6 +758,25 @@ Hierarchy amg_build(const Csr &A0, const Options &o) {
     H.coarse_n = A.n;
     C.A = std::move(A);
     H.lev.push_back(std::move(C));
+}
+
+Hierarchy amg_build(const Csr &A0, const Options &o) {
+    Hierarchy H;
+    Csr A = A0;
+    while (A.n > o.coarse_max && (int)H.lev.size() + 1 < o.max_levels) {
+        Level L;
+        if (!coarsen_level(A, o, L)) break;
+        Csr Ac;
+        {
+            Tick t("Galerkin RAP (host)");
+            Ac = galerkin(L, A);
+        }
+        L.A = std::move(A);
+        finish_level(L, o.smoother);
+        H.lev.push_back(std::move(L));
+        A = std::move(Ac);
+    }
+    coarse_level(std::move(A), H);
     return H;
 }
 
@@ -940,16 +952,13 @@ BiluSchedule color_schedule(const Bsr &S) {
     return sc;
 }
 
-void build_flow(const System &s, const Options &o, FlowSetup &f) {
-    {
-        Tick t("fixed stress + qIMPES");
-        fixed_stress(s, f.Sff);
-        quasi_impes(s, f.Sff, f.Spp, f.dss_inv);
-    }
-    {
-        Tick t("pressure AMG");
-        f.pres = amg_build(f.Spp, o);
-    }
+void build_flow_operators(const System &s, FlowSetup &f) {
+    Tick t("fixed stress + qIMPES");
+    fixed_stress(s, f.Sff);
+    quasi_impes(s, f.Sff, f.Spp, f.dss_inv);
+}
+
+void build_flow_local(const System &s, const Options &o, FlowSetup &f) {
     Tick t("local stage factor");
     if (o.ml_kind == PS_BILU0) {
         if (!s.ml_part.empty()) {
@@ -973,6 +982,15 @@ void build_flow(const System &s, const Options &o, FlowSetup &f) {
         block_jacobi_factor(f.Sff, f.ml);
         f.sched = BiluSchedule();
     }
+}
+
+void build_flow(const System &s, const Options &o, FlowSetup &f) {
+    build_flow_operators(s, f);
+    {
+        Tick t("pressure AMG");
+        f.pres = amg_build(f.Spp, o);
+    }
+    build_flow_local(s, o, f);
 }
 
 }  // namespace ps

@@ -84,6 +84,11 @@ void fixed_stress(const System &s, Bsr &S);              // into S, reusing its 
 void quasi_impes(const System &s, const Bsr &Sff, Csr &Spp, std::vector<double> &dss_inv);
 Csr sdc_matrix(const System &s);                         // component-major
 Hierarchy amg_build(const Csr &A, const Options &o);
+// The steps of amg_build, for builders that form the Galerkin product elsewhere:
+bool coarsen_level(const Csr &A, const Options &o, Level &L);  // cf, P, R; false: stop coarsening
+Csr galerkin(const Level &L, const Csr &A);                   // R (A P), exact zeros dropped
+void finish_level(Level &L, int smoother);                    // smoother data of L (L.A set)
+void coarse_level(Csr A, Hierarchy &H);                       // dense inverse of the last level
 void bilu0_factor(const Bsr &S, Bsr &F);                 // throws Error(PS_ESINGULAR)
 void bilu0_factor_inplace(Bsr &F, const BiluSchedule &sc);  // sc: forward levels of F's pattern
 Bsr restrict_to_parts(const Bsr &S, const std::vector<int> &part);   // drop inter-part blocks
@@ -92,6 +97,8 @@ void block_jacobi_factor(const Bsr &S, Bsr &F);
 BiluSchedule bilu_schedule(const Bsr &S);
 BiluSchedule color_schedule(const Bsr &S);             // colour groups in fwd_ptr/fwd_rows
 void build_flow(const System &s, const Options &o, FlowSetup &f);
+void build_flow_operators(const System &s, FlowSetup &f);            // S_ff^(fs), S_pp, D_ss^{-1}
+void build_flow_local(const System &s, const Options &o, FlowSetup &f);  // local-stage factors
 
 // Run f(begin, end, part) over [0, n) split into contiguous parts on host threads.
 void parallel_for(int n, const std::function<void(int, int, int)> &f);

@@ -933,8 +933,15 @@ template <bool NORM, bool LDSW>
 __global__ __launch_bounds__(WG) void mdot(const double *__restrict__ V, size_t ldv, int nv,
                                           const double *__restrict__ w, size_t n, int chunk,
                                           double *__restrict__ partial, int nblk) {
+    // Eight vectors per pass over the chunk, three elements per thread per step: the 24
+    // loads of a step are issued before any of them is used (a wave needs many bytes in
+    // flight to stream at full bandwidth).  The |w|^2 term rides along in the first pass;
+    // each wave's sums go to LDS without a barrier and the four waves are combined once
+    // at the end in a fixed order.  Per thread, elements are accumulated in increasing
+    // index order.
+    constexpr int U = 3;
     extern __shared__ double sw[];
-    __shared__ double red[4 * 4];
+    __shared__ double red[4][MAXV + 1];
     size_t i0 = (size_t)blockIdx.x * chunk;
     int len = i0 < n ? (int)((n - i0) < (size_t)chunk ? (n - i0) : (size_t)chunk) : 0;
     const double *wb = w + i0;
@@ -943,40 +950,55 @@ __global__ __launch_bounds__(WG) void mdot(const double *__restrict__ V, size_t 
         __syncthreads();
     }
     const double *ws = LDSW ? sw : wb;
-    int ntot = nv + (NORM ? 1 : 0);
-    for (int k0 = 0; k0 < ntot; k0 += 4) {
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        const double *v0 = k0 + 0 < nv ? V + (size_t)(k0 + 0) * ldv + i0 : ws;
-        const double *v1 = k0 + 1 < nv ? V + (size_t)(k0 + 1) * ldv + i0 : ws;
-        const double *v2 = k0 + 2 < nv ? V + (size_t)(k0 + 2) * ldv + i0 : ws;
-        const double *v3 = k0 + 3 < nv ? V + (size_t)(k0 + 3) * ldv + i0 : ws;
-        int kk = ntot - k0;
-        for (int t = threadIdx.x; t < len; t += WG) {
-            double wt = ws[t];
-            a0 += v0[t] * wt;
-            if (kk > 1) a1 += v1[t] * wt;
-            if (kk > 2) a2 += v2[t] * wt;
-            if (kk > 3) a3 += v3[t] * wt;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int npass = nv > 0 ? (nv + 7) / 8 : (NORM ? 1 : 0);
+    for (int p = 0; p < npass; ++p) {
+        const int k0 = 8 * p, kk = nv - k0 < 8 ? nv - k0 : 8;
+        const bool wnorm = NORM && p == 0;
+        // rows past nv re-read row k0 (in bounds, unused): every load is unconditional
+        const double *v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = kk > 0 ? V + (size_t)(q < kk ? k0 + q : k0) * ldv + i0 : ws;
+        double a[8], an = 0.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) a[q] = 0.0;
+        for (int t0 = threadIdx.x; t0 < len; t0 += U * WG) {
+            double x[U][8], wt[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int t = t0 + u * WG, tc = t < len ? t : len - 1;
+                wt[u] = ws[tc];
+                if (kk > 0) {
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) x[u][q] = v[q][tc];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (t0 + u * WG < len) {
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+                        if (q < kk) a[q] += x[u][q] * wt[u];
+                    if (wnorm) an += wt[u] * wt[u];
+                }
+            }
         }
-        a0 = wave_sum(a0);
-        a1 = wave_sum(a1);
-        a2 = wave_sum(a2);
-        a3 = wave_sum(a3);
-        int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-        if (lane == 0) {
-            red[wid * 4 + 0] = a0;
-            red[wid * 4 + 1] = a1;
-            red[wid * 4 + 2] = a2;
-            red[wid * 4 + 3] = a3;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            if (q < kk) {
+                const double r = wave_sum(a[q]);
+                if (lane == 0) red[wid][k0 + q] = r;
+            }
         }
-        __syncthreads();
-        if (threadIdx.x < 4 && threadIdx.x < kk) {
-            int q = threadIdx.x;
-            double s = ((red[0 * 4 + q] + red[1 * 4 + q]) + red[2 * 4 + q]) + red[3 * 4 + q];
-            partial[(size_t)(k0 + q) * nblk + blockIdx.x] = s;
+        if (wnorm) {
+            const double r = wave_sum(an);
+            if (lane == 0) red[wid][nv] = r;
         }
-        __syncthreads();
     }
+    __syncthreads();
+    const int ntot = nv + (NORM ? 1 : 0);
+    for (int k = threadIdx.x; k < ntot; k += WG)
+        partial[(size_t)k * nblk + blockIdx.x] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
 }
 
 // out[k] = sum_b partial[k * nblk + b] (fixed order); if add: sum_out[k] = add[k] + out[k].
@@ -1020,38 +1042,124 @@ __global__ __launch_bounds__(WG) void gemv_sub(const double *__restrict__ V, siz
     }
 }
 
+// The middle of CGS2 in one pass over V: w -= V h (stored), then partial[k * nblk + blk] =
+// V_k . w over this block's chunk, for k < nv.  The chunk goes through LDS in tiles of
+// 64 elements x nv vectors (row stride 65 doubles), so each element of V is read from
+// HBM once for both products.  Dynamic LDS: nv * 65 doubles.
+constexpr int SUBDOT_MAXV = 112;    // 112 x 65 doubles + static arrays < 64 KB of LDS
+__global__ __launch_bounds__(WG) void gemv_sub_mdot(const double *__restrict__ V, size_t ldv, int nv,
+                                                   const double *__restrict__ h, double *__restrict__ w,
+                                                   size_t n, int chunk, double *__restrict__ partial,
+                                                   int nblk) {
+    extern __shared__ double tile[];
+    __shared__ double hs[SUBDOT_MAXV];
+    __shared__ double part[4][64];
+    __shared__ double wn[64];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    for (int t = tid; t < nv; t += WG) hs[t] = h[t];
+    const size_t i0 = (size_t)blockIdx.x * chunk;
+    const int len = i0 < n ? (int)((n - i0) < (size_t)chunk ? (n - i0) : (size_t)chunk) : 0;
+    double acc = 0.0;
+    __syncthreads();
+    for (int e0 = 0; e0 < len; e0 += 64) {
+        const int ne = len - e0 < 64 ? len - e0 : 64;
+        // 16 rows per wave per batch, loaded before any is stored (loads in flight);
+        // indices clamped so that every load is in bounds and unconditional
+        const int el = lane < ne ? lane : ne - 1;
+        for (int kb = wid; kb < nv; kb += 64) {
+            double r[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int k = kb + 4 * q < nv ? kb + 4 * q : nv - 1;
+                r[q] = V[(size_t)k * ldv + i0 + e0 + el];
+            }
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int k = kb + 4 * q;
+                if (k < nv) tile[k * 65 + lane] = lane < ne ? r[q] : 0.0;
+            }
+        }
+        __syncthreads();
+        double s = 0.0;
+        for (int k = wid; k < nv; k += 4) s += tile[k * 65 + lane] * hs[k];
+        part[wid][lane] = s;
+        __syncthreads();
+        if (wid == 0) {
+            double wv = 0.0;
+            if (lane < ne) {
+                const size_t i = i0 + e0 + lane;
+                wv = w[i] - (((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]);
+                w[i] = wv;
+            }
+            wn[lane] = wv;
+        }
+        __syncthreads();
+        if (tid < nv) {
+            double d = 0.0;
+#pragma unroll 8
+            for (int e = 0; e < 64; ++e) d += tile[tid * 65 + e] * wn[e];
+            acc += d;
+        }
+        __syncthreads();
+    }
+    if (tid < nv) partial[(size_t)tid * nblk + blockIdx.x] = acc;
+}
+
 // Givens update of Hessenberg column j (column-major, leading dimension m+1).
 // h: j+1 orthogonalisation coefficients; nrm[0] = |A z_j|^2, nrm[1] = |w|^2.
 // scal out: [0] |g_{j+1}|, [1] h_{j+1,j}, [2] |A z_j|, [3] breakdown flag.
-__global__ void givens(int j, int m, const double *__restrict__ h, const double *__restrict__ naz2,
-                       const double *__restrict__ nw2, double *__restrict__ H, double *__restrict__ cs,
-                       double *__restrict__ sn, double *__restrict__ g, double *__restrict__ scal) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double *col = H + (size_t)j * (m + 1);
-    double hn = sqrt(nw2[0]);
-    for (int i = 0; i <= j; ++i) col[i] = h[i];
-    col[j + 1] = hn;
-    for (int i = 0; i < j; ++i) {
-        double t = cs[i] * col[i] + sn[i] * col[i + 1];
-        col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
-        col[i] = t;
+__global__ __launch_bounds__(WG) void givens(int j, int m, const double *__restrict__ h,
+                                            const double *__restrict__ naz2, const double *__restrict__ nw2,
+                                            double *__restrict__ H, double *__restrict__ cs,
+                                            double *__restrict__ sn, double *__restrict__ g,
+                                            double *__restrict__ scal, double *__restrict__ hscal) {
+    // the column and the previous rotations are staged in LDS by the workgroup; one thread
+    // applies the rotations in order (a dependent chain), the workgroup writes back
+    __shared__ double col[MAXV + 1], c[MAXV], s[MAXV];
+    __shared__ double out[4];
+    const int tid = threadIdx.x;
+    for (int i = tid; i <= j; i += WG) {
+        col[i] = h[i];
+        if (i < j) {
+            c[i] = cs[i];
+            s[i] = sn[i];
+        }
     }
-    double rho = hypot(col[j], col[j + 1]);
-    scal[1] = hn;
-    scal[2] = sqrt(naz2[0]);
-    if (rho == 0.0) {
-        scal[0] = fabs(g[j]);
-        scal[3] = 1.0;
-        return;
+    __syncthreads();
+    if (tid == 0) {
+        const double hn = sqrt(nw2[0]);
+        col[j + 1] = hn;
+        for (int i = 0; i < j; ++i) {
+            double t = c[i] * col[i] + s[i] * col[i + 1];
+            col[i + 1] = -s[i] * col[i] + c[i] * col[i + 1];
+            col[i] = t;
+        }
+        const double rho = hypot(col[j], col[j + 1]);
+        out[1] = hn;
+        out[2] = sqrt(naz2[0]);
+        if (rho == 0.0) {
+            out[0] = fabs(g[j]);
+            out[3] = 1.0;
+        } else {
+            const double cj = col[j] / rho, sj = col[j + 1] / rho;
+            cs[j] = cj;
+            sn[j] = sj;
+            col[j] = rho;
+            col[j + 1] = 0.0;
+            const double gj = g[j];
+            g[j + 1] = -sj * gj;
+            g[j] = cj * gj;
+            out[0] = fabs(-sj * gj);
+            out[3] = 0.0;
+        }
     }
-    cs[j] = col[j] / rho;
-    sn[j] = col[j + 1] / rho;
-    col[j] = rho;
-    col[j + 1] = 0.0;
-    g[j + 1] = -sn[j] * g[j];
-    g[j] = cs[j] * g[j];
-    scal[0] = fabs(g[j + 1]);
-    scal[3] = 0.0;
+    __syncthreads();
+    double *hc = H + (size_t)j * (m + 1);
+    for (int i = tid; i <= j + 1; i += WG) hc[i] = col[i];
+    if (tid < 4) {
+        scal[tid] = out[tid];
+        if (hscal) hscal[tid] = out[tid];     // pinned host copy: no separate transfer
+    }
 }
 
 // Start of a cycle: g = beta e_1 with beta = sqrt(nr2[0]).

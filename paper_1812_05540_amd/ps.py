@@ -65,6 +65,9 @@ _SIGS = {
     "ps_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(ps_result)]),
     "ps_wait": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(ps_result)]),
     "ps_footprint": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
+    "ps_pressure_level": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_double), C.POINTER(C.c_int8)]),
     "ps_destroy": (None, [C.c_void_p]),
     "ps_strerror": (C.c_char_p, [C.c_int]),
     "ps_last_error": (C.c_char_p, []),
@@ -249,6 +252,22 @@ def ps_wait(ctx, ticket):
     return d
 
 
+def ps_pressure_level(h, lvl):
+    """Level lvl of the handle's pressure hierarchy: dict(nlevels, n, rowptr, colind, vals, cf)."""
+    lib = load()
+    nl, n, nnz = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(lib.ps_pressure_level(h, lvl, C.byref(nl), C.byref(n), C.byref(nnz), None, None, None, None),
+           "ps_pressure_level")
+    rp = np.zeros(n.value + 1, np.int32)
+    ci = np.zeros(nnz.value, np.int32)
+    v = np.zeros(nnz.value, np.float64)
+    cf = np.zeros(n.value, np.int8)
+    _check(lib.ps_pressure_level(h, lvl, None, None, None, rp.ctypes.data_as(_i32p), ci.ctypes.data_as(_i32p),
+                                 v.ctypes.data_as(_f64p), cf.ctypes.data_as(C.POINTER(C.c_int8))),
+           "ps_pressure_level")
+    return dict(nlevels=nl.value, n=n.value, rowptr=rp, colind=ci, vals=v, cf=cf)
+
+
 def ps_footprint(h):
     b = C.c_size_t()
     _check(load().ps_footprint(h, C.byref(b)), "ps_footprint")
@@ -364,6 +383,9 @@ class Solver:
 
     def footprint(self):
         return ps_footprint(self.h)
+
+    def pressure_level(self, lvl):
+        return ps_pressure_level(self.h, lvl)
 
     def close(self):
         if self.h:
