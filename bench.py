@@ -70,6 +70,32 @@ def recorded_traffic(kernel, profile):
     return int(rec["traffic_bytes_per_launch"]) if "traffic_bytes_per_launch" in rec else None
 
 
+# instrumented kernel -> (kernel template in kernels.h, HBM-counter summary under profiles/)
+KERNEL_SOURCES = {
+    "system_spmv": ("spmv2", "system_spmv_grf64_traffic.md"),
+    "cgs2_project": ("mdot", "cgs2_project_grf64_traffic.md"),
+    "cgs2_subtract_project": ("gemv_sub_mdot", "cgs2_fused_grf64_traffic.md"),
+    "cgs2_subtract_norm": ("gemv_sub", "cgs2_subtract_grf64_traffic.md"),
+    "bilu_subdomain": ("bilu_sub", "bilu_subdomain_grf64_traffic.md"),
+}
+
+
+def dominant_roofline(kernels, workload):
+    """Roofline line of the instrumented kernel with the most event time in the timed
+    region: algorithmic bytes per launch / mean launch duration, against HBM peak."""
+    name, k = max(((n, v) for n, v in kernels.items() if v["launches"]), key=lambda kv: kv[1]["seconds"])
+    per_launch_s = k["seconds"] / k["launches"]
+    per_launch_b = k["bytes"] / k["launches"]
+    achieved = per_launch_b / per_launch_s / 1e9
+    src, prof = KERNEL_SOURCES.get(name, (None, None))
+    traffic = recorded_traffic(src, prof) if src and workload == "grf64" else None
+    return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, kernel=name,
+                launches=k["launches"], us_per_launch=round(per_launch_s * 1e6, 2),
+                algorithmic_bytes_per_launch=int(per_launch_b),
+                share_of_instrumented_time=round(k["seconds"] / sum(v["seconds"] for v in kernels.values()), 3))
+
+
 def run_gpu(args, s, b):
     import torch
     from paper_1812_05540_amd import ps
@@ -99,6 +125,8 @@ def run_gpu(args, s, b):
         t_setup = t_solve = 0.0
         its = []
         res = None
+        if name == precs[0][0]:
+            ps.ps_kernel_timing(True)         # HIP events around the hot kernels, on their streams
         t_all = time.perf_counter()
         for _ in range(args.steps):
             t0 = time.perf_counter()
@@ -113,6 +141,9 @@ def run_gpu(args, s, b):
             its.append(res["iterations"])
         torch.cuda.synchronize()
         total = time.perf_counter() - t_all
+        if name == precs[0][0]:
+            out["kernels"] = ps.ps_kernel_stats()
+            ps.ps_kernel_timing(False)
         xs[name] = x.clone()
         out[name] = dict(status=res["status"], iterations=its[-1], rel_residual=res["rel_residual"],
                          restarts=res["restarts"], ms_per_step=1e3 * total / args.steps,
@@ -135,11 +166,10 @@ def run_gpu(args, s, b):
             t_ms = start.elapsed_time(end) / args.kernel_reps
             nbytes = spmv_bytes(s)
             achieved = nbytes / (t_ms * 1e-3) / 1e9
-            traffic = recorded_traffic("spmv2", "system_spmv_grf64_traffic.md") if args.workload == "grf64" else None
-            out["roofline"] = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                                   frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                                   kernel="system SpMV y = A x (FP64 SELL-64, node rows + cell rows)",
-                                   ms=round(t_ms, 4), algorithmic_bytes=nbytes)
+            out["spmv"] = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                               frac=round(achieved / HBM_PEAK_GBS, 4),
+                               kernel="system SpMV y = A x (FP64 SELL-64, node rows + cell rows)",
+                               ms=round(t_ms, 4), algorithmic_bytes=nbytes)
             # plain copy of known size (1 GiB read + 1 GiB written): the box's attainable
             # stream bandwidth, and the calibration kernel for the HBM traffic counters
             src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
@@ -151,7 +181,7 @@ def run_gpu(args, s, b):
             end.record(stream)
             end.synchronize()
             t_copy = start.elapsed_time(end) / 5
-            out["roofline"]["copy_GBs"] = round(2 * src.numel() * 8 / (t_copy * 1e-3) / 1e9, 1)
+            out["spmv"]["copy_GBs"] = round(2 * src.numel() * 8 / (t_copy * 1e-3) / 1e9, 1)
             del src, dst
         sv.close()
     if "fp32" in xs and "fp64" in xs:
@@ -373,7 +403,11 @@ def main():
                    "ml_sweeps": args.ml_sweeps, "smoother": args.smoother, "ml_kind": args.ml_kind,
                    "ml_part": args.ml_part if args.ml_part else "global"},
         "paths": {k: v for k, v in g.items() if k in ("fp32", "fp64")},
-        "roofline": g["roofline"],
+        "roofline": dominant_roofline(g["kernels"], args.workload),
+        "kernels": {n: dict(launches=v["launches"], us_per_launch=round(1e6 * v["seconds"] / v["launches"], 2),
+                            GBs=round(v["bytes"] / v["seconds"] / 1e9, 1))
+                    for n, v in g["kernels"].items() if v["launches"]},
+        "spmv": g["spmv"],
     }
     if "fp64" in g and "fp32" in g:
         line["fp32_over_fp64_speedup"] = round(g["fp32"]["solves_per_s"] / g["fp64"]["solves_per_s"], 3)

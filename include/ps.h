@@ -168,6 +168,17 @@ int  ps_wait(ps_ctx *ctx, uint64_t ticket, ps_result *res);
 /* Device bytes held by the handle (system matrix, hierarchy, Krylov space). */
 int  ps_footprint(ps_handle *h, size_t *bytes);
 
+/* Instrumentation.  ps_kernel_timing(1) clears the totals and starts bracketing the
+ * hot kernels -- the system SpMV (both block-row kernels), the three CGS2 passes over the
+ * Krylov basis, the subdomain BILU(0) sweeps -- with HIP events recorded on the stream
+ * each runs on, adding each launch's algorithmic bytes (values, indices and vectors the
+ * kernel must move, not what the caches do); 0 stops.  Process-wide. */
+int  ps_kernel_timing(int enable);
+/* Totals of instrumented kernel idx = 0, 1, ... (PS_EINVAL past the last): its name
+ * (NUL-terminated, truncated to len bytes), launches, event seconds and algorithmic
+ * bytes.  Waits for the events still pending. */
+int  ps_kernel_stats(int idx, char *name, size_t len, int64_t *launches, double *seconds, double *bytes);
+
 /* Level `lvl` of the quasi-IMPES pressure AMG hierarchy built by the last ps_setup
  * (Sec. 5.3, M_pp = amg(S_pp)); its coarse operators R (A P) are formed on the device
  * (PS_GALERKIN=host in the environment: on host threads; the two agree bit for bit).

@@ -541,6 +541,30 @@ int ps_poll(ps_ctx *c, uint64_t ticket, ps_result *res) {
     });
 }
 
+int ps_kernel_timing(int enable) {
+    return guard([&] {
+        ktime::set_enabled(enable != 0);
+        return PS_OK;
+    });
+}
+
+int ps_kernel_stats(int idx, char *name, size_t len, int64_t *launches, double *seconds, double *bytes) {
+    return guard([&] {
+        if (idx < 0 || idx >= ktime::NUM) throw Error(PS_EINVAL, "kernel index out of range");
+        long long l = 0;
+        double sec = 0.0, b = 0.0;
+        ktime::totals(idx, l, sec, b);
+        if (name && len) {
+            std::strncpy(name, ktime::name(idx), len - 1);
+            name[len - 1] = 0;
+        }
+        if (launches) *launches = l;
+        if (seconds) *seconds = sec;
+        if (bytes) *bytes = b;
+        return PS_OK;
+    });
+}
+
 int ps_pressure_level(ps_handle *h, int lvl, int32_t *nlevels, int32_t *n, int32_t *nnz, int32_t *rowptr,
                       int32_t *colind, double *vals, int8_t *cf) {
     return guard([&] {

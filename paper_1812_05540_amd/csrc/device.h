@@ -177,6 +177,7 @@ struct HierWork {                 // per-handle vectors of one hierarchy
 template <typename T>
 struct SubBilu {
     int N = 0, nsub = 0, W = 0, bs = 0, lev_cap = 0;
+    double bytes = 0.0;                   // algorithmic bytes of one application
     size_t lds = 0;
     T *ygl = nullptr;                     // vectors in HBM when a subdomain's does not fit in LDS
     const int *sub_off = nullptr, *flev_off = nullptr, *blev_off = nullptr, *flev = nullptr, *blev = nullptr,
@@ -227,8 +228,29 @@ struct PrecWork {                 // per-handle work vectors for Algorithm 1
 struct DSystem {                  // FP64 system matrix for A z and the true residual
     int n_nodes = 0, n_cells = 0, nf = 0;
     Sell<double> Auu, Auf, Afu, Aff;
+    double mat_bytes = 0.0;       // algorithmic bytes of the four blocks (values, columns, row pointers)
     Arena arena;
 };
+
+// Optional HIP-event timing of the hot kernels (ps_kernel_timing / ps_kernel_stats): an
+// instrumented launch records an event before and after it on the stream it runs on and
+// adds its algorithmic bytes.  Off by default; a launch then costs one atomic load.
+namespace ktime {
+enum Id { SPMV, CGS2_PROJECT, CGS2_FUSED, CGS2_SUBTRACT, BILU_SUB, NUM };
+const char *name(int id);
+bool enabled();
+void set_enabled(bool on);          // clears the totals
+struct Scope {
+    Scope(int id, hipStream_t st, double bytes);
+    ~Scope();
+    int id;
+    hipStream_t st;
+    double bytes;
+    hipEvent_t e0 = nullptr;
+};
+// totals of kernel id (waits for recorded events)
+void totals(int id, long long &launches, double &seconds, double &bytes);
+}  // namespace ktime
 
 struct Krylov {                   // FGMRES workspace (FP64 basis, Z in the precond type)
     int m = 0, nblk = 0, chunk = 0;

@@ -1,8 +1,10 @@
 // Device data layout, uploads and the solve-phase drivers (Algorithm 1, FGMRES).
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 
@@ -25,6 +27,90 @@ static inline unsigned grid_for(size_t n) { return (unsigned)((n + WG - 1) / WG)
     do {                                                                               \
         if ((grid) > 0) hipLaunchKernelGGL(kernel, dim3(grid), dim3(WG), shm, st, __VA_ARGS__); \
     } while (0)
+
+// ------------------------------------------------------------------ kernel timing
+namespace ktime {
+namespace {
+std::atomic<bool> g_on{false};
+std::mutex g_mu;
+struct Rec {
+    int id;
+    hipEvent_t e0, e1;
+    double bytes;
+};
+std::vector<Rec> g_pending;
+std::vector<hipEvent_t> g_pool;
+long long g_launches[NUM];
+double g_seconds[NUM], g_bytes[NUM];
+
+hipEvent_t get_event() {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_pool.empty()) {
+        hipEvent_t e = g_pool.back();
+        g_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    PS_HIP(hipEventCreate(&e));
+    return e;
+}
+
+void drain_locked() {
+    for (Rec &r : g_pending) {
+        PS_HIP(hipEventSynchronize(r.e1));
+        float ms = 0.f;
+        PS_HIP(hipEventElapsedTime(&ms, r.e0, r.e1));
+        g_launches[r.id] += 1;
+        g_seconds[r.id] += ms * 1e-3;
+        g_bytes[r.id] += r.bytes;
+        g_pool.push_back(r.e0);
+        g_pool.push_back(r.e1);
+    }
+    g_pending.clear();
+}
+}  // namespace
+
+const char *name(int id) {
+    static const char *n[NUM] = {"system_spmv", "cgs2_project", "cgs2_subtract_project", "cgs2_subtract_norm",
+                                 "bilu_subdomain"};
+    return id >= 0 && id < NUM ? n[id] : "";
+}
+
+bool enabled() { return g_on.load(std::memory_order_relaxed); }
+
+void set_enabled(bool on) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    drain_locked();
+    for (int i = 0; i < NUM; ++i) {
+        g_launches[i] = 0;
+        g_seconds[i] = g_bytes[i] = 0.0;
+    }
+    g_on.store(on);
+}
+
+Scope::Scope(int i, hipStream_t s, double b) : id(i), st(s), bytes(b) {
+    if (!enabled()) return;
+    e0 = get_event();
+    PS_HIP(hipEventRecord(e0, st));
+}
+
+Scope::~Scope() {
+    if (!e0) return;
+    hipEvent_t e1 = get_event();
+    if (hipEventRecord(e1, st) != hipSuccess) return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (g_pending.size() >= 4096) drain_locked();    // bound the events in flight
+    g_pending.push_back({id, e0, e1, bytes});
+}
+
+void totals(int id, long long &launches, double &seconds, double &bytes) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    drain_locked();
+    launches = g_launches[id];
+    seconds = g_seconds[id];
+    bytes = g_bytes[id];
+}
+}  // namespace ktime
 
 // ------------------------------------------------------------------ SELL
 HostSell sell_from_bsr(const std::vector<int> &rp, const std::vector<int> &ci, const std::vector<double> &v,
@@ -418,6 +504,14 @@ static bool layout_sub_bilu(DFlow<T> &d, const FlowSetup &f, const System &s) {
         }
     }
     b.dsrc = dsrc;
+    {
+        // stored blocks (values + column) of both sweeps, D^{-1}, and the vectors
+        // (rhs read, z_s/z_p read, z written)
+        size_t nblk = 0;
+        for (int v : b.fsrc) nblk += v >= 0;
+        for (int v : b.bsrc) nblk += v >= 0;
+        b.bytes = (double)nblk * (nf * nf * sizeof(T) + 4) + (double)N * nf * nf * sizeof(T) + 3.0 * N * nf * sizeof(T);
+    }
     std::vector<int> ncell(N), npos(N);
     for (int g = 0; g < D; ++g) {
         std::vector<int> cells(ford.begin() + sub_off[g], ford.begin() + sub_off[g + 1]);
@@ -600,6 +694,8 @@ void upload_system(const System &s, DSystem &d) {
     d.Auf = upload_sell<double>(d.arena, sell_from_bsr(s.Auf.rp, s.Auf.ci, s.Auf.v, s.n_nodes, 3, s.nf));
     d.Afu = upload_sell<double>(d.arena, sell_from_bsr(s.Afu.rp, s.Afu.ci, s.Afu.v, s.n_cells, s.nf, 3));
     d.Aff = upload_sell<double>(d.arena, sell_from_bsr(s.Aff.rp, s.Aff.ci, s.Aff.v, s.n_cells, s.nf, s.nf));
+    auto blk = [](const Bsr &b) { return (double)b.nb() * (b.br * b.bc * 8 + 4) + 4.0 * b.rp.size(); };
+    d.mat_bytes = blk(s.Auu) + blk(s.Auf) + blk(s.Afu) + blk(s.Aff);
 }
 
 template <typename T>
@@ -730,6 +826,7 @@ static void launch_sub_y(const SubBilu<T> &b, const T *src, PrecWork<T> &w, T *z
         }
     }
     k::SubLayout L{b.N, b.sub_off, b.flev_off, b.blev_off, b.flev, b.blev, b.bpos, b.ncell, b.npos, b.fcol, b.bcol};
+    ktime::Scope ts(ktime::BILU_SUB, st, b.bytes);
     hipLaunchKernelGGL(kern, dim3(b.nsub), dim3(b.bs), b.lds, st, L, (const T *)b.fval, (const T *)b.bval,
                        (const T *)b.bdinv, src, w.dz, (const T *)w.zs, (const T *)w.zp, zf, b.ygl, b.lev_cap);
 }
@@ -870,6 +967,8 @@ void apply_precond(const DHierarchy<T> &sdc, const DFlow<T> &fl, PrecWork<T> &w,
 template <int NF, typename TX>
 static void spmv_full_nf(const DSystem &S, const TX *x, const double *b, double *y, hipStream_t st) {
     size_t nu = (size_t)3 * S.n_nodes;
+    const double N = (double)nu + (double)NF * S.n_cells;
+    ktime::Scope ts(ktime::SPMV, st, S.mat_bytes + N * sizeof(TX) + N * 8 * (b ? 2 : 1));
     if (b) {
         LAUNCH((k::spmv2<3, 3, NF, TX, true>), grid_for(S.n_nodes), 0, st, S.Auu, x, S.Auf, x + nu, b, y);
         LAUNCH((k::spmv2<NF, 3, NF, TX, true>), grid_for(S.n_cells), 0, st, S.Afu, x, S.Aff, x + nu, b + nu, y + nu);
@@ -984,10 +1083,15 @@ void Fgmres::enqueue_iteration() {
     if (K_.z_fp32) spmv_full<float>(S_, (const float *)zj, nullptr, w, st_);   // w = A z_j
     else spmv_full<double>(S_, (const double *)zj, nullptr, w, st_);
     // CGS2: h1 = V^T w (+ |w|^2), w -= V h1, h2 = V^T w, w -= V h2, h = h1 + h2, |w|^2
-    launch_mdot(K_, K_.V, nv, w, true, st_);
+    const double vb = (double)N * 8;                  // bytes of one basis vector
+    {
+        ktime::Scope ts(ktime::CGS2_PROJECT, st_, (nv + 1) * vb);
+        launch_mdot(K_, K_.V, nv, w, true, st_);
+    }
     LAUNCH(k::reduce_rows, nv + 1, 0, st_, (const double *)K_.partial, K_.nblk, K_.h1, (const double *)nullptr,
            (double *)nullptr);
     if (nv >= 22 && nv <= k::SUBDOT_MAXV) {          // below ~22 vectors two passes are faster
+        ktime::Scope ts(ktime::CGS2_FUSED, st_, (nv + 2) * vb);
         LAUNCH(k::gemv_sub_mdot, K_.nblk, (size_t)nv * 65 * sizeof(double), st_, (const double *)K_.V, N, nv,
                (const double *)K_.h1, w, N, K_.chunk, K_.partial, K_.nblk);
     } else {
@@ -996,8 +1100,11 @@ void Fgmres::enqueue_iteration() {
         launch_mdot(K_, K_.V, nv, w, false, st_);
     }
     LAUNCH(k::reduce_rows, nv, 0, st_, (const double *)K_.partial, K_.nblk, K_.h2, (const double *)K_.h1, K_.hsum);
-    LAUNCH((k::gemv_sub<true>), K_.nblk, 0, st_, (const double *)K_.V, N, nv, (const double *)K_.h2, w, N,
-           K_.chunk, K_.partial);
+    {
+        ktime::Scope ts(ktime::CGS2_SUBTRACT, st_, (nv + 2) * vb);
+        LAUNCH((k::gemv_sub<true>), K_.nblk, 0, st_, (const double *)K_.V, N, nv, (const double *)K_.h2, w, N,
+               K_.chunk, K_.partial);
+    }
     LAUNCH(k::reduce_rows, 1, 0, st_, (const double *)K_.partial, K_.nblk, K_.nw2, (const double *)nullptr,
            (double *)nullptr);
     LAUNCH(k::givens, 1, 0, st_, j, m, (const double *)K_.hsum, (const double *)(K_.h1 + nv),

@@ -12,6 +12,9 @@
 #include <cstdlib>
 #include <cstring>
 #include <atomic>
+#include <mutex>
+#include <functional>
+#include <condition_variable>
 #include <numeric>
 #include <thread>
 
@@ -46,6 +49,86 @@ int setup_threads() {
     return n;
 }
 
+// Persistent worker threads for parallel_rows: starting 16 threads per parallel loop
+// costs about as much as the loops of the setup themselves.  Workers spin briefly on a
+// generation counter, then sleep on a condition variable.  One loop at a time uses the
+// pool; a loop started while it is busy (the local-stage factorisation runs beside the
+// pressure AMG) starts its own threads.
+class Pool {
+  public:
+    explicit Pool(int n) : n_(n) {
+        for (int t = 1; t < n_; ++t) th_.emplace_back([this, t] { worker(t); });
+    }
+    ~Pool() {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            stop_ = true;
+            gen_.fetch_add(1);
+        }
+        cv_.notify_all();
+        for (auto &t : th_) t.join();
+    }
+    int size() const { return n_; }
+    std::mutex busy;
+    // run job(p) for p = 0 .. parts-1 (parts <= size()); the caller runs part 0
+    void run(int parts, const std::function<void(int)> &job) {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            job_ = &job;
+            parts_ = parts;
+            left_.store(parts - 1);
+            gen_.fetch_add(1);
+        }
+        cv_.notify_all();
+        job(0);
+        while (left_.load(std::memory_order_acquire) > 0) std::this_thread::yield();
+    }
+
+  private:
+    void worker(int t) {
+        unsigned long long seen = 0;
+        for (;;) {
+            unsigned long long g;
+            for (int spin = 0; (g = gen_.load(std::memory_order_acquire)) == seen && spin < 20000; ++spin) {
+            }
+            if (g == seen) {
+                std::unique_lock<std::mutex> lk(mu_);
+                cv_.wait(lk, [&] { return gen_.load() != seen; });
+            }
+            // generation, job and part count are read together under the lock, so a
+            // worker runs each generation's part at most once (a run cannot start
+            // before every part of the previous one has finished)
+            const std::function<void(int)> *job;
+            int parts;
+            {
+                std::lock_guard<std::mutex> lk(mu_);
+                if (stop_) return;
+                seen = gen_.load();
+                job = job_;
+                parts = parts_;
+            }
+            if (t < parts) {
+                (*job)(t);
+                left_.fetch_sub(1, std::memory_order_acq_rel);
+            }
+        }
+    }
+    int n_;
+    std::vector<std::thread> th_;
+    std::mutex mu_;
+    std::condition_variable cv_;
+    std::atomic<unsigned long long> gen_{0};
+    std::atomic<int> left_{0};
+    const std::function<void(int)> *job_ = nullptr;
+    int parts_ = 0;
+    bool stop_ = false;
+};
+
+Pool &pool() {
+    static Pool p(setup_threads());
+    return p;
+}
+
 template <class F>
 void parallel_rows(int n, F &&f) {           // f(begin, end, part)
     int parts = std::min(setup_threads(), std::max(1, n / 8192));
@@ -53,11 +136,30 @@ void parallel_rows(int n, F &&f) {           // f(begin, end, part)
         f(0, n, 0);
         return;
     }
+    auto range = [n, parts](int p, int &b, int &e) {
+        b = (int)((long long)n * p / parts);
+        e = (int)((long long)n * (p + 1) / parts);
+    };
+    Pool &P = pool();
+    std::unique_lock<std::mutex> lk(P.busy, std::try_to_lock);
+    if (lk.owns_lock()) {
+        std::function<void(int)> job = [&](int p) {
+            int b, e;
+            range(p, b, e);
+            f(b, e, p);
+        };
+        P.run(parts, job);
+        return;
+    }
     std::vector<std::thread> th;
-    for (int p = 0; p < parts; ++p) {
-        int b = (int)((long long)n * p / parts), e = (int)((long long)n * (p + 1) / parts);
+    for (int p = 1; p < parts; ++p) {
+        int b, e;
+        range(p, b, e);
         th.emplace_back([&f, b, e, p] { f(b, e, p); });
     }
+    int b, e;
+    range(0, b, e);
+    f(b, e, 0);
     for (auto &t : th) t.join();
 }
 

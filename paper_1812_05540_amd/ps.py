@@ -65,6 +65,9 @@ _SIGS = {
     "ps_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(ps_result)]),
     "ps_wait": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(ps_result)]),
     "ps_footprint": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
+    "ps_kernel_timing": (C.c_int, [C.c_int]),
+    "ps_kernel_stats": (C.c_int, [C.c_int, C.c_char_p, C.c_size_t, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                  C.POINTER(C.c_double)]),
     "ps_pressure_level": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                     C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                     C.POINTER(C.c_double), C.POINTER(C.c_int8)]),
@@ -250,6 +253,26 @@ def ps_wait(ctx, ticket):
     d = r.as_dict()
     d["status"] = code
     return d
+
+
+def ps_kernel_timing(enable):
+    _check(load().ps_kernel_timing(1 if enable else 0), "ps_kernel_timing")
+
+
+def ps_kernel_stats():
+    """Instrumented kernel totals: {name: dict(launches, seconds, bytes)}."""
+    lib = load()
+    out = {}
+    idx = 0
+    while True:
+        name = C.create_string_buffer(64)
+        n, sec, b = C.c_int64(), C.c_double(), C.c_double()
+        code = lib.ps_kernel_stats(idx, name, 64, C.byref(n), C.byref(sec), C.byref(b))
+        if code == PS_EINVAL:
+            return out
+        _check(code, "ps_kernel_stats")
+        out[name.value.decode()] = dict(launches=n.value, seconds=sec.value, bytes=b.value)
+        idx += 1
 
 
 def ps_pressure_level(h, lvl):
