@@ -345,7 +345,7 @@ int ps_setup(ps_handle *h) {
                     }
                 });
                 try {
-                    PhaseTimer pt2("pressure AMG (device RAP)");
+                    PhaseTimer pt2("pressure AMG (device)");
                     build_pressure(h->flow.Spp, h->opt, h->flow.pres, h->pstore);
                 } catch (...) {
                     local.join();
@@ -354,6 +354,7 @@ int ps_setup(ps_handle *h) {
                 local.join();
                 if (err) std::rethrow_exception(err);
             } else {
+                h->pstore.on_device = false;
                 {
                     PhaseTimer pt2("pressure AMG (host)");
                     h->flow.pres = amg_build(h->flow.Spp, h->opt);
@@ -573,13 +574,18 @@ int ps_pressure_level(ps_handle *h, int lvl, int32_t *nlevels, int32_t *n, int32
         const Hierarchy &H = h->flow.pres;
         if (nlevels) *nlevels = (int32_t)H.lev.size();
         if (lvl < 0 || lvl >= (int)H.lev.size()) throw Error(PS_EINVAL, "level out of range");
-        const Level &L = H.lev[lvl];
-        if (n) *n = L.A.n;
-        if (nnz) *nnz = L.A.nnz();
-        if (rowptr) std::memcpy(rowptr, L.A.rp.data(), L.A.rp.size() * sizeof(int32_t));
-        if (colind) std::memcpy(colind, L.A.ci.data(), L.A.ci.size() * sizeof(int32_t));
-        if (vals) std::memcpy(vals, L.A.v.data(), L.A.v.size() * sizeof(double));
-        if (cf) std::memcpy(cf, L.cf.data(), L.cf.size());
+        Csr dA;
+        std::vector<int8_t> dcf;
+        const bool dev = h->pstore.on_device;
+        if (dev) download_level(h->pstore, lvl, dA, dcf);      // built on the device: copy back
+        const Csr &A = dev ? dA : H.lev[lvl].A;
+        const std::vector<int8_t> &c = dev ? dcf : H.lev[lvl].cf;
+        if (n) *n = A.n;
+        if (nnz) *nnz = A.nnz();
+        if (rowptr) std::memcpy(rowptr, A.rp.data(), A.rp.size() * sizeof(int32_t));
+        if (colind) std::memcpy(colind, A.ci.data(), A.ci.size() * sizeof(int32_t));
+        if (vals) std::memcpy(vals, A.v.data(), A.v.size() * sizeof(double));
+        if (cf && !c.empty()) std::memcpy(cf, c.data(), c.size());
         return PS_OK;
     });
 }

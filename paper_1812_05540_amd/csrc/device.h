@@ -138,8 +138,14 @@ void spgemm_device(const DevCsr &A, const DevCsr &B, DevCsr &C, Arena &out, Aren
 struct PresStore {
     Arena arena, work, tmp;
     std::vector<DevCsr> A, P, R;
+    bool on_device = false;            // whole build on the device (l1-Jacobi): the host levels
+                                       // in H carry sizes only; cf and dinv are here
+    std::vector<signed char *> cf;     // C/F splitting per level (1 C, -1 F)
+    std::vector<double *> dinv;        // l1-Jacobi 1 / (a_ii + sum |a_ij|) per level
 };
 void build_pressure(const Csr &Spp, const Options &o, Hierarchy &H, PresStore &S);
+// operator and splitting of level lvl copied to the host (zeros on the coarsest level)
+void download_level(const PresStore &S, int lvl, Csr &A, std::vector<int8_t> &cf);
 
 template <typename T>
 struct DCsr {

@@ -597,7 +597,16 @@ static void adopt_hierarchy(DHierarchy<T> &d, const Hierarchy &H, const PresStor
         D.A = adopt_csr<T>(d.arena, S.A[l]);
         D.P = adopt_csr<T>(d.arena, S.P[l]);
         D.R = adopt_csr<T>(d.arena, S.R[l]);
-        if (smoother == PS_L1JAC) {
+        if (S.on_device) {
+            if constexpr (sizeof(T) == 8) {
+                D.dinv = S.dinv[l];
+            } else {
+                T *v = d.arena.template alloc<T>(D.n);
+                LAUNCH((k::convert<double, T>), grid_for((size_t)D.n), 0, 0, (const double *)S.dinv[l], v,
+                       (size_t)D.n);
+                D.dinv = v;
+            }
+        } else if (smoother == PS_L1JAC) {
             std::vector<double> inv(L.dl1.size());
             for (size_t i = 0; i < L.dl1.size(); ++i) inv[i] = 1.0 / L.dl1[i];
             D.dinv = upload_vec<T>(d.arena, inv);

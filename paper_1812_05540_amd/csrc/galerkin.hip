@@ -118,6 +118,288 @@ T read_back(const T *d, hipStream_t st) {
     return h;
 }
 
+// ---------------------------------------------------------------- coarsening on the device
+// The steps of coarsen_level (host) with the same definitions and, where floating point
+// is involved, the same operations in the same order, so that C/F splittings and
+// interpolation weights equal the host's bit for bit.
+
+__device__ __forceinline__ double unit_hash_dev(unsigned long long i) {
+    // SplitMix64 (Steele, Lea, Flood 2014) of the row index, top 53 bits as a double in [0, 1)
+    unsigned long long z = i + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z = z ^ (z >> 31);
+    return (double)(z >> 11) * 0x1.0p-53;
+}
+
+// strength: j in S_i iff j != i and -a_ij >= theta * max_{k != i}(-a_ik) > 0; per-row
+// counts of S_i and of S^T (how many rows depend on j)
+__global__ void strength_k(const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ v,
+                           int n, double theta, signed char *__restrict__ smask, int *__restrict__ scount,
+                           int *__restrict__ lam) {
+    int i = blockIdx.x * TB + threadIdx.x;
+    if (i >= n) return;
+    double m = -INFINITY;
+    for (int t = rp[i]; t < rp[i + 1]; ++t) {
+        if (ci[t] == i) continue;
+        const double x = -v[t];
+        m = m < x ? x : m;
+    }
+    int c = 0;
+    if (m > 0.0) {
+        const double thr = __dmul_rn(theta, m);
+        for (int t = rp[i]; t < rp[i + 1]; ++t) {
+            const bool s = ci[t] != i && -v[t] >= thr;
+            smask[t] = s;
+            if (s) {
+                ++c;
+                atomicAdd(&lam[ci[t]], 1);
+            }
+        }
+    } else {
+        for (int t = rp[i]; t < rp[i + 1]; ++t) smask[t] = 0;
+    }
+    scount[i] = c;
+}
+
+__global__ void fill_s_k(const int *__restrict__ rp, const int *__restrict__ ci, const signed char *__restrict__ smask,
+                         int n, const int *__restrict__ srp, int *__restrict__ sci) {
+    int i = blockIdx.x * TB + threadIdx.x;
+    if (i >= n) return;
+    int k = srp[i];
+    for (int t = rp[i]; t < rp[i + 1]; ++t)
+        if (smask[t]) sci[k++] = ci[t];
+}
+
+// S^T rows (order inside a row is irrelevant: PMIS only asks whether some neighbour wins)
+__global__ void fill_st_k(const int *__restrict__ srp, const int *__restrict__ sci, int n, int *__restrict__ cur,
+                          int *__restrict__ tci) {
+    int i = blockIdx.x * TB + threadIdx.x;
+    if (i >= n) return;
+    for (int k = srp[i]; k < srp[i + 1]; ++k) tci[atomicAdd(&cur[sci[k]], 1)] = i;
+}
+
+// weights w_i = |S^T_i| + u_i; points nobody depends on start as F
+__global__ void pmis_init_k(const int *__restrict__ trp, int n, double *__restrict__ w, signed char *__restrict__ st,
+                            int *__restrict__ undecided) {
+    int i = blockIdx.x * TB + threadIdx.x;
+    if (i >= n) return;
+    const int lam = trp[i + 1] - trp[i];
+    w[i] = (double)lam + unit_hash_dev((unsigned long long)i);
+    st[i] = lam == 0 ? -1 : 0;
+    if (lam != 0) atomicAdd(undecided, 1);
+}
+
+__device__ __forceinline__ bool beats(const double *w, int j, int i) { return w[j] > w[i] || (w[j] == w[i] && j > i); }
+
+// one PMIS round, part 1: an undecided point becomes C if no undecided neighbour in
+// S_i u S^T_i beats it (reads the states at the start of the round only)
+__global__ void pmis_select_k(const signed char *__restrict__ st, const double *__restrict__ w,
+                              const int *__restrict__ srp, const int *__restrict__ sci, const int *__restrict__ trp,
+                              const int *__restrict__ tci, int n, signed char *__restrict__ newc) {
+    int i = blockIdx.x * TB + threadIdx.x;
+    if (i >= n) return;
+    if (st[i] != 0) {
+        newc[i] = 0;
+        return;
+    }
+    bool beaten = false;
+    for (int k = srp[i]; k < srp[i + 1] && !beaten; ++k) {
+        const int j = sci[k];
+        if (st[j] == 0 && beats(w, j, i)) beaten = true;
+    }
+    for (int k = trp[i]; k < trp[i + 1] && !beaten; ++k) {
+        const int j = tci[k];
+        if (st[j] == 0 && beats(w, j, i)) beaten = true;
+    }
+    newc[i] = !beaten;
+}
+
+// part 2: new C points are set; an undecided point strongly depending on one becomes F
+__global__ void pmis_mark_k(signed char *__restrict__ st, const signed char *__restrict__ newc,
+                            const int *__restrict__ srp, const int *__restrict__ sci, int n,
+                            int *__restrict__ undecided) {
+    int i = blockIdx.x * TB + threadIdx.x;
+    if (i >= n) return;
+    if (newc[i]) {
+        st[i] = 1;
+        return;
+    }
+    if (st[i] != 0) return;
+    for (int k = srp[i]; k < srp[i + 1]; ++k)
+        if (newc[sci[k]]) {
+            st[i] = -1;
+            return;
+        }
+    atomicAdd(undecided, 1);
+}
+
+// C-promotion, equal to the sequential rule "in increasing i, an F point with S_i
+// non-empty and no C point in S_i becomes C": candidates are the F points whose S_i has
+// no PMIS C point; a candidate is promoted iff no candidate j < i in S_i was promoted,
+// decided in rounds once every candidate j < i in S_i is decided (cs: 0 not a candidate
+// / decided F, 1 undecided, 2 promoted)
+__global__ void promo_init_k(const signed char *__restrict__ st, const int *__restrict__ srp,
+                             const int *__restrict__ sci, int n, signed char *__restrict__ cs,
+                             int *__restrict__ count) {
+    int i = blockIdx.x * TB + threadIdx.x;
+    if (i >= n) return;
+    signed char c = 0;
+    if (st[i] == -1 && srp[i + 1] > srp[i]) {
+        c = 1;
+        for (int k = srp[i]; k < srp[i + 1]; ++k)
+            if (st[sci[k]] == 1) {
+                c = 0;
+                break;
+            }
+    }
+    cs[i] = c;
+    if (c) atomicAdd(count, 1);
+}
+
+__global__ void promo_round_k(signed char *cs, const int *__restrict__ srp, const int *__restrict__ sci, int n,
+                              int *__restrict__ undecided) {
+    int i = blockIdx.x * TB + threadIdx.x;
+    if (i >= n) return;
+    if (__hip_atomic_load(&cs[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 1) return;
+    bool wait = false;
+    for (int k = srp[i]; k < srp[i + 1]; ++k) {
+        const int j = sci[k];
+        if (j >= i) continue;
+        const signed char c = __hip_atomic_load(&cs[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (c == 2) {                          // an earlier promoted point: stays F
+            __hip_atomic_store(&cs[i], (signed char)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return;
+        }
+        if (c == 1) wait = true;
+    }
+    if (wait) {
+        atomicAdd(undecided, 1);
+        return;
+    }
+    __hip_atomic_store(&cs[i], (signed char)2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void promo_apply_k(signed char *__restrict__ st, const signed char *__restrict__ cs, int n,
+                              int *__restrict__ cflag) {
+    int i = blockIdx.x * TB + threadIdx.x;
+    if (i > n) return;
+    if (i == n) {
+        cflag[n] = 0;
+        return;
+    }
+    if (cs[i] == 2) st[i] = 1;
+    cflag[i] = st[i] == 1;
+}
+
+// direct interpolation (Stueben): C rows identity; F row i:
+// P_ij = -(alpha_i a_ij) / atil_ii for j in S_i n C, alpha_i = sum_{a_ij<0} a_ij / sum_{j in S_i n C} a_ij,
+// atil_ii = a_ii + sum_{j != i, a_ij > 0} a_ij, all sums in increasing column order from 0
+__global__ void interp_count_k(const int *__restrict__ rp, const int *__restrict__ ci,
+                               const signed char *__restrict__ smask, const signed char *__restrict__ st, int n,
+                               int *__restrict__ plen) {
+    int i = blockIdx.x * TB + threadIdx.x;
+    if (i > n) return;
+    if (i == n) {
+        plen[n] = 0;
+        return;
+    }
+    if (st[i] == 1) {
+        plen[i] = 1;
+        return;
+    }
+    int c = 0;
+    for (int t = rp[i]; t < rp[i + 1]; ++t) c += ci[t] != i && smask[t] && st[ci[t]] == 1;
+    plen[i] = c;
+}
+
+__global__ void interp_fill_k(const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ v,
+                              const signed char *__restrict__ smask, const signed char *__restrict__ st,
+                              const int *__restrict__ cidx, int n, const int *__restrict__ prp,
+                              int *__restrict__ pci, double *__restrict__ pv) {
+    int i = blockIdx.x * TB + threadIdx.x;
+    if (i >= n) return;
+    int o = prp[i];
+    if (st[i] == 1) {
+        pci[o] = cidx[i];
+        pv[o] = 1.0;
+        return;
+    }
+    double diag = 0.0, pos = 0.0, negs = 0.0, den = 0.0;
+    for (int t = rp[i]; t < rp[i + 1]; ++t) {
+        const int j = ci[t];
+        const double a = v[t];
+        if (j == i) {
+            diag = a;
+            continue;
+        }
+        if (a > 0.0) pos = __dadd_rn(pos, a);
+        if (a < 0.0) negs = __dadd_rn(negs, a);
+        if (smask[t] && st[j] == 1) den = __dadd_rn(den, a);
+    }
+    const double atil = __dadd_rn(diag, pos);
+    const double alpha = den != 0.0 ? __ddiv_rn(negs, den) : 0.0;
+    for (int t = rp[i]; t < rp[i + 1]; ++t) {
+        const int j = ci[t];
+        if (j != i && smask[t] && st[j] == 1) {
+            pci[o] = cidx[j];
+            pv[o] = __ddiv_rn(-__dmul_rn(alpha, v[t]), atil);
+            ++o;
+        }
+    }
+}
+
+// R = P^T: column counts, unordered fill, then each row sorted by fine index
+__global__ void col_count_k(const int *__restrict__ ci, int nnz, int *__restrict__ cnt) {
+    int t = blockIdx.x * TB + threadIdx.x;
+    if (t < nnz) atomicAdd(&cnt[ci[t]], 1);
+}
+
+__global__ void transpose_fill_k(const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ v,
+                                 int n, int *__restrict__ cur, int *__restrict__ tci, double *__restrict__ tv) {
+    int i = blockIdx.x * TB + threadIdx.x;
+    if (i >= n) return;
+    for (int t = rp[i]; t < rp[i + 1]; ++t) {
+        const int k = atomicAdd(&cur[ci[t]], 1);
+        tci[k] = i;
+        tv[k] = v[t];
+    }
+}
+
+__global__ void sort_rows_k(const int *__restrict__ rp, int n, int *__restrict__ ci, double *__restrict__ v) {
+    int r = blockIdx.x * TB + threadIdx.x;
+    if (r >= n) return;
+    for (int a = rp[r] + 1; a < rp[r + 1]; ++a) {
+        const int c = ci[a];
+        const double x = v[a];
+        int b = a - 1;
+        while (b >= rp[r] && ci[b] > c) {
+            ci[b + 1] = ci[b];
+            v[b + 1] = v[b];
+            --b;
+        }
+        ci[b + 1] = c;
+        v[b + 1] = x;
+    }
+}
+
+// l1-Jacobi: dinv_i = 1 / (a_ii + sum_{j != i} |a_ij|), the sum in column order from 0
+__global__ void l1_inv_k(const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ v, int n,
+                         double *__restrict__ dinv, int *__restrict__ zero_diag) {
+    int i = blockIdx.x * TB + threadIdx.x;
+    if (i >= n) return;
+    double diag = 0.0, s = 0.0;
+    for (int t = rp[i]; t < rp[i + 1]; ++t) {
+        if (ci[t] == i) {
+            diag = v[t];
+            continue;
+        }
+        s = __dadd_rn(s, fabs(v[t]));
+    }
+    if (diag == 0.0) atomicAdd(zero_diag, 1);
+    dinv[i] = __ddiv_rn(1.0, __dadd_rn(diag, s));
+}
+
 }  // namespace
 
 void spgemm_device(const DevCsr &A, const DevCsr &B, DevCsr &C, Arena &out, Arena &tmp, hipStream_t st) {
@@ -213,12 +495,8 @@ static Csr download(const DevCsr &d) {
 // The pressure AMG of amg_build with each Galerkin product R (A P) formed on the device:
 // the host coarsens level l (strength, PMIS, interpolation) from its copy of A_l, the
 // device forms A_{l+1}, and the host copy of A_{l+1} comes back for the next level.
-void build_pressure(const Csr &Spp, const Options &o, Hierarchy &H, PresStore &S) {
-    H = Hierarchy();
-    S.arena.recycle();
-    S.A.clear();
-    S.P.clear();
-    S.R.clear();
+// (Used with Chebyshev smoothing, whose eigenvalue estimate is taken on the host.)
+static void build_pressure_hybrid(const Csr &Spp, const Options &o, Hierarchy &H, PresStore &S) {
     const hipStream_t st = 0;
     Csr A = Spp;
     DevCsr Ad = upload(S.arena, A);
@@ -243,7 +521,137 @@ void build_pressure(const Csr &Spp, const Options &o, Hierarchy &H, PresStore &S
     }
     S.A.push_back(Ad);
     coarse_level(std::move(A), H);
+}
+
+// The whole pressure AMG on the device (l1-Jacobi smoothing): strength, PMIS, C-promotion,
+// direct interpolation, R = P^T, the Galerkin product and the smoother diagonal, with the
+// same results as the host build; only counts come back per step, and the coarsest
+// operator at the end for its dense inverse.  H holds the level sizes and the coarse
+// inverse; the operators, splittings and smoother data stay in S.
+static void build_pressure_device(const Csr &Spp, const Options &o, Hierarchy &H, PresStore &S) {
+    const hipStream_t st = 0;
+    auto zero = [&](int *p, long long n) {
+        hipLaunchKernelGGL(fill_int, dim3(blocks(n)), dim3(TB), 0, st, p, 0, n);
+    };
+    int *ctr = S.arena.alloc<int>(4);
+    DevCsr A = upload(S.arena, Spp);
+    while (A.n > o.coarse_max && (int)H.lev.size() + 1 < o.max_levels) {
+        const int n = A.n, nnz = A.nnz;
+        S.work.recycle();
+        S.tmp.recycle();
+        // strength and S, S^T
+        signed char *smask = S.work.alloc<signed char>(nnz);
+        int *scount = S.work.alloc<int>((size_t)n + 1), *lam = S.work.alloc<int>((size_t)n + 1);
+        zero(scount, n + 1);
+        zero(lam, n + 1);
+        hipLaunchKernelGGL(strength_k, dim3(blocks(n)), dim3(TB), 0, st, A.rp, A.ci, A.v, n, o.theta, smask, scount,
+                           lam);
+        int *srp = S.work.alloc<int>((size_t)n + 1), *trp = S.work.alloc<int>((size_t)n + 1);
+        exclusive_scan(S.tmp, scount, srp, (size_t)n + 1, st);
+        exclusive_scan(S.tmp, lam, trp, (size_t)n + 1, st);
+        const int ns = read_back(srp + n, st);
+        int *sci = S.work.alloc<int>(ns), *tci = S.work.alloc<int>(ns), *cur = S.work.alloc<int>(n);
+        hipLaunchKernelGGL(fill_s_k, dim3(blocks(n)), dim3(TB), 0, st, A.rp, A.ci, smask, n, srp, sci);
+        PS_HIP(hipMemcpyAsync(cur, trp, sizeof(int) * n, hipMemcpyDeviceToDevice, st));
+        hipLaunchKernelGGL(fill_st_k, dim3(blocks(n)), dim3(TB), 0, st, srp, sci, n, cur, tci);
+        // PMIS rounds
+        double *w = S.work.alloc<double>(n);
+        signed char *cf = S.arena.alloc<signed char>(n), *newc = S.work.alloc<signed char>(n);
+        zero(ctr, 1);
+        hipLaunchKernelGGL(pmis_init_k, dim3(blocks(n)), dim3(TB), 0, st, trp, n, w, cf, ctr);
+        int rounds = 0;
+        for (int und = read_back(ctr, st); und > 0; und = read_back(ctr, st)) {
+            if (++rounds > n) throw Error(PS_EDEVICE, "PMIS did not terminate");   // each round decides >= 1 point
+            hipLaunchKernelGGL(pmis_select_k, dim3(blocks(n)), dim3(TB), 0, st, cf, w, srp, sci, trp, tci, n, newc);
+            zero(ctr, 1);
+            hipLaunchKernelGGL(pmis_mark_k, dim3(blocks(n)), dim3(TB), 0, st, cf, newc, srp, sci, n, ctr);
+        }
+        // C-promotion
+        signed char *cs = S.work.alloc<signed char>(n);
+        zero(ctr, 1);
+        hipLaunchKernelGGL(promo_init_k, dim3(blocks(n)), dim3(TB), 0, st, cf, srp, sci, n, cs, ctr);
+        rounds = 0;
+        for (int und = read_back(ctr, st); und > 0; und = read_back(ctr, st)) {
+            if (++rounds > n) throw Error(PS_EDEVICE, "C-promotion did not terminate");
+            zero(ctr, 1);
+            hipLaunchKernelGGL(promo_round_k, dim3(blocks(n)), dim3(TB), 0, st, cs, srp, sci, n, ctr);
+        }
+        int *cflag = S.work.alloc<int>((size_t)n + 1), *cidx = S.work.alloc<int>((size_t)n + 1);
+        hipLaunchKernelGGL(promo_apply_k, dim3(blocks(n + 1)), dim3(TB), 0, st, cf, cs, n, cflag);
+        exclusive_scan(S.tmp, cflag, cidx, (size_t)n + 1, st);
+        const int nc = read_back(cidx + n, st);
+        if (nc == 0 || (double)nc > 0.9 * (double)n) break;
+        // direct interpolation and R = P^T
+        int *plen = S.work.alloc<int>((size_t)n + 1);
+        hipLaunchKernelGGL(interp_count_k, dim3(blocks(n + 1)), dim3(TB), 0, st, A.rp, A.ci, smask, cf, n, plen);
+        DevCsr P;
+        P.n = n;
+        P.m = nc;
+        P.rp = S.arena.alloc<int>((size_t)n + 1);
+        exclusive_scan(S.tmp, plen, P.rp, (size_t)n + 1, st);
+        P.nnz = read_back(P.rp + n, st);
+        P.ci = S.arena.alloc<int>(P.nnz);
+        P.v = S.arena.alloc<double>(P.nnz);
+        hipLaunchKernelGGL(interp_fill_k, dim3(blocks(n)), dim3(TB), 0, st, A.rp, A.ci, A.v, smask, cf, cidx, n, P.rp,
+                           P.ci, P.v);
+        DevCsr R;
+        R.n = nc;
+        R.m = n;
+        R.nnz = P.nnz;
+        int *rcnt = S.work.alloc<int>((size_t)nc + 1), *rcur = S.work.alloc<int>(nc);
+        zero(rcnt, nc + 1);
+        hipLaunchKernelGGL(col_count_k, dim3(blocks(P.nnz)), dim3(TB), 0, st, P.ci, P.nnz, rcnt);
+        R.rp = S.arena.alloc<int>((size_t)nc + 1);
+        exclusive_scan(S.tmp, rcnt, R.rp, (size_t)nc + 1, st);
+        R.ci = S.arena.alloc<int>(R.nnz);
+        R.v = S.arena.alloc<double>(R.nnz);
+        PS_HIP(hipMemcpyAsync(rcur, R.rp, sizeof(int) * nc, hipMemcpyDeviceToDevice, st));
+        hipLaunchKernelGGL(transpose_fill_k, dim3(blocks(n)), dim3(TB), 0, st, P.rp, P.ci, P.v, n, rcur, R.ci, R.v);
+        hipLaunchKernelGGL(sort_rows_k, dim3(blocks(nc)), dim3(TB), 0, st, R.rp, nc, R.ci, R.v);
+        // smoother diagonal
+        double *dinv = S.arena.alloc<double>(n);
+        zero(ctr, 1);
+        hipLaunchKernelGGL(l1_inv_k, dim3(blocks(n)), dim3(TB), 0, st, A.rp, A.ci, A.v, n, dinv, ctr);
+        if (read_back(ctr, st) != 0) throw Error(PS_ESINGULAR, "zero diagonal in an AMG level");
+        // Galerkin product
+        DevCsr AP, Ac;
+        S.tmp.recycle();
+        spgemm_device(A, P, AP, S.work, S.tmp, st);
+        S.tmp.recycle();
+        spgemm_device(R, AP, Ac, S.arena, S.tmp, st);
+        Level L;
+        L.A.n = L.A.m = n;
+        H.lev.push_back(std::move(L));
+        S.A.push_back(A);
+        S.P.push_back(P);
+        S.R.push_back(R);
+        S.cf.push_back(cf);
+        S.dinv.push_back(dinv);
+        A = Ac;
+    }
+    S.A.push_back(A);
+    coarse_level(download(A), H);
+}
+
+void build_pressure(const Csr &Spp, const Options &o, Hierarchy &H, PresStore &S) {
+    H = Hierarchy();
+    S.arena.recycle();
+    S.A.clear();
+    S.P.clear();
+    S.R.clear();
+    S.cf.clear();
+    S.dinv.clear();
+    S.on_device = o.smoother == PS_L1JAC;
+    if (S.on_device) build_pressure_device(Spp, o, H, S);
+    else build_pressure_hybrid(Spp, o, H, S);
     S.arena.trim();          // blocks of an earlier, larger hierarchy that were not reused
+}
+
+void download_level(const PresStore &S, int lvl, Csr &A, std::vector<int8_t> &cf) {
+    A = download(S.A.at(lvl));
+    cf.assign(A.n, 0);
+    if (lvl < (int)S.cf.size() && A.n)
+        PS_HIP(hipMemcpy(cf.data(), S.cf[lvl], (size_t)A.n, hipMemcpyDeviceToHost));
 }
 
 }  // namespace ps

@@ -340,13 +340,17 @@ GAL_CASES = {
     "grf12_cheb2": (dict(grid=(12, 11, 10), kind="grf", seed=2, rhs_seed=102, sigma=1.0), ps.PS_CHEB2),
     "grf24_l1jac": (dict(grid=(24, 24, 24), kind="grf", seed=5, rhs_seed=105, sigma=2.0), ps.PS_L1JAC),
     "three_phase": (dict(grid=(12, 10, 8), kind="iid3", seed=3, rhs_seed=103), ps.PS_CHEB2),
+    "three_phase_l1jac": (dict(grid=(12, 10, 8), kind="iid3", seed=3, rhs_seed=103), ps.PS_L1JAC),
+    "iid8_l1jac": (dict(grid=(8, 8, 8), kind="iid", seed=1, rhs_seed=101), ps.PS_L1JAC),
+    "grf12_l1jac": (dict(grid=(12, 11, 10), kind="grf", seed=2, rhs_seed=102, sigma=2.0), ps.PS_L1JAC),
 }
 
 
 @pytest.mark.parametrize("case", list(GAL_CASES))
 def test_device_galerkin_hierarchy_equals_oracle_bitwise(ctx, case):
     """Pressure AMG with R (A P) formed on the device (expansion, stable sort, ordered
-    sums): every level operator and C/F splitting equals the oracle's bit for bit."""
+    sums) -- with l1-Jacobi the whole coarsening too (strength, PMIS, C-promotion, direct
+    interpolation): every level operator and C/F splitting equals the oracle's bit for bit."""
     spec, sm = GAL_CASES[case]
     s, _ = workload(**spec)
     sv = make_solver(ctx, s, smoother=sm)
