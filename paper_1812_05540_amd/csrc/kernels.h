@@ -241,14 +241,28 @@ __device__ __forceinline__ T group_sum(T a) {
 }
 
 // sum_j a_ij x_j (or a_ij x_j s_j when S) for the calling group's row
+// (four of a lane's entries are loaded before any is used, so their index loads and
+// gathers overlap; past the row's end the loads repeat its last entry and are not added;
+// the sum still runs in increasing t)
 template <int G, bool S, typename T>
 __device__ __forceinline__ T csr_dot(const DCsr<T> &A, int i, int g, const T *__restrict__ x,
                                      const T *__restrict__ s) {
     T acc = T(0);
-    int e = A.rp[i + 1];
-    for (int t = A.rp[i] + g; t < e; t += G) {
-        int c = A.ci[t];
-        acc += A.v[t] * (S ? x[c] * s[c] : x[c]);
+    const int e = A.rp[i + 1];
+    for (int t = A.rp[i] + g; t < e; t += 4 * G) {
+        int c[4];
+        T a[4], xv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int tt = t + u * G < e ? t + u * G : e - 1;
+            c[u] = A.ci[tt];
+            a[u] = A.v[tt];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) xv[u] = S ? x[c[u]] * s[c[u]] : x[c[u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (t + u * G < e) acc += a[u] * xv[u];
     }
     return group_sum<G>(acc);
 }
