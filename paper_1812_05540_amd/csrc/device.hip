@@ -1099,10 +1099,21 @@ void Fgmres::enqueue_iteration() {
     }
     LAUNCH(k::reduce_rows, nv + 1, 0, st_, (const double *)K_.partial, K_.nblk, K_.h1, (const double *)nullptr,
            (double *)nullptr);
-    if (nv >= 22 && nv <= k::SUBDOT_MAXV) {          // below ~22 vectors two passes are faster
+    if (nv >= 16 && nv <= k::SUBDOT_MAXV) {          // below ~16 vectors two passes are as fast
         ktime::Scope ts(ktime::CGS2_FUSED, st_, (nv + 2) * vb);
-        LAUNCH(k::gemv_sub_mdot, K_.nblk, (size_t)nv * 65 * sizeof(double), st_, (const double *)K_.V, N, nv,
-               (const double *)K_.h1, w, N, K_.chunk, K_.partial, K_.nblk);
+        const size_t shm = (size_t)nv * 65 * sizeof(double);
+        if (nv <= 32)
+            LAUNCH((k::gemv_sub_mdot<8>), K_.nblk, shm, st_, (const double *)K_.V, N, nv, (const double *)K_.h1, w,
+                   N, K_.chunk, K_.partial, K_.nblk);
+        else if (nv <= 64)
+            LAUNCH((k::gemv_sub_mdot<16>), K_.nblk, shm, st_, (const double *)K_.V, N, nv, (const double *)K_.h1, w,
+                   N, K_.chunk, K_.partial, K_.nblk);
+        else if (nv <= 96)
+            LAUNCH((k::gemv_sub_mdot<24>), K_.nblk, shm, st_, (const double *)K_.V, N, nv, (const double *)K_.h1, w,
+                   N, K_.chunk, K_.partial, K_.nblk);
+        else
+            LAUNCH((k::gemv_sub_mdot<28>), K_.nblk, shm, st_, (const double *)K_.V, N, nv, (const double *)K_.h1, w,
+                   N, K_.chunk, K_.partial, K_.nblk);
     } else {
         LAUNCH((k::gemv_sub<false>), K_.nblk, 0, st_, (const double *)K_.V, N, nv, (const double *)K_.h1, w, N,
                K_.chunk, K_.partial);

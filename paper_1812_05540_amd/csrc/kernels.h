@@ -724,19 +724,19 @@ __global__ __launch_bounds__(512) void bilu_sub(SubLayout L, const T *__restrict
         for (int e = 0; e < NF; ++e) y[p * NF + e] = win[(size_t)c * NF + e];
     }
     __syncthreads();
-    // forward: t_p = w_p - sum_k L_pk t_k, in place.  Three register buffers rotate
-    // without copies (the loop is unrolled by three), so a level's loads have two
+    // forward: t_p = w_p - sum_k L_pk t_k, in place.  Four register buffers rotate
+    // without copies (the loop is unrolled by four), so a level's loads have three
     // levels' time to arrive.
     {
         const int nl = nfl - 1;
-        SubRow<T, NF, W> c0, c1, c2;
+        SubRow<T, NF, W> c0, c1, c2, c3;
         auto load = [&](SubRow<T, NF, W> &x, int l) {
             int r = l < nl ? lf[l] + tid : 0;
             sub_load(x, L.fcol, fval, N, r, l < nl && r < lf[l + 1]);
         };
         auto step = [&](int l, const SubRow<T, NF, W> &cur, SubRow<T, NF, W> &ahead) {
             const int r0 = lf[l], r1 = lf[l + 1];
-            load(ahead, l + 2);
+            load(ahead, l + 3);
             {
                 T acc[NF];
                 sub_acc(cur, y, n, acc);
@@ -757,16 +757,18 @@ __global__ __launch_bounds__(512) void bilu_sub(SubLayout L, const T *__restrict
         };
         load(c0, 0);
         load(c1, 1);
-        for (int l = 0; l < nl; l += 3) {
-            step(l, c0, c2);
+        load(c2, 2);
+        for (int l = 0; l < nl; l += 4) {
+            step(l, c0, c3);
             if (l + 1 < nl) step(l + 1, c1, c0);
             if (l + 2 < nl) step(l + 2, c2, c1);
+            if (l + 3 < nl) step(l + 3, c3, c2);
         }
     }
     // backward: delta_p = D_p^{-1} (t_p - sum_j U_pj delta_j), in place
     {
         const int nl = nbl - 1;
-        SubRowB<T, NF, W> c0, c1, c2;
+        SubRowB<T, NF, W> c0, c1, c2, c3;
         auto load = [&](SubRowB<T, NF, W> &x, int l) {
             int r = l < nl ? lb[l] + tid : 0;
             sub_load_b(x, L, bval, bdinv, N, r, l < nl && r < lb[l + 1]);
@@ -787,7 +789,7 @@ __global__ __launch_bounds__(512) void bilu_sub(SubLayout L, const T *__restrict
         };
         auto step = [&](int l, const SubRowB<T, NF, W> &cur, SubRowB<T, NF, W> &ahead) {
             const int r0 = lb[l], r1 = lb[l + 1];
-            load(ahead, l + 2);
+            load(ahead, l + 3);
             row(cur, r0 + tid < r1);
             for (int rr = r0 + tid + bs; rr < r1; rr += bs) {
                 SubRowB<T, NF, W> x;
@@ -798,10 +800,12 @@ __global__ __launch_bounds__(512) void bilu_sub(SubLayout L, const T *__restrict
         };
         load(c0, 0);
         load(c1, 1);
-        for (int l = 0; l < nl; l += 3) {
-            step(l, c0, c2);
+        load(c2, 2);
+        for (int l = 0; l < nl; l += 4) {
+            step(l, c0, c3);
             if (l + 1 < nl) step(l + 1, c1, c0);
             if (l + 2 < nl) step(l + 2, c2, c1);
+            if (l + 3 < nl) step(l + 3, c3, c2);
         }
     }
     for (int j = tid; j < n; j += bs) {
@@ -1059,8 +1063,11 @@ __global__ __launch_bounds__(WG) void gemv_sub(const double *__restrict__ V, siz
 // The middle of CGS2 in one pass over V: w -= V h (stored), then partial[k * nblk + blk] =
 // V_k . w over this block's chunk, for k < nv.  The chunk goes through LDS in tiles of
 // 64 elements x nv vectors (row stride 65 doubles), so each element of V is read from
-// HBM once for both products.  Dynamic LDS: nv * 65 doubles.
+// HBM once for both products; the next tile's rows are loaded into registers (RW rows
+// per wave, nv <= 4 RW) while the current tile is computed.  Loads past the chunk or past
+// nv repeat the last element / row (in bounds, unused).  Dynamic LDS: nv * 65 doubles.
 constexpr int SUBDOT_MAXV = 112;    // 112 x 65 doubles + static arrays < 64 KB of LDS
+template <int RW>
 __global__ __launch_bounds__(WG) void gemv_sub_mdot(const double *__restrict__ V, size_t ldv, int nv,
                                                    const double *__restrict__ h, double *__restrict__ w,
                                                    size_t n, int chunk, double *__restrict__ partial,
@@ -1074,26 +1081,27 @@ __global__ __launch_bounds__(WG) void gemv_sub_mdot(const double *__restrict__ V
     const size_t i0 = (size_t)blockIdx.x * chunk;
     const int len = i0 < n ? (int)((n - i0) < (size_t)chunk ? (n - i0) : (size_t)chunk) : 0;
     double acc = 0.0;
+    double r[RW];
+    auto load = [&](int e0) {
+        const int ne = len - e0 < 64 ? len - e0 : 64;
+        const int el = lane < ne ? lane : ne - 1;
+#pragma unroll
+        for (int q = 0; q < RW; ++q) {
+            const int k = wid + 4 * q < nv ? wid + 4 * q : nv - 1;
+            r[q] = V[(size_t)k * ldv + i0 + e0 + el];
+        }
+    };
+    if (len > 0) load(0);
     __syncthreads();
     for (int e0 = 0; e0 < len; e0 += 64) {
         const int ne = len - e0 < 64 ? len - e0 : 64;
-        // 16 rows per wave per batch, loaded before any is stored (loads in flight);
-        // indices clamped so that every load is in bounds and unconditional
-        const int el = lane < ne ? lane : ne - 1;
-        for (int kb = wid; kb < nv; kb += 64) {
-            double r[16];
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int k = kb + 4 * q < nv ? kb + 4 * q : nv - 1;
-                r[q] = V[(size_t)k * ldv + i0 + e0 + el];
-            }
-#pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int k = kb + 4 * q;
-                if (k < nv) tile[k * 65 + lane] = lane < ne ? r[q] : 0.0;
-            }
+        for (int q = 0; q < RW; ++q) {
+            const int k = wid + 4 * q;
+            if (k < nv) tile[k * 65 + lane] = lane < ne ? r[q] : 0.0;
         }
         __syncthreads();
+        if (e0 + 64 < len) load(e0 + 64);
         double s = 0.0;
         for (int k = wid; k < nv; k += 4) s += tile[k * 65 + lane] * hs[k];
         part[wid][lane] = s;
