@@ -299,7 +299,11 @@ def run_serving(args, pool):
                     r = ps.ps_wait(ctx, sv.submit(b, x, args.rtol, stream))
                     sv.close()
                     status[q], iters[q] = r["status"], r["iterations"]
+                    if r["status"] != ps.PS_OK:
+                        log("serving request %d (%d^3): status %d after %d iterations, residual %.3g" %
+                            (i, n, r["status"], r["iterations"], r["rel_residual"]))
                 except ps.PsError as e:
+                    log("serving request %d (%d^3) failed: %s" % (i, n, e))
                     status[q] = e.code
                 except Exception as e:            # recorded as a failed request
                     log("serving request %d failed: %r" % (i, e))
