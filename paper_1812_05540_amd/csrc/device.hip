@@ -186,15 +186,58 @@ Sell<T> upload_sell(Arena &ar, const HostSell &h) {
     return s;
 }
 
-template <typename T>
-static DCsr<T> upload_csr(Arena &ar, const Csr &A) {
-    DCsr<T> d;
-    d.n = A.n;
-    double avg = A.n ? (double)A.nnz() / A.n : 1.0;
+// An operator takes the SELL-64 form (one lane per row, coalesced loads) when its 64-row
+// slices pad it to at most 1.5 stored slots per entry, its rows average at most 32 entries
+// and it has at least 2^17 rows (2048 wavefronts); otherwise one lane per row leaves too
+// few wavefronts with too long a chain of loads each, and CSR with G lanes per row is
+// faster on MI355X.  PS_SELL=all puts every operator in SELL-64, PS_SELL=off none.
+static int sell_mode() {                 // 0 by the rule above, 1 all, -1 none
+    const char *e = std::getenv("PS_SELL");
+    if (!e) return 0;
+    if (std::string(e) == "all") return 1;
+    if (std::string(e) == "off") return -1;
+    return 0;
+}
+
+// Stored slots per entry of the SELL-64 form of an n-row matrix with nnz entries whose
+// slices have widths w.
+static double sell_padding(const int *w, int n, size_t nnz) {
+    size_t slots = 0;
+    for (int s = 0; s < (n + 63) / 64; ++s) slots += (size_t)w[s] * 64;
+    return nnz ? (double)slots / nnz : 1e30;
+}
+
+static bool take_sell(double pad, int n, size_t nnz) {
+    const int mode = sell_mode();
+    if (mode < 0 || pad * nnz >= 2e9) return false;
+    return mode > 0 || (pad <= 1.5 && n >= (1 << 17) && nnz <= (size_t)32 * n);
+}
+
+static int lanes_per_row(int n, size_t nnz) {
+    double avg = n ? (double)nnz / n : 1.0;
     int G = 1;
     while (G < 32 && G * 3 < avg) G *= 2;
-    d.G = G;
+    return G;
+}
+
+// sell: an operator A, which may take SELL-64 (P and R stay CSR)
+template <typename T>
+static DCsr<T> upload_csr(Arena &ar, const Csr &A, bool sell) {
+    DCsr<T> d;
+    d.n = A.n;
+    d.G = lanes_per_row(A.n, A.nnz());
     d.rp = ar.upload(A.rp.data(), A.rp.size());
+    std::vector<int> w((A.n + 63) / 64, 0);
+    for (int i = 0; i < A.n; ++i) w[i >> 6] = std::max(w[i >> 6], A.rp[i + 1] - A.rp[i]);
+    if (sell && A.n && take_sell(sell_padding(w.data(), A.n, A.nnz()), A.n, A.nnz())) {
+        HostSell h = sell_from_bsr(A.rp, A.ci, A.v, A.n, 1, 1);
+        d.G = 0;
+        d.cptr = ar.upload(h.cptr.data(), h.cptr.size());
+        d.ci = ar.upload(h.col.data(), h.col.size());
+        std::vector<T> v(h.val.begin(), h.val.end());
+        d.v = ar.upload(v.data(), v.size());
+        return d;
+    }
     d.ci = ar.upload(A.ci.data(), A.ci.size());
     std::vector<T> v(A.v.begin(), A.v.end());
     d.v = ar.upload(v.data(), v.size());
@@ -270,9 +313,9 @@ void upload_hierarchy_into(DHierarchy<T> &dh, const Hierarchy &H, int smoother, 
             std::vector<double> dl1 = L.dl1, c0 = L.c0, c1 = L.c1, cm = L.cm;
             interleave_level0(A, P, R, {&dl1, &c0, &c1, &cm});
             D.n = A.n;
-            D.A = upload_csr<T>(d->arena, A);
-            D.P = upload_csr<T>(d->arena, P);
-            D.R = upload_csr<T>(d->arena, R);
+            D.A = upload_csr<T>(d->arena, A, true);
+            D.P = upload_csr<T>(d->arena, P, false);
+            D.R = upload_csr<T>(d->arena, R, false);
             if (smoother == PS_L1JAC) {
                 std::vector<double> inv(dl1.size());
                 for (size_t i = 0; i < dl1.size(); ++i) inv[i] = 1.0 / dl1[i];
@@ -285,9 +328,9 @@ void upload_hierarchy_into(DHierarchy<T> &dh, const Hierarchy &H, int smoother, 
             continue;
         }
         D.n = L.A.n;
-        D.A = upload_csr<T>(d->arena, L.A);
-        D.P = upload_csr<T>(d->arena, L.P);
-        D.R = upload_csr<T>(d->arena, L.R);
+        D.A = upload_csr<T>(d->arena, L.A, true);
+        D.P = upload_csr<T>(d->arena, L.P, false);
+        D.R = upload_csr<T>(d->arena, L.R, false);
         if (smoother == PS_L1JAC) {
             std::vector<double> inv(L.dl1.size());
             for (size_t i = 0; i < L.dl1.size(); ++i) inv[i] = 1.0 / L.dl1[i];
@@ -563,15 +606,29 @@ static bool layout_sub_bilu(DFlow<T> &d, const FlowSetup &f, const System &s) {
 
 // A level matrix of the device-built pressure hierarchy as a kernel operand: index arrays
 // shared, values shared (FP64) or converted (FP32).
+// w: slice widths of an operator A (which may then take SELL-64, built on the device), or
+// null for P and R.
 template <typename T>
-static DCsr<T> adopt_csr(Arena &ar, const DevCsr &c) {
+static DCsr<T> adopt_csr(Arena &ar, const DevCsr &c, const int *w) {
     DCsr<T> d;
     d.n = c.n;
-    double avg = c.n ? (double)c.nnz / c.n : 1.0;
-    int G = 1;
-    while (G < 32 && G * 3 < avg) G *= 2;
-    d.G = G;
+    d.G = lanes_per_row(c.n, c.nnz);
     d.rp = c.rp;
+    if (w && c.n && take_sell(sell_padding(w, c.n, c.nnz), c.n, c.nnz)) {
+        const int ns = (c.n + 63) / 64;
+        std::vector<int> cptr(ns + 1, 0);
+        for (int s = 0; s < ns; ++s) cptr[s + 1] = cptr[s] + w[s];
+        const size_t slots = (size_t)cptr[ns] * 64;
+        int *sci = ar.template alloc<int>(slots);
+        T *sv = ar.template alloc<T>(slots);
+        const int *dcp = ar.upload(cptr.data(), cptr.size());
+        LAUNCH((k::csr_to_sell<T>), grid_for((size_t)c.n), 0, 0, c.rp, c.ci, c.v, c.n, dcp, sci, sv);
+        d.G = 0;
+        d.cptr = dcp;
+        d.ci = sci;
+        d.v = sv;
+        return d;
+    }
     d.ci = c.ci;
     if constexpr (sizeof(T) == 8) {
         d.v = c.v;
@@ -590,13 +647,27 @@ static void adopt_hierarchy(DHierarchy<T> &d, const Hierarchy &H, const PresStor
     const int nl = (int)H.lev.size();
     if ((int)S.A.size() != nl || (int)S.P.size() != nl - 1) throw Error(PS_EDEVICE, "pressure hierarchy mismatch");
     d.lev.assign(nl, DLevel<T>());
+    // slice widths of every level operator, in one copy to the host
+    std::vector<size_t> woff(nl, 0);
+    size_t nw = 0;
+    for (int l = 0; l + 1 < nl; ++l) {
+        woff[l] = nw;
+        nw += ((size_t)S.A[l].n + 63) / 64;
+    }
+    std::vector<int> hw(nw);
+    if (nw) {
+        int *dw = d.arena.template alloc<int>(nw);
+        for (int l = 0; l + 1 < nl; ++l)
+            LAUNCH(k::slice_width, grid_for(((size_t)S.A[l].n + 63) / 64), 0, 0, S.A[l].rp, S.A[l].n, dw + woff[l]);
+        PS_HIP(hipMemcpy(hw.data(), dw, nw * sizeof(int), hipMemcpyDeviceToHost));
+    }
     for (int l = 0; l + 1 < nl; ++l) {
         const Level &L = H.lev[l];
         DLevel<T> &D = d.lev[l];
         D.n = L.A.n;
-        D.A = adopt_csr<T>(d.arena, S.A[l]);
-        D.P = adopt_csr<T>(d.arena, S.P[l]);
-        D.R = adopt_csr<T>(d.arena, S.R[l]);
+        D.A = adopt_csr<T>(d.arena, S.A[l], hw.data() + woff[l]);
+        D.P = adopt_csr<T>(d.arena, S.P[l], nullptr);
+        D.R = adopt_csr<T>(d.arena, S.R[l], nullptr);
         if (S.on_device) {
             if constexpr (sizeof(T) == 8) {
                 D.dinv = S.dinv[l];
@@ -756,6 +827,7 @@ void alloc_prec_work(PrecWork<T> &w, const DHierarchy<T> &sdc, const DFlow<T> &f
 template <typename F>
 static void with_G(int G, F &&f) {
     switch (G) {
+    case 0: f(std::integral_constant<int, 0>{}); break;
     case 1: f(std::integral_constant<int, 1>{}); break;
     case 2: f(std::integral_constant<int, 2>{}); break;
     case 4: f(std::integral_constant<int, 4>{}); break;
@@ -769,7 +841,7 @@ template <int MODE, typename T>
 static void csr_spmv(const DCsr<T> &A, const T *x, const T *b, T *y, hipStream_t st) {
     with_G(A.G, [&](auto Gc) {
         constexpr int G = decltype(Gc)::value;
-        LAUNCH((k::csr_spmv<G, MODE, T>), grid_for((size_t)A.n * G), 0, st, A, x, b, y);
+        LAUNCH((k::csr_spmv<G, MODE, T>), grid_for((size_t)A.n * (G ? G : 1)), 0, st, A, x, b, y);
     });
 }
 
@@ -785,20 +857,30 @@ static void vcycle(const DHierarchy<T> &H, HierWork<T> &W, int l, const T *b, T 
     const bool cheb = H.smoother == PS_CHEB2;
     with_G(L.A.G, [&](auto Gc) {
         constexpr int G = decltype(Gc)::value;
-        unsigned g = grid_for((size_t)L.n * G);
+        unsigned g = grid_for((size_t)L.n * (G ? G : 1));
         if (cheb) {
             LAUNCH((k::csr_cheb_pre<G, T>), g, 0, st, L.A, b, L.c0, L.c1, L.cm, W.x[l]);
+            LAUNCH((k::csr_spmv<G, 1, T>), g, 0, st, L.A, (const T *)W.x[l], b, W.r[l]);
+        } else if (l > 0) {                 // x = D^-1 b was written with b by the restriction
             LAUNCH((k::csr_spmv<G, 1, T>), g, 0, st, L.A, (const T *)W.x[l], b, W.r[l]);
         } else {
             LAUNCH((k::csr_l1_pre<G, T>), g, 0, st, L.A, b, L.dinv, W.x[l], W.r[l]);
         }
     });
-    csr_spmv<0, T>(L.R, (const T *)W.r[l], (const T *)nullptr, W.b[l + 1], st);
+    if (!cheb && l + 1 < last) {
+        with_G(L.R.G, [&](auto Gc) {
+            constexpr int G = decltype(Gc)::value;
+            LAUNCH((k::csr_restrict_l1<G, T>), grid_for((size_t)L.R.n * (G ? G : 1)), 0, st, L.R,
+                   (const T *)W.r[l], H.lev[l + 1].dinv, W.b[l + 1], W.x[l + 1]);
+        });
+    } else {
+        csr_spmv<0, T>(L.R, (const T *)W.r[l], (const T *)nullptr, W.b[l + 1], st);
+    }
     vcycle(H, W, l + 1, W.b[l + 1], W.e[l + 1], st);
     csr_spmv<2, T>(L.P, (const T *)W.e[l + 1], (const T *)nullptr, W.x[l], st);
     with_G(L.A.G, [&](auto Gc) {
         constexpr int G = decltype(Gc)::value;
-        unsigned g = grid_for((size_t)L.n * G);
+        unsigned g = grid_for((size_t)L.n * (G ? G : 1));
         if (cheb) {
             LAUNCH((k::csr_cheb_post1<G, T>), g, 0, st, L.A, b, (const T *)W.x[l], L.c0, W.x1[l], W.d[l]);
             LAUNCH((k::csr_cheb_post2<G, T>), g, 0, st, L.A, b, (const T *)W.x1[l], (const T *)W.d[l], L.c1,

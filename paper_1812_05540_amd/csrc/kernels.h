@@ -235,9 +235,64 @@ __global__ __launch_bounds__(WG) void coarse_solve(const double *__restrict__ Ai
 // consecutive rows, so a wavefront reads one contiguous stretch of ci/v.
 template <int G, typename T>
 __device__ __forceinline__ T group_sum(T a) {
+    if constexpr (G <= 1) return a;
 #pragma unroll
     for (int off = G / 2; off > 0; off >>= 1) a += __shfl_xor(a, off, G);
     return a;
+}
+
+// SELL-64 row (G == 0): the lane owns row i and adds its entries in order; a wavefront's
+// loads of entry k of its 64 rows are one contiguous stretch, and on a stencil-like level
+// so are the gathers of x.  Four entries are loaded before any is used; past the row's
+// end the loads repeat its last entry and are not added.
+template <bool S, typename T>
+__device__ __forceinline__ T sell_dot(const DCsr<T> &A, int i, const T *__restrict__ x,
+                                      const T *__restrict__ s) {
+    const int len = A.rp[i + 1] - A.rp[i];
+    const size_t base = (size_t)A.cptr[i >> 6] * 64 + (i & 63);
+    const int *__restrict__ ci = A.ci + base;
+    const T *__restrict__ v = A.v + base;
+    T acc = T(0);
+    for (int k = 0; k < len; k += 4) {
+        int c[4];
+        T a[4], xv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int kk = k + u < len ? k + u : len - 1;
+            c[u] = ci[kk * 64];
+            a[u] = v[kk * 64];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) xv[u] = S ? x[c[u]] * s[c[u]] : x[c[u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (k + u < len) acc += a[u] * xv[u];
+    }
+    return acc;
+}
+
+// Setup: the longest row of each 64-row slice.
+__global__ __launch_bounds__(WG) void slice_width(const int *__restrict__ rp, int n, int *__restrict__ w) {
+    const int s = blockIdx.x * WG + threadIdx.x;
+    if (s >= (n + 63) / 64) return;
+    int m = 0;
+    for (int i = s * 64; i < n && i < s * 64 + 64; ++i) m = max(m, rp[i + 1] - rp[i]);
+    w[s] = m;
+}
+
+// Setup: CSR (FP64 values) into SELL-64 slots; padding slots are left as they are.
+template <typename T>
+__global__ __launch_bounds__(WG) void csr_to_sell(const int *__restrict__ rp, const int *__restrict__ ci,
+                                                 const double *__restrict__ v, int n,
+                                                 const int *__restrict__ cptr, int *__restrict__ sci,
+                                                 T *__restrict__ sv) {
+    const int i = blockIdx.x * WG + threadIdx.x;
+    if (i >= n) return;
+    const size_t base = (size_t)cptr[i >> 6] * 64 + (i & 63);
+    for (int t = rp[i], k = 0; t < rp[i + 1]; ++t, ++k) {
+        sci[base + (size_t)k * 64] = ci[t];
+        sv[base + (size_t)k * 64] = (T)v[t];
+    }
 }
 
 // sum_j a_ij x_j (or a_ij x_j s_j when S) for the calling group's row
@@ -247,29 +302,34 @@ __device__ __forceinline__ T group_sum(T a) {
 template <int G, bool S, typename T>
 __device__ __forceinline__ T csr_dot(const DCsr<T> &A, int i, int g, const T *__restrict__ x,
                                      const T *__restrict__ s) {
-    T acc = T(0);
-    const int e = A.rp[i + 1];
-    for (int t = A.rp[i] + g; t < e; t += 4 * G) {
-        int c[4];
-        T a[4], xv[4];
+    if constexpr (G == 0) {
+        return sell_dot<S>(A, i, x, s);
+    } else {
+        T acc = T(0);
+        const int e = A.rp[i + 1];
+        for (int t = A.rp[i] + g; t < e; t += 4 * G) {
+            int c[4];
+            T a[4], xv[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int tt = t + u * G < e ? t + u * G : e - 1;
-            c[u] = A.ci[tt];
-            a[u] = A.v[tt];
+            for (int u = 0; u < 4; ++u) {
+                const int tt = t + u * G < e ? t + u * G : e - 1;
+                c[u] = A.ci[tt];
+                a[u] = A.v[tt];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) xv[u] = S ? x[c[u]] * s[c[u]] : x[c[u]];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (t + u * G < e) acc += a[u] * xv[u];
         }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) xv[u] = S ? x[c[u]] * s[c[u]] : x[c[u]];
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (t + u * G < e) acc += a[u] * xv[u];
+        return group_sum<G>(acc);
     }
-    return group_sum<G>(acc);
 }
 
 #define PS_CSR_ROW(G)                                         \
+    constexpr int LPR_ = G ? G : 1;                           \
     int gid = blockIdx.x * WG + threadIdx.x;                  \
-    int i = gid / G, g = gid % G;                             \
+    int i = gid / LPR_, g = gid % LPR_;                       \
     if (i >= A.n) return;
 
 // y = A x (0), b - A x (1), y + A x (2)
@@ -279,6 +339,20 @@ __global__ __launch_bounds__(WG) void csr_spmv(DCsr<T> A, const T *__restrict__ 
     PS_CSR_ROW(G)
     T a = csr_dot<G, false>(A, i, g, x, x);
     if (g == 0) y[i] = MODE == 0 ? a : MODE == 1 ? b[i] - a : y[i] + a;
+}
+
+// Restriction to a level below which the V-cycle goes on (l1-Jacobi): b = R r, and that
+// level's first smoothing step x = D^-1 b, so its pre-smoother gathers one vector.
+template <int G, typename T>
+__global__ __launch_bounds__(WG) void csr_restrict_l1(DCsr<T> A, const T *__restrict__ r,
+                                                     const T *__restrict__ dinv, T *__restrict__ b,
+                                                     T *__restrict__ x) {
+    PS_CSR_ROW(G)
+    T a = csr_dot<G, false>(A, i, g, r, r);
+    if (g == 0) {
+        b[i] = a;
+        x[i] = a * dinv[i];
+    }
 }
 
 template <int G, typename T>

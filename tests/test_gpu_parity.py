@@ -112,6 +112,26 @@ def test_precond_fp64_matches_oracle(ctx, name, opts):
     sv.close()
 
 
+@pytest.mark.parametrize("layout", ["all", "off"])
+@pytest.mark.parametrize("name,opts", [("grf12", dict()), ("grf12", dict(smoother=ps.PS_L1JAC)),
+                                       ("iid3ph", dict(smoother=ps.PS_L1JAC))])
+def test_level_layouts_match_oracle(ctx, name, opts, layout, monkeypatch):
+    """Every AMG operator in SELL-64 (one lane per row), or every one in CSR (G lanes per
+    row): both give the oracle's preconditioner, in FP64 and in FP32."""
+    monkeypatch.setenv("PS_SELL", layout)
+    s, _ = small(name)
+    st = P.setup(s, oracle_opts(**opts))
+    v = np.random.default_rng(4).standard_normal(s.N)
+    ref = P.apply_precond(st, v)
+    for prec, tol in ((ps.PS_FP64, 1e-10), (ps.PS_FP32_PREC, 1e-3)):
+        sv = make_solver(ctx, s, precision=prec, **opts)
+        z = dev(np.zeros(s.N))
+        sv.apply_precond(dev(v), z)
+        err = np.linalg.norm(host(z) - ref) / np.linalg.norm(ref)
+        assert err <= tol, (prec, err)
+        sv.close()
+
+
 @pytest.mark.parametrize("name", ["iid8", "grf12"])
 def test_precond_fp32_close_to_fp64(ctx, name):
     s, _ = small(name)
