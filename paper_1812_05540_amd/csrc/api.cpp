@@ -330,16 +330,33 @@ int ps_setup(ps_handle *h) {
             ensure_mech_device(h, f64, f32);
         }
         const bool dev_rap = galerkin_on_device();
+        // layouts (first call) and values of the flow stage that do not depend on the
+        // pressure hierarchy, for the precisions in use
+        auto flow_values = [&] {
+            PhaseTimer pt("flow values upload");
+            if (f64) {
+                if (!h->fl64) h->fl64 = std::make_unique<DFlow<double>>();
+                update_flow_values<double>(*h->fl64, h->flow, h->sys, h->dsys, h->opt, h->staging, h->afu_changed);
+            }
+            if (f32) {
+                if (!h->fl32) h->fl32 = std::make_unique<DFlow<float>>();
+                update_flow_values<float>(*h->fl32, h->flow, h->sys, h->dsys, h->opt, h->staging, h->afu_changed);
+            }
+        };
         {
             PhaseTimer pt("flow setup");
             build_flow_operators(h->sys, h->flow);
             if (dev_rap) {
-                // local-stage factors on a host thread while the pressure hierarchy is built
-                // (host coarsening, device Galerkin products)
+                // local-stage factors and the flow-stage value uploads on a host thread
+                // while the pressure hierarchy is built (its own copies run on the null
+                // stream, the uploads on the staging buffer's stream)
                 std::exception_ptr err;
+                const int dev = h->ctx->device;
                 std::thread local([&] {
                     try {
+                        set_device(dev);
                         build_flow_local(h->sys, h->opt, h->flow);
+                        flow_values();
                     } catch (...) {
                         err = std::current_exception();
                     }
@@ -360,18 +377,17 @@ int ps_setup(ps_handle *h) {
                     h->flow.pres = amg_build(h->flow.Spp, h->opt);
                 }
                 build_flow_local(h->sys, h->opt, h->flow);
+                flow_values();
             }
         }
         const PresStore *ps = dev_rap ? &h->pstore : nullptr;
-        PhaseTimer pt("flow upload + work");
+        PhaseTimer pt("pressure levels + work");
         if (f64) {
-            if (!h->fl64) h->fl64 = std::make_unique<DFlow<double>>();
-            update_flow<double>(*h->fl64, h->flow, h->sys, h->opt, h->staging, h->afu_changed, ps);
+            update_flow_pressure<double>(*h->fl64, h->flow, h->opt, ps);
             alloc_prec_work(h->w64, *h->mech->d64, *h->fl64, h->sys.n_nodes);
         }
         if (f32) {
-            if (!h->fl32) h->fl32 = std::make_unique<DFlow<float>>();
-            update_flow<float>(*h->fl32, h->flow, h->sys, h->opt, h->staging, h->afu_changed, ps);
+            update_flow_pressure<float>(*h->fl32, h->flow, h->opt, ps);
             alloc_prec_work(h->w32, *h->mech->d32, *h->fl32, h->sys.n_nodes);
         }
         h->afu_changed = false;

@@ -206,6 +206,8 @@ struct DFlow {                    // flow stage of Algorithm 1 on the device
     std::vector<int> src_afu, src_sff, src_lf, src_ub;   // value source maps (host)
     std::vector<int> lchunk_f, lchunk_b;                 // chunk ranges per level / colour
     const int *d_lchunk_f = nullptr, *d_lchunk_b = nullptr;
+    const int *sff_dslot = nullptr;   // slot of each row's diagonal block in Sff (-1: padding lane)
+    double *d_fs = nullptr;       // fixed-stress terms d_sp (nc * (nf-1)) then d_pp (nc)
     T *dss_inv = nullptr;         // nc * (nf-1)^2
     T *dinv = nullptr;            // BILU D_i^{-1} or block-diagonal inverse, nc * nf * nf
     bool sub = false;             // BILU applied by the subdomain-resident kernel
@@ -215,11 +217,23 @@ struct DFlow {                    // flow stage of Algorithm 1 on the device
     size_t bytes() const { return arena.bytes() + (pres ? pres->bytes() : 0); }
 };
 
-// Pinned host buffer for value uploads.
+// PS_TRACE=1: a setup phase prints its wall time (and a note) to stderr when it ends.
+struct TraceTick {
+    const char *what;
+    double t0;
+    int note = -1;                // printed when >= 0 (e.g. host-device round trips)
+    explicit TraceTick(const char *w);
+    ~TraceTick();
+};
+
+// Pinned host buffer for value uploads, and the (non-blocking) stream its copies use, so
+// that uploads from a setup thread do not wait on work queued on the null stream.
 struct Staging {
     void *p = nullptr;
     size_t bytes = 0;
+    hipStream_t st = nullptr;
     void *get(size_t n);
+    void copy_to_device(void *dev, const void *host, size_t n);   // returns when done
     ~Staging();
 };
 
@@ -282,10 +296,15 @@ template <typename T>
 std::unique_ptr<DHierarchy<T>> upload_hierarchy(const Hierarchy &H, int smoother, bool interleave3);
 template <typename T>
 void upload_hierarchy_into(DHierarchy<T> &d, const Hierarchy &H, int smoother, bool interleave3);
-// ps: device copies of the pressure hierarchy (adopted, not uploaded), or nullptr.
+// Flow stage of a setup in two parts: the layouts (first call) and values of A_fu, S_ff,
+// D_ss and the local-stage factors, which do not depend on the pressure hierarchy (S: the
+// system on the device, whose A_ff gives S_ff's values); then the pressure levels (ps:
+// device copies of the pressure hierarchy, adopted rather than uploaded, or nullptr).
 template <typename T>
-void update_flow(DFlow<T> &d, const FlowSetup &f, const System &s, const Options &o, Staging &stg,
-                 bool afu_changed, const PresStore *ps);
+void update_flow_values(DFlow<T> &d, const FlowSetup &f, const System &s, const DSystem &S, const Options &o,
+                        Staging &stg, bool afu_changed);
+template <typename T>
+void update_flow_pressure(DFlow<T> &d, const FlowSetup &f, const Options &o, const PresStore *ps);
 void upload_system(const System &s, DSystem &d);
 template <typename T>
 void alloc_prec_work(PrecWork<T> &w, const DHierarchy<T> &sdc, const DFlow<T> &fl, int n_nodes);

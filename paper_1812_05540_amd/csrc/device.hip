@@ -1,6 +1,8 @@
 // Device data layout, uploads and the solve-phase drivers (Algorithm 1, FGMRES).
 #include <algorithm>
 #include <atomic>
+#include <chrono>
+#include <cstdio>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -111,6 +113,27 @@ void totals(int id, long long &launches, double &seconds, double &bytes) {
     bytes = g_bytes[id];
 }
 }  // namespace ktime
+
+// ------------------------------------------------------------------ setup tracing
+static bool trace_setup() {
+    static const bool on = [] {
+        const char *e = std::getenv("PS_TRACE");
+        return e && *e && *e != '0';
+    }();
+    return on;
+}
+
+static double wall_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+TraceTick::TraceTick(const char *w) : what(w), t0(wall_s()) {}
+
+TraceTick::~TraceTick() {
+    if (!trace_setup()) return;
+    if (note >= 0) std::fprintf(stderr, "[ps]     %-24s %8.2f ms  (%d)\n", what, 1e3 * (wall_s() - t0), note);
+    else std::fprintf(stderr, "[ps]     %-24s %8.2f ms\n", what, 1e3 * (wall_s() - t0));
+}
 
 // ------------------------------------------------------------------ SELL
 HostSell sell_from_bsr(const std::vector<int> &rp, const std::vector<int> &ci, const std::vector<double> &v,
@@ -367,7 +390,15 @@ void *Staging::get(size_t n) {
     return p;
 }
 
+void Staging::copy_to_device(void *dev, const void *host, size_t n) {
+    if (!n) return;
+    if (!st) PS_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    PS_HIP(hipMemcpyAsync(dev, host, n, hipMemcpyHostToDevice, st));
+    PS_HIP(hipStreamSynchronize(st));
+}
+
 Staging::~Staging() {
+    if (st) (void)hipStreamDestroy(st);
     if (p) (void)hipHostFree(p);
 }
 
@@ -387,7 +418,7 @@ static void upload_values(T *dev, const std::vector<int> &src, int rc, const std
                     out[((size_t)s * rc + q) * 64 + l] = t < 0 ? T(0) : (T)v[(size_t)t * rc + q];
             }
     });
-    PS_HIP(hipMemcpy(dev, out, nslots * 64 * rc * sizeof(T), hipMemcpyHostToDevice));
+    stg.copy_to_device(dev, out, nslots * 64 * rc * sizeof(T));
 }
 
 template <typename T>
@@ -397,7 +428,7 @@ static void upload_dense(T *dev, const std::vector<double> &v, Staging &stg) {
     parallel_for((int)v.size(), [&](int b, int e, int) {
         for (int i = b; i < e; ++i) out[i] = (T)v[i];
     });
-    PS_HIP(hipMemcpy(dev, out, v.size() * sizeof(T), hipMemcpyHostToDevice));
+    stg.copy_to_device(dev, out, v.size() * sizeof(T));
 }
 
 template <typename T>
@@ -425,14 +456,14 @@ static void upload_ell(T *dev, const std::vector<int> &src, int W, int N, int rc
     if (n == 0) return;
     T *out = static_cast<T *>(stg.get(n * sizeof(T)));
     parallel_for(N, [&](int b, int e, int) {
-        for (int s = 0; s < W; ++s)
-            for (int q = 0; q < rc; ++q)
-                for (int r = b; r < e; ++r) {
-                    int t = src[(size_t)s * N + r];
+        for (int r = b; r < e; ++r)             // a block's rc values are read together
+            for (int s = 0; s < W; ++s) {
+                const int t = src[(size_t)s * N + r];
+                for (int q = 0; q < rc; ++q)
                     out[((size_t)s * rc + q) * N + r] = t < 0 ? T(0) : (T)v[(size_t)t * rc + q];
-                }
+            }
     });
-    PS_HIP(hipMemcpy(dev, out, n * sizeof(T), hipMemcpyHostToDevice));
+    stg.copy_to_device(dev, out, n * sizeof(T));
 }
 
 static bool bilu_levels_forced() {
@@ -694,8 +725,8 @@ static void adopt_hierarchy(DHierarchy<T> &d, const Hierarchy &H, const PresStor
 }
 
 template <typename T>
-void update_flow(DFlow<T> &d, const FlowSetup &f, const System &s, const Options &o, Staging &stg,
-                 bool afu_changed, const PresStore *ps) {
+void update_flow_values(DFlow<T> &d, const FlowSetup &f, const System &s, const DSystem &S, const Options &o,
+                        Staging &stg, bool afu_changed) {
     const int nf = s.nf, nc = s.n_cells, nn = nf * nf;
     static const std::vector<double> none;
     if (!d.layout) {
@@ -705,8 +736,27 @@ void update_flow(DFlow<T> &d, const FlowSetup &f, const System &s, const Options
         d.ml_sweeps = o.ml_sweeps;
         d.Afu = layout_sell<T>(d.arena, sell_from_bsr(s.Afu.rp, s.Afu.ci, none, nc, nf, 3, nullptr, nullptr, false),
                                d.afu_val, d.src_afu);
-        d.Sff = layout_sell<T>(d.arena, sell_from_bsr(f.Sff.rp, f.Sff.ci, none, nc, nf, nf, nullptr, nullptr, false),
-                               d.sff_val, d.src_sff);
+        {
+            HostSell hs = sell_from_bsr(f.Sff.rp, f.Sff.ci, none, nc, nf, nf, nullptr, nullptr, false);
+            d.Sff = layout_sell<T>(d.arena, hs, d.sff_val, d.src_sff);
+            // S_ff is formed on the device from A_ff when both have the same SELL layout
+            if (S.Aff.nchunks == hs.nchunks && S.Aff.nslots == d.Sff.nslots && f.Sff.rp == s.Aff.rp &&
+                f.Sff.ci == s.Aff.ci) {
+                std::vector<int> dslot((size_t)hs.nchunks * 64, -1);
+                for (int i = 0; i < nc; ++i) {
+                    const int ch = i >> 6, lane = i & 63;
+                    for (int k = hs.cptr[ch]; k < hs.cptr[ch + 1]; ++k) {
+                        const int t = hs.src[(size_t)k * 64 + lane];
+                        if (t >= 0 && f.Sff.ci[t] == i) {
+                            dslot[i] = k - hs.cptr[ch];
+                            break;
+                        }
+                    }
+                }
+                d.sff_dslot = d.arena.upload(dslot.data(), dslot.size());
+                d.d_fs = d.arena.template alloc<double>((size_t)nc * nf);
+            }
+        }
         auto order = [&](const std::vector<int> &ptr, const std::vector<int> &rows, std::vector<int> &lchunk) {
             std::vector<int> ord;
             lchunk.assign(1, 0);
@@ -739,11 +789,31 @@ void update_flow(DFlow<T> &d, const FlowSetup &f, const System &s, const Options
         d.layout = true;
         afu_changed = true;
     }
-    if (afu_changed) upload_values(d.afu_val, d.src_afu, nf * 3, s.Afu.v, stg);
-    upload_values(d.sff_val, d.src_sff, nn, f.Sff.v, stg);
-    upload_dense(d.dss_inv, f.dss_inv, stg);
+    {
+        TraceTick tt("values A_fu, S_ff, D_ss");
+        if (afu_changed) upload_values(d.afu_val, d.src_afu, nf * 3, s.Afu.v, stg);
+        if (d.sff_dslot) {
+            const size_t nsp = (size_t)nc * (nf - 1);
+            double *h = static_cast<double *>(stg.get((size_t)nc * nf * sizeof(double)));
+            std::memcpy(h, s.d_sp.data(), nsp * sizeof(double));
+            std::memcpy(h + nsp, s.d_pp.data(), (size_t)nc * sizeof(double));
+            stg.copy_to_device(d.d_fs, h, (size_t)nc * nf * sizeof(double));
+            const unsigned g = grid_for((size_t)S.Aff.nchunks * 64);
+            if (nf == 2)
+                LAUNCH((k::sff_from_aff<2, T>), g, 0, stg.st, S.Aff, (const double *)d.d_fs,
+                       (const double *)d.d_fs + nsp, d.sff_dslot, d.sff_val);
+            else
+                LAUNCH((k::sff_from_aff<3, T>), g, 0, stg.st, S.Aff, (const double *)d.d_fs,
+                       (const double *)d.d_fs + nsp, d.sff_dslot, d.sff_val);
+            PS_HIP(hipStreamSynchronize(stg.st));
+        } else {
+            upload_values(d.sff_val, d.src_sff, nn, f.Sff.v, stg);
+        }
+        upload_dense(d.dss_inv, f.dss_inv, stg);
+    }
     std::vector<double> dinv((size_t)nc * nn);
     if (d.sub) {
+        TraceTick tt("values subdomain BILU");
         const SubBilu<T> &b = d.sb;
         upload_ell(b.fval, b.fsrc, b.W, nc, nn, f.ml.v, stg);
         upload_ell(b.bval, b.bsrc, b.W, nc, nn, f.ml.v, stg);
@@ -762,6 +832,11 @@ void update_flow(DFlow<T> &d, const FlowSetup &f, const System &s, const Options
         dinv = f.ml.v;
     }
     if (!dinv.empty()) upload_dense(d.dinv, dinv, stg);
+}
+
+template <typename T>
+void update_flow_pressure(DFlow<T> &d, const FlowSetup &f, const Options &o, const PresStore *ps) {
+    TraceTick tt("pressure levels");
     if (ps) adopt_hierarchy(*d.pres, f.pres, *ps, o.smoother);
     else upload_hierarchy_into(*d.pres, f.pres, o.smoother, false);
 }
@@ -1314,10 +1389,12 @@ template Sell<double> upload_sell<double>(Arena &, const HostSell &);
 template Sell<float> upload_sell<float>(Arena &, const HostSell &);
 template std::unique_ptr<DHierarchy<double>> upload_hierarchy<double>(const Hierarchy &, int, bool);
 template std::unique_ptr<DHierarchy<float>> upload_hierarchy<float>(const Hierarchy &, int, bool);
-template void update_flow<double>(DFlow<double> &, const FlowSetup &, const System &, const Options &, Staging &,
-                                  bool, const PresStore *);
-template void update_flow<float>(DFlow<float> &, const FlowSetup &, const System &, const Options &, Staging &,
-                                 bool, const PresStore *);
+template void update_flow_values<double>(DFlow<double> &, const FlowSetup &, const System &, const DSystem &,
+                                         const Options &, Staging &, bool);
+template void update_flow_values<float>(DFlow<float> &, const FlowSetup &, const System &, const DSystem &,
+                                        const Options &, Staging &, bool);
+template void update_flow_pressure<double>(DFlow<double> &, const FlowSetup &, const Options &, const PresStore *);
+template void update_flow_pressure<float>(DFlow<float> &, const FlowSetup &, const Options &, const PresStore *);
 template void alloc_prec_work<double>(PrecWork<double> &, const DHierarchy<double> &, const DFlow<double> &, int);
 template void alloc_prec_work<float>(PrecWork<float> &, const DHierarchy<float> &, const DFlow<float> &, int);
 template void apply_precond<double>(const DHierarchy<double> &, const DFlow<double> &, PrecWork<double> &, int,

@@ -110,8 +110,11 @@ void exclusive_scan(Arena &tmp, const T *in, T *out, size_t n, hipStream_t st) {
     PS_HIP(rocprim::exclusive_scan(w, bytes, in, out, T(0), n, rocprim::plus<T>(), st));
 }
 
+int g_round_trips = 0;              // host-device round trips of the current level (tracing)
+
 template <typename T>
 T read_back(const T *d, hipStream_t st) {
+    ++g_round_trips;
     T h;
     PS_HIP(hipMemcpyAsync(&h, d, sizeof(T), hipMemcpyDeviceToHost, st));
     PS_HIP(hipStreamSynchronize(st));
@@ -537,6 +540,12 @@ static void build_pressure_device(const Csr &Spp, const Options &o, Hierarchy &H
     DevCsr A = upload(S.arena, Spp);
     while (A.n > o.coarse_max && (int)H.lev.size() + 1 < o.max_levels) {
         const int n = A.n, nnz = A.nnz;
+        TraceTick lt("pressure level");
+        g_round_trips = 0;
+        struct Note {
+            TraceTick &t;
+            ~Note() { t.note = g_round_trips; }
+        } note{lt};
         S.work.recycle();
         S.tmp.recycle();
         // strength and S, S^T
@@ -559,12 +568,16 @@ static void build_pressure_device(const Csr &Spp, const Options &o, Hierarchy &H
         signed char *cf = S.arena.alloc<signed char>(n), *newc = S.work.alloc<signed char>(n);
         zero(ctr, 1);
         hipLaunchKernelGGL(pmis_init_k, dim3(blocks(n)), dim3(TB), 0, st, trp, n, w, cf, ctr);
+        // two rounds per read-back of the undecided count (a round with nothing undecided
+        // changes nothing)
         int rounds = 0;
         for (int und = read_back(ctr, st); und > 0; und = read_back(ctr, st)) {
-            if (++rounds > n) throw Error(PS_EDEVICE, "PMIS did not terminate");   // each round decides >= 1 point
-            hipLaunchKernelGGL(pmis_select_k, dim3(blocks(n)), dim3(TB), 0, st, cf, w, srp, sci, trp, tci, n, newc);
-            zero(ctr, 1);
-            hipLaunchKernelGGL(pmis_mark_k, dim3(blocks(n)), dim3(TB), 0, st, cf, newc, srp, sci, n, ctr);
+            for (int k = 0; k < 2; ++k) {
+                if (++rounds > n + 1) throw Error(PS_EDEVICE, "PMIS did not terminate");   // each round decides >= 1 point
+                hipLaunchKernelGGL(pmis_select_k, dim3(blocks(n)), dim3(TB), 0, st, cf, w, srp, sci, trp, tci, n, newc);
+                zero(ctr, 1);
+                hipLaunchKernelGGL(pmis_mark_k, dim3(blocks(n)), dim3(TB), 0, st, cf, newc, srp, sci, n, ctr);
+            }
         }
         // C-promotion
         signed char *cs = S.work.alloc<signed char>(n);
@@ -572,9 +585,11 @@ static void build_pressure_device(const Csr &Spp, const Options &o, Hierarchy &H
         hipLaunchKernelGGL(promo_init_k, dim3(blocks(n)), dim3(TB), 0, st, cf, srp, sci, n, cs, ctr);
         rounds = 0;
         for (int und = read_back(ctr, st); und > 0; und = read_back(ctr, st)) {
-            if (++rounds > n) throw Error(PS_EDEVICE, "C-promotion did not terminate");
-            zero(ctr, 1);
-            hipLaunchKernelGGL(promo_round_k, dim3(blocks(n)), dim3(TB), 0, st, cs, srp, sci, n, ctr);
+            for (int k = 0; k < 2; ++k) {
+                if (++rounds > n + 1) throw Error(PS_EDEVICE, "C-promotion did not terminate");
+                zero(ctr, 1);
+                hipLaunchKernelGGL(promo_round_k, dim3(blocks(n)), dim3(TB), 0, st, cs, srp, sci, n, ctr);
+            }
         }
         int *cflag = S.work.alloc<int>((size_t)n + 1), *cidx = S.work.alloc<int>((size_t)n + 1);
         hipLaunchKernelGGL(promo_apply_k, dim3(blocks(n + 1)), dim3(TB), 0, st, cf, cs, n, cflag);

@@ -410,6 +410,29 @@ __global__ __launch_bounds__(WG) void csr_l1_post(DCsr<T> A, const T *__restrict
     if (g == 0) out[i] = x[i] + (b[i] - a) * dinv[i];
 }
 
+// ------------------------------------------------------------------ setup
+// S_ff (Sec. 5.1, fixed stress) from the system's A_ff in the same SELL-64 layout: the
+// fixed-stress terms are added in FP64 to the last column of each row's diagonal block
+// (slot dslot[pos]), then every entry is rounded to T.  One lane per row position,
+// padding lanes included.
+template <int NF, typename T>
+__global__ __launch_bounds__(WG) void sff_from_aff(Sell<double> A, const double *__restrict__ d_sp,
+                                                  const double *__restrict__ d_pp, const int *__restrict__ dslot,
+                                                  T *__restrict__ sff) {
+    const int pos = blockIdx.x * WG + threadIdx.x;
+    if (pos >= A.nchunks * 64) return;
+    const int lane = pos & 63, ch = pos >> 6, s0 = A.cptr[ch], w = A.cptr[ch + 1] - s0, ds = dslot[pos];
+    for (int k = 0; k < w; ++k)
+#pragma unroll
+        for (int e = 0; e < NF * NF; ++e) {
+            const size_t idx = ((size_t)(s0 + k) * (NF * NF) + e) * 64 + lane;
+            double v = A.val[idx];
+            if (k == ds && e % NF == NF - 1)
+                v += e / NF < NF - 1 ? d_sp[(size_t)pos * (NF - 1) + e / NF] : d_pp[pos];
+            sff[idx] = (T)v;
+        }
+}
+
 // ------------------------------------------------------------------ Algorithm 1 kernels
 // Steps 2-3: y = v_f - A_fu z_u (per cell), z_s = D_ss^{-1} y_s.
 template <int NF, typename T>
@@ -709,15 +732,17 @@ struct SubRow {
 // Loads are unconditional (row 0 stands in for rows past the level's end, whose
 // results are not used): a load whose result may be replaced on another path forces
 // the compiler to wait for it at once, which would serialise the prefetch.
+// (each plane's base is uniform and the row a 32-bit unsigned offset, so a load takes one
+// scalar base and one shared vector offset)
 template <typename T, int NF, int W>
 __device__ __forceinline__ void sub_load(SubRow<T, NF, W> &d, const int *__restrict__ col,
                                          const T *__restrict__ val, size_t N, int r, bool ok) {
-    const size_t rr = ok ? (size_t)r : 0;
+    const unsigned rr = ok ? (unsigned)r : 0u;
 #pragma unroll
     for (int s = 0; s < W; ++s) {
-        d.c[s] = col[(size_t)s * N + rr];
+        d.c[s] = (col + (size_t)s * N)[rr];
 #pragma unroll
-        for (int q = 0; q < NF * NF; ++q) d.v[s][q] = val[((size_t)s * NF * NF + q) * N + rr];
+        for (int q = 0; q < NF * NF; ++q) d.v[s][q] = (val + ((size_t)s * NF * NF + q) * N)[rr];
     }
 }
 
@@ -758,9 +783,9 @@ template <typename T, int NF, int W>
 __device__ __forceinline__ void sub_load_b(SubRowB<T, NF, W> &d, const SubLayout &L, const T *__restrict__ bval,
                                            const T *__restrict__ bdinv, size_t N, int r, bool ok) {
     sub_load(d.u, L.bcol, bval, N, r, ok);
-    const size_t rr = ok ? (size_t)r : 0;
+    const unsigned rr = ok ? (unsigned)r : 0u;
 #pragma unroll
-    for (int q = 0; q < NF * NF; ++q) d.dv[q] = bdinv[(size_t)q * N + rr];
+    for (int q = 0; q < NF * NF; ++q) d.dv[q] = (bdinv + (size_t)q * N)[rr];
     d.p = L.bpos[rr];
 }
 
@@ -798,27 +823,34 @@ __global__ __launch_bounds__(512) void bilu_sub(SubLayout L, const T *__restrict
         for (int e = 0; e < NF; ++e) y[p * NF + e] = win[(size_t)c * NF + e];
     }
     __syncthreads();
-    // forward: t_p = w_p - sum_k L_pk t_k, in place.  Four register buffers rotate
-    // without copies (the loop is unrolled by four), so a level's loads have three
-    // levels' time to arrive.
+    // A level's rows are prefetched three levels ahead into one of four register buffers
+    // that rotate without copies (the loop is unrolled by four), together with the level's
+    // bounds, so that after a barrier a level only gathers from LDS, computes and writes;
+    // the reads of the next bounds and the issue of the next loads follow.  Steps past the
+    // last level are empty (bounds 0, 0).
+    // forward: t_p = w_p - sum_k L_pk t_k, in place.
     {
         const int nl = nfl - 1;
-        SubRow<T, NF, W> c0, c1, c2, c3;
-        auto load = [&](SubRow<T, NF, W> &x, int l) {
-            int r = l < nl ? lf[l] + tid : 0;
-            sub_load(x, L.fcol, fval, N, r, l < nl && r < lf[l + 1]);
+        struct Buf {
+            SubRow<T, NF, W> x;
+            int r0, r1;
         };
-        auto step = [&](int l, const SubRow<T, NF, W> &cur, SubRow<T, NF, W> &ahead) {
-            const int r0 = lf[l], r1 = lf[l + 1];
-            load(ahead, l + 3);
+        Buf c0, c1, c2, c3;
+        auto load = [&](Buf &b, int l) {
+            b.r0 = l < nl ? lf[l] : 0;
+            b.r1 = l < nl ? lf[l + 1] : 0;
+            const int r = b.r0 + tid;
+            sub_load(b.x, L.fcol, fval, N, r, r < b.r1);
+        };
+        auto step = [&](int l, const Buf &cur, Buf &ahead) {
             {
                 T acc[NF];
-                sub_acc(cur, y, n, acc);
-                const int p = r0 + tid < r1 ? r0 + tid - off : n;
+                sub_acc(cur.x, y, n, acc);
+                const int p = cur.r0 + tid < cur.r1 ? cur.r0 + tid - off : n;
 #pragma unroll
                 for (int e = 0; e < NF; ++e) y[p * NF + e] = y[p * NF + e] - acc[e];
             }
-            for (int rr = r0 + tid + bs; rr < r1; rr += bs) {
+            for (int rr = cur.r0 + tid + bs; rr < cur.r1; rr += bs) {
                 SubRow<T, NF, W> x;
                 sub_load(x, L.fcol, fval, N, rr, true);
                 T acc[NF];
@@ -827,6 +859,7 @@ __global__ __launch_bounds__(512) void bilu_sub(SubLayout L, const T *__restrict
 #pragma unroll
                 for (int e = 0; e < NF; ++e) y[p * NF + e] = y[p * NF + e] - acc[e];
             }
+            load(ahead, l + 3);
             __syncthreads();
         };
         load(c0, 0);
@@ -834,18 +867,24 @@ __global__ __launch_bounds__(512) void bilu_sub(SubLayout L, const T *__restrict
         load(c2, 2);
         for (int l = 0; l < nl; l += 4) {
             step(l, c0, c3);
-            if (l + 1 < nl) step(l + 1, c1, c0);
-            if (l + 2 < nl) step(l + 2, c2, c1);
-            if (l + 3 < nl) step(l + 3, c3, c2);
+            step(l + 1, c1, c0);
+            step(l + 2, c2, c1);
+            step(l + 3, c3, c2);
         }
     }
     // backward: delta_p = D_p^{-1} (t_p - sum_j U_pj delta_j), in place
     {
         const int nl = nbl - 1;
-        SubRowB<T, NF, W> c0, c1, c2, c3;
-        auto load = [&](SubRowB<T, NF, W> &x, int l) {
-            int r = l < nl ? lb[l] + tid : 0;
-            sub_load_b(x, L, bval, bdinv, N, r, l < nl && r < lb[l + 1]);
+        struct Buf {
+            SubRowB<T, NF, W> x;
+            int r0, r1;
+        };
+        Buf c0, c1, c2, c3;
+        auto load = [&](Buf &b, int l) {
+            b.r0 = l < nl ? lb[l] : 0;
+            b.r1 = l < nl ? lb[l + 1] : 0;
+            const int r = b.r0 + tid;
+            sub_load_b(b.x, L, bval, bdinv, N, r, r < b.r1);
         };
         auto row = [&](const SubRowB<T, NF, W> &x, bool act) {
             T acc[NF], rv[NF];
@@ -861,15 +900,14 @@ __global__ __launch_bounds__(512) void bilu_sub(SubLayout L, const T *__restrict
                 y[p * NF + a2] = sm;
             }
         };
-        auto step = [&](int l, const SubRowB<T, NF, W> &cur, SubRowB<T, NF, W> &ahead) {
-            const int r0 = lb[l], r1 = lb[l + 1];
-            load(ahead, l + 3);
-            row(cur, r0 + tid < r1);
-            for (int rr = r0 + tid + bs; rr < r1; rr += bs) {
+        auto step = [&](int l, const Buf &cur, Buf &ahead) {
+            row(cur.x, cur.r0 + tid < cur.r1);
+            for (int rr = cur.r0 + tid + bs; rr < cur.r1; rr += bs) {
                 SubRowB<T, NF, W> x;
                 sub_load_b(x, L, bval, bdinv, N, rr, true);
                 row(x, true);
             }
+            load(ahead, l + 3);
             __syncthreads();
         };
         load(c0, 0);
@@ -877,9 +915,9 @@ __global__ __launch_bounds__(512) void bilu_sub(SubLayout L, const T *__restrict
         load(c2, 2);
         for (int l = 0; l < nl; l += 4) {
             step(l, c0, c3);
-            if (l + 1 < nl) step(l + 1, c1, c0);
-            if (l + 2 < nl) step(l + 2, c2, c1);
-            if (l + 3 < nl) step(l + 3, c3, c2);
+            step(l + 1, c1, c0);
+            step(l + 2, c2, c1);
+            step(l + 3, c3, c2);
         }
     }
     for (int j = tid; j < n; j += bs) {
