@@ -112,12 +112,22 @@ void exclusive_scan(Arena &tmp, const T *in, T *out, size_t n, hipStream_t st) {
 
 int g_round_trips = 0;              // host-device round trips of the current level (tracing)
 
+// A pinned word per thread for the size and count read-backs of the build (a copy into
+// pageable memory would be staged through a bounce buffer), kept until the process ends.
+void *pinned_word() {
+    static thread_local void *p = nullptr;
+    if (!p) PS_HIP(hipHostMalloc(&p, 64, hipHostMallocDefault));
+    return p;
+}
+
 template <typename T>
 T read_back(const T *d, hipStream_t st) {
     ++g_round_trips;
-    T h;
-    PS_HIP(hipMemcpyAsync(&h, d, sizeof(T), hipMemcpyDeviceToHost, st));
+    void *pin = pinned_word();
+    PS_HIP(hipMemcpyAsync(pin, d, sizeof(T), hipMemcpyDeviceToHost, st));
     PS_HIP(hipStreamSynchronize(st));
+    T h;
+    std::memcpy(&h, pin, sizeof(T));
     return h;
 }
 
