@@ -234,6 +234,8 @@ struct Staging {
     hipStream_t st = nullptr;
     void *get(size_t n);
     void copy_to_device(void *dev, const void *host, size_t n);   // returns when done
+    void copy_async(void *dev, const void *host, size_t n);       // queued; see wait()
+    void wait();
     ~Staging();
 };
 

@@ -237,9 +237,13 @@ static bool take_sell(double pad, int n, size_t nnz) {
 }
 
 static int lanes_per_row(int n, size_t nnz) {
+    static const double mul = [] {
+        const char *e = std::getenv("PS_CSR_GMUL");
+        return e ? std::atof(e) : 1.0;
+    }();
     double avg = n ? (double)nnz / n : 1.0;
     int G = 1;
-    while (G < 32 && G * 3 < avg) G *= 2;
+    while (G < 32 && G * 3 < avg * mul) G *= 2;
     return G;
 }
 
@@ -390,11 +394,18 @@ void *Staging::get(size_t n) {
     return p;
 }
 
-void Staging::copy_to_device(void *dev, const void *host, size_t n) {
-    if (!n) return;
+void Staging::copy_async(void *dev, const void *host, size_t n) {
     if (!st) PS_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-    PS_HIP(hipMemcpyAsync(dev, host, n, hipMemcpyHostToDevice, st));
-    PS_HIP(hipStreamSynchronize(st));
+    if (n) PS_HIP(hipMemcpyAsync(dev, host, n, hipMemcpyHostToDevice, st));
+}
+
+void Staging::wait() {
+    if (st) PS_HIP(hipStreamSynchronize(st));
+}
+
+void Staging::copy_to_device(void *dev, const void *host, size_t n) {
+    copy_async(dev, host, n);
+    wait();
 }
 
 Staging::~Staging() {
@@ -450,11 +461,7 @@ static Sell<T> layout_sell(Arena &ar, const HostSell &h, T *&val, std::vector<in
 
 // Scatter block values into an ELL layout val[(s*rc + q)*N + r] (src[s*N + r]: source block).
 template <typename T>
-static void upload_ell(T *dev, const std::vector<int> &src, int W, int N, int rc, const std::vector<double> &v,
-                       Staging &stg) {
-    size_t n = (size_t)W * rc * N;
-    if (n == 0) return;
-    T *out = static_cast<T *>(stg.get(n * sizeof(T)));
+static void scatter_ell(T *out, const std::vector<int> &src, int W, int N, int rc, const std::vector<double> &v) {
     parallel_for(N, [&](int b, int e, int) {
         for (int r = b; r < e; ++r)             // a block's rc values are read together
             for (int s = 0; s < W; ++s) {
@@ -463,7 +470,6 @@ static void upload_ell(T *dev, const std::vector<int> &src, int W, int N, int rc
                     out[((size_t)s * rc + q) * N + r] = t < 0 ? T(0) : (T)v[(size_t)t * rc + q];
             }
     });
-    stg.copy_to_device(dev, out, n * sizeof(T));
 }
 
 static bool bilu_levels_forced() {
@@ -813,11 +819,18 @@ void update_flow_values(DFlow<T> &d, const FlowSetup &f, const System &s, const 
     }
     std::vector<double> dinv((size_t)nc * nn);
     if (d.sub) {
+        // each array is copied while the next one is scattered
         TraceTick tt("values subdomain BILU");
         const SubBilu<T> &b = d.sb;
-        upload_ell(b.fval, b.fsrc, b.W, nc, nn, f.ml.v, stg);
-        upload_ell(b.bval, b.bsrc, b.W, nc, nn, f.ml.v, stg);
-        upload_ell(b.bdinv, b.dsrc, 1, nc, nn, f.ml.v, stg);
+        const size_t ne = (size_t)b.W * nn * nc, nd = (size_t)nn * nc;
+        T *out = static_cast<T *>(stg.get((2 * ne + nd) * sizeof(T)));
+        scatter_ell(out, b.fsrc, b.W, nc, nn, f.ml.v);
+        stg.copy_async(b.fval, out, ne * sizeof(T));
+        scatter_ell(out + ne, b.bsrc, b.W, nc, nn, f.ml.v);
+        stg.copy_async(b.bval, out + ne, ne * sizeof(T));
+        scatter_ell(out + 2 * ne, b.dsrc, 1, nc, nn, f.ml.v);
+        stg.copy_async(b.bdinv, out + 2 * ne, nd * sizeof(T));
+        stg.wait();
         dinv.clear();
     } else if (o.ml_kind == PS_BILU0) {
         upload_values(d.lf_val, d.src_lf, nn, f.ml.v, stg);
