@@ -237,13 +237,9 @@ static bool take_sell(double pad, int n, size_t nnz) {
 }
 
 static int lanes_per_row(int n, size_t nnz) {
-    static const double mul = [] {
-        const char *e = std::getenv("PS_CSR_GMUL");
-        return e ? std::atof(e) : 1.0;
-    }();
     double avg = n ? (double)nnz / n : 1.0;
     int G = 1;
-    while (G < 32 && G * 3 < avg * mul) G *= 2;
+    while (G < 32 && G * 3 < avg) G *= 2;
     return G;
 }
 
