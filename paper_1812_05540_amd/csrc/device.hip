@@ -256,7 +256,27 @@ static DCsr<T> upload_csr(Arena &ar, const Csr &A, bool sell) {
         HostSell h = sell_from_bsr(A.rp, A.ci, A.v, A.n, 1, 1);
         d.G = 0;
         d.cptr = ar.upload(h.cptr.data(), h.cptr.size());
-        d.ci = ar.upload(h.col.data(), h.col.size());
+        // columns as 16-bit offsets from the row when every one fits (stencil-like levels)
+        std::vector<short> cd(h.col.size(), 0);
+        bool fits = true;
+        for (int i = 0; i < A.n && fits; ++i) {
+            const int ch = i >> 6, lane = i & 63;
+            for (int k = 0; k < A.rp[i + 1] - A.rp[i]; ++k) {
+                const size_t q = ((size_t)h.cptr[ch] + k) * 64 + lane;
+                const int dlt = h.col[q] - i;
+                if (dlt < -32768 || dlt > 32767) {
+                    fits = false;
+                    break;
+                }
+                cd[q] = (short)dlt;
+            }
+        }
+        if (fits) {
+            d.G = -1;
+            d.cd = ar.upload(cd.data(), cd.size());
+        } else {
+            d.ci = ar.upload(h.col.data(), h.col.size());
+        }
         std::vector<T> v(h.val.begin(), h.val.end());
         d.v = ar.upload(v.data(), v.size());
         return d;
@@ -911,6 +931,7 @@ void alloc_prec_work(PrecWork<T> &w, const DHierarchy<T> &sdc, const DFlow<T> &f
 template <typename F>
 static void with_G(int G, F &&f) {
     switch (G) {
+    case -1: f(std::integral_constant<int, -1>{}); break;
     case 0: f(std::integral_constant<int, 0>{}); break;
     case 1: f(std::integral_constant<int, 1>{}); break;
     case 2: f(std::integral_constant<int, 2>{}); break;
@@ -925,7 +946,7 @@ template <int MODE, typename T>
 static void csr_spmv(const DCsr<T> &A, const T *x, const T *b, T *y, hipStream_t st) {
     with_G(A.G, [&](auto Gc) {
         constexpr int G = decltype(Gc)::value;
-        LAUNCH((k::csr_spmv<G, MODE, T>), grid_for((size_t)A.n * (G ? G : 1)), 0, st, A, x, b, y);
+        LAUNCH((k::csr_spmv<G, MODE, T>), grid_for((size_t)A.n * (G > 0 ? G : 1)), 0, st, A, x, b, y);
     });
 }
 
@@ -941,7 +962,7 @@ static void vcycle(const DHierarchy<T> &H, HierWork<T> &W, int l, const T *b, T 
     const bool cheb = H.smoother == PS_CHEB2;
     with_G(L.A.G, [&](auto Gc) {
         constexpr int G = decltype(Gc)::value;
-        unsigned g = grid_for((size_t)L.n * (G ? G : 1));
+        unsigned g = grid_for((size_t)L.n * (G > 0 ? G : 1));
         if (cheb) {
             LAUNCH((k::csr_cheb_pre<G, T>), g, 0, st, L.A, b, L.c0, L.c1, L.cm, W.x[l]);
             LAUNCH((k::csr_spmv<G, 1, T>), g, 0, st, L.A, (const T *)W.x[l], b, W.r[l]);
@@ -954,7 +975,7 @@ static void vcycle(const DHierarchy<T> &H, HierWork<T> &W, int l, const T *b, T 
     if (!cheb && l + 1 < last) {
         with_G(L.R.G, [&](auto Gc) {
             constexpr int G = decltype(Gc)::value;
-            LAUNCH((k::csr_restrict_l1<G, T>), grid_for((size_t)L.R.n * (G ? G : 1)), 0, st, L.R,
+            LAUNCH((k::csr_restrict_l1<G, T>), grid_for((size_t)L.R.n * (G > 0 ? G : 1)), 0, st, L.R,
                    (const T *)W.r[l], H.lev[l + 1].dinv, W.b[l + 1], W.x[l + 1]);
         });
     } else {
@@ -964,7 +985,7 @@ static void vcycle(const DHierarchy<T> &H, HierWork<T> &W, int l, const T *b, T 
     csr_spmv<2, T>(L.P, (const T *)W.e[l + 1], (const T *)nullptr, W.x[l], st);
     with_G(L.A.G, [&](auto Gc) {
         constexpr int G = decltype(Gc)::value;
-        unsigned g = grid_for((size_t)L.n * (G ? G : 1));
+        unsigned g = grid_for((size_t)L.n * (G > 0 ? G : 1));
         if (cheb) {
             LAUNCH((k::csr_cheb_post1<G, T>), g, 0, st, L.A, b, (const T *)W.x[l], L.c0, W.x1[l], W.d[l]);
             LAUNCH((k::csr_cheb_post2<G, T>), g, 0, st, L.A, b, (const T *)W.x1[l], (const T *)W.d[l], L.c1,

@@ -241,16 +241,19 @@ __device__ __forceinline__ T group_sum(T a) {
     return a;
 }
 
-// SELL-64 row (G == 0): the lane owns row i and adds its entries in order; a wavefront's
+// SELL-64 row (G <= 0): the lane owns row i and adds its entries in order; a wavefront's
 // loads of entry k of its 64 rows are one contiguous stretch, and on a stencil-like level
 // so are the gathers of x.  Four entries are loaded before any is used; past the row's
 // end the loads repeat its last entry and are not added.
-template <bool S, typename T>
+// (DELTA: the columns are read as 16-bit offsets from the row, 6 bytes per FP32 entry
+// instead of 8)
+template <bool S, bool DELTA, typename T>
 __device__ __forceinline__ T sell_dot(const DCsr<T> &A, int i, const T *__restrict__ x,
                                       const T *__restrict__ s) {
     const int len = A.rp[i + 1] - A.rp[i];
     const size_t base = (size_t)A.cptr[i >> 6] * 64 + (i & 63);
-    const int *__restrict__ ci = A.ci + base;
+    const int *__restrict__ ci = DELTA ? nullptr : A.ci + base;
+    const short *__restrict__ cd = DELTA ? A.cd + base : nullptr;
     const T *__restrict__ v = A.v + base;
     T acc = T(0);
     for (int k = 0; k < len; k += 4) {
@@ -259,7 +262,7 @@ __device__ __forceinline__ T sell_dot(const DCsr<T> &A, int i, const T *__restri
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int kk = k + u < len ? k + u : len - 1;
-            c[u] = ci[kk * 64];
+            c[u] = DELTA ? i + (int)cd[kk * 64] : ci[kk * 64];
             a[u] = v[kk * 64];
         }
 #pragma unroll
@@ -302,8 +305,8 @@ __global__ __launch_bounds__(WG) void csr_to_sell(const int *__restrict__ rp, co
 template <int G, bool S, typename T>
 __device__ __forceinline__ T csr_dot(const DCsr<T> &A, int i, int g, const T *__restrict__ x,
                                      const T *__restrict__ s) {
-    if constexpr (G == 0) {
-        return sell_dot<S>(A, i, x, s);
+    if constexpr (G <= 0) {
+        return sell_dot<S, G == -1>(A, i, x, s);
     } else {
         T acc = T(0);
         const int e = A.rp[i + 1];
@@ -327,7 +330,7 @@ __device__ __forceinline__ T csr_dot(const DCsr<T> &A, int i, int g, const T *__
 }
 
 #define PS_CSR_ROW(G)                                         \
-    constexpr int LPR_ = G ? G : 1;                           \
+    constexpr int LPR_ = G > 0 ? G : 1;                       \
     int gid = blockIdx.x * WG + threadIdx.x;                  \
     int i = gid / LPR_, g = gid % LPR_;                       \
     if (i >= A.n) return;
