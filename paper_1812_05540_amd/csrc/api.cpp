@@ -630,7 +630,10 @@ void ps_ctx::scheduler() {
         }
         r->res.setup_s = r->h->setup_s;
         r->res.solve_s = now_s() - r->t_submit;
-        if (r->st) (void)hipStreamDestroy(r->st);
+        if (r->st) {                      // work still queued (after an error) ends first
+            (void)hipStreamSynchronize(r->st);
+            (void)hipStreamDestroy(r->st);
+        }
         r->st = nullptr;
         if (r->ready) (void)hipEventDestroy(r->ready);
         r->ready = nullptr;
