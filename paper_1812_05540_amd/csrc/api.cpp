@@ -330,17 +330,23 @@ int ps_setup(ps_handle *h) {
             ensure_mech_device(h, f64, f32);
         }
         const bool dev_rap = galerkin_on_device();
+        // after the first setup has laid out the subdomain BILU(0), its factorization runs on
+        // the device from S_ff's values (the host keeps the pattern only)
+        auto dev_factor_ready = [](const auto &fl) { return fl && fl->sub && fl->sb.dev_factor; };
+        const bool dev_factor = (!f64 || dev_factor_ready(h->fl64)) && (!f32 || dev_factor_ready(h->fl32));
         // layouts (first call) and values of the flow stage that do not depend on the
         // pressure hierarchy, for the precisions in use
         auto flow_values = [&] {
             PhaseTimer pt("flow values upload");
             if (f64) {
                 if (!h->fl64) h->fl64 = std::make_unique<DFlow<double>>();
-                update_flow_values<double>(*h->fl64, h->flow, h->sys, h->dsys, h->opt, h->staging, h->afu_changed);
+                update_flow_values<double>(*h->fl64, h->flow, h->sys, h->dsys, h->opt, h->staging, h->afu_changed,
+                                           dev_factor);
             }
             if (f32) {
                 if (!h->fl32) h->fl32 = std::make_unique<DFlow<float>>();
-                update_flow_values<float>(*h->fl32, h->flow, h->sys, h->dsys, h->opt, h->staging, h->afu_changed);
+                update_flow_values<float>(*h->fl32, h->flow, h->sys, h->dsys, h->opt, h->staging, h->afu_changed,
+                                          dev_factor);
             }
         };
         {
@@ -355,7 +361,7 @@ int ps_setup(ps_handle *h) {
                 std::thread local([&] {
                     try {
                         set_device(dev);
-                        build_flow_local(h->sys, h->opt, h->flow);
+                        build_flow_local(h->sys, h->opt, h->flow, dev_factor);
                         flow_values();
                     } catch (...) {
                         err = std::current_exception();
@@ -376,7 +382,7 @@ int ps_setup(ps_handle *h) {
                     PhaseTimer pt2("pressure AMG (host)");
                     h->flow.pres = amg_build(h->flow.Spp, h->opt);
                 }
-                build_flow_local(h->sys, h->opt, h->flow);
+                build_flow_local(h->sys, h->opt, h->flow, dev_factor);
                 flow_values();
             }
         }

@@ -195,6 +195,18 @@ struct SubBilu {
               *bpos = nullptr, *ncell = nullptr, *npos = nullptr, *fcol = nullptr, *bcol = nullptr;
     T *fval = nullptr, *bval = nullptr, *bdinv = nullptr;
     std::vector<int> fsrc, bsrc, dsrc;    // value source blocks (host), -1 = padding
+    std::vector<int> ford;                // cell of each forward position (host)
+    // The factorization on the device (when S_ff's values are formed there): per factor
+    // block its A_ff SELL position and, for a diagonal block, its cell (else -1); per
+    // forward position r, the diagonal block, and for each strict-lower block k (slot
+    // k*N + r, -1 past the row's end) the diagonal block of its column row and the matched
+    // updates (slot (k*W + m)*N + r): block u of that row's upper part and block q of row r.
+    bool dev_factor = false;
+    int nml = 0;
+    const int *ml_src = nullptr, *ml_fs = nullptr, *fdiag = nullptr, *lo_t = nullptr, *lo_d = nullptr,
+              *up_u = nullptr, *up_q = nullptr, *d_fsrc = nullptr, *d_bsrc = nullptr, *d_dsrc = nullptr;
+    double *fv = nullptr;                 // FP64 factor values, nml blocks
+    int *flag = nullptr;                  // set when a pivot block is singular
 };
 
 template <typename T>
@@ -304,9 +316,11 @@ void upload_hierarchy_into(DHierarchy<T> &d, const Hierarchy &H, int smoother, b
 // D_ss and the local-stage factors, which do not depend on the pressure hierarchy (S: the
 // system on the device, whose A_ff gives S_ff's values); then the pressure levels (ps:
 // device copies of the pressure hierarchy, adopted rather than uploaded, or nullptr).
+// factor_on_device: the local-stage BILU(0) factor is computed on the device from S_ff's
+// values (f.ml holds the pattern only); possible once d.sb.dev_factor is set.
 template <typename T>
 void update_flow_values(DFlow<T> &d, const FlowSetup &f, const System &s, const DSystem &S, const Options &o,
-                        Staging &stg, bool afu_changed);
+                        Staging &stg, bool afu_changed, bool factor_on_device = false);
 template <typename T>
 void update_flow_pressure(DFlow<T> &d, const FlowSetup &f, const Options &o, const PresStore *ps);
 void upload_system(const System &s, DSystem &d);

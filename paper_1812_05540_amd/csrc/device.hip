@@ -488,6 +488,12 @@ static void scatter_ell(T *out, const std::vector<int> &src, int W, int N, int r
     });
 }
 
+// PS_BILU_FACTOR=host keeps the local-stage factorization on the host at every setup.
+static bool device_factor_off() {
+    const char *e = std::getenv("PS_BILU_FACTOR");
+    return e && std::string(e) == "host";
+}
+
 static bool bilu_levels_forced() {
     const char *e = std::getenv("PS_BILU_LAUNCH");
     return e && (std::string(e) == "levels" || std::string(e) == "1wg");
@@ -600,6 +606,7 @@ static bool layout_sub_bilu(DFlow<T> &d, const FlowSetup &f, const System &s) {
         }
     }
     b.dsrc = dsrc;
+    b.ford = ford;
     {
         // stored blocks (values + column) of both sweeps, D^{-1}, and the vectors
         // (rhs read, z_s/z_p read, z written)
@@ -655,6 +662,98 @@ static bool layout_sub_bilu(DFlow<T> &d, const FlowSetup &f, const System &s) {
     b.bdinv = ar.template alloc<T>((size_t)nf * nf * N);
     b.ygl = vec_in_lds ? nullptr : ar.template alloc<T>((size_t)nf * (N + D));   // + one dummy row each
     return true;
+}
+
+// Tables of the device BILU(0) factorization (pattern only, built once): hs is the SELL
+// layout shared by S_ff and the system's A_ff.  Returns false (the host factors) when a
+// factor block has no A_ff position or a table would not fit 32-bit indices.
+template <typename T>
+static bool layout_sub_factor(DFlow<T> &d, const FlowSetup &f, const HostSell &hs) {
+    SubBilu<T> &b = d.sb;
+    const Bsr &F = f.ml, &S = f.Sff;
+    const int N = F.nbr, nn = F.br * F.bc, W = b.W;
+    const int nml = F.rp[N];
+    if ((size_t)hs.cptr.back() * nn * 64 >= (size_t)1 << 31 || (size_t)W * W * N >= (size_t)1 << 31) return false;
+    std::vector<int> ml_src(nml, -1), ml_fs(nml, -1), dpos(N, -1);
+    for (int i = 0; i < N; ++i) {
+        const int ch = i >> 6, lane = i & 63;
+        int tm = F.rp[i];
+        for (int ts = S.rp[i]; ts < S.rp[i + 1] && tm < F.rp[i + 1]; ++ts) {
+            if (F.ci[tm] != S.ci[ts]) continue;                  // dropped: another subdomain
+            const size_t slot = (size_t)hs.cptr[ch] + (ts - S.rp[i]);
+            ml_src[tm] = (int)(slot * nn * 64 + lane);
+            if (F.ci[tm] == i) {
+                ml_fs[tm] = i;
+                dpos[i] = tm;
+            }
+            ++tm;
+        }
+        if (tm != F.rp[i + 1] || dpos[i] < 0) return false;
+    }
+    std::vector<int> fdiag(N), lo_t((size_t)W * N, -1), lo_d((size_t)W * N, -1), up_u((size_t)W * W * N, -1),
+        up_q((size_t)W * W * N, -1);
+    for (int r = 0; r < N; ++r) {
+        const int i = b.ford[r];
+        fdiag[r] = dpos[i];
+        int k = 0;
+        for (int t = F.rp[i]; t < F.rp[i + 1] && F.ci[t] < i; ++t, ++k) {
+            if (k >= W) return false;
+            const int kc = F.ci[t];
+            lo_t[(size_t)k * N + r] = t;
+            lo_d[(size_t)k * N + r] = dpos[kc];
+            int m = 0;
+            for (int u = dpos[kc] + 1; u < F.rp[kc + 1]; ++u) {
+                int q = -1;
+                for (int x = F.rp[i]; x < F.rp[i + 1]; ++x)
+                    if (F.ci[x] == F.ci[u]) q = x;
+                if (q < 0) continue;
+                if (m >= W) return false;
+                up_u[((size_t)k * W + m) * N + r] = u;
+                up_q[((size_t)k * W + m) * N + r] = q;
+                ++m;
+            }
+        }
+    }
+    Arena &ar = d.arena;
+    b.nml = nml;
+    b.ml_src = ar.upload(ml_src.data(), ml_src.size());
+    b.ml_fs = ar.upload(ml_fs.data(), ml_fs.size());
+    b.fdiag = ar.upload(fdiag.data(), fdiag.size());
+    b.lo_t = ar.upload(lo_t.data(), lo_t.size());
+    b.lo_d = ar.upload(lo_d.data(), lo_d.size());
+    b.up_u = ar.upload(up_u.data(), up_u.size());
+    b.up_q = ar.upload(up_q.data(), up_q.size());
+    b.d_fsrc = ar.upload(b.fsrc.data(), b.fsrc.size());
+    b.d_bsrc = ar.upload(b.bsrc.data(), b.bsrc.size());
+    b.d_dsrc = ar.upload(b.dsrc.data(), b.dsrc.size());
+    b.fv = ar.template alloc<double>((size_t)nml * nn);
+    b.flag = ar.template alloc<int>(1);
+    b.dev_factor = true;
+    return true;
+}
+
+// The local-stage factor on st from A_ff and the fixed-stress terms in d.d_fs (uploaded on
+// st before), then the sweeps' value planes in T.
+template <int NF, int W, typename T>
+static void factor_sub_device(DFlow<T> &d, const DSystem &S, Staging &stg) {
+    SubBilu<T> &b = d.sb;
+    constexpr int NN = NF * NF;
+    const hipStream_t st = stg.st;
+    const size_t nsp = (size_t)d.nc * (NF - 1);
+    k::SubFactorLayout F{b.N, b.nml, b.ml_src, b.ml_fs, b.fdiag, b.lo_t, b.lo_d, b.up_u, b.up_q};
+    k::SubLayout L{b.N, b.sub_off, b.flev_off, b.blev_off, b.flev, b.blev, b.bpos, b.ncell, b.npos, b.fcol, b.bcol};
+    LAUNCH((k::fill<int>), 1, 0, st, b.flag, 0, (size_t)1);
+    LAUNCH((k::sub_factor_init<NF>), grid_for((size_t)b.nml), 0, st, F, (const double *)S.Aff.val,
+           (const double *)d.d_fs, (const double *)d.d_fs + nsp, b.fv);
+    hipLaunchKernelGGL((k::sub_factor<NF, W>), dim3(b.nsub), dim3(b.bs), 0, st, L, F, b.fv, b.flag);
+    PS_HIP(hipGetLastError());
+    LAUNCH((k::sub_factor_out<NN, T>), grid_for((size_t)W * b.N), 0, st, b.N, W, b.d_fsrc, (const double *)b.fv, b.fval);
+    LAUNCH((k::sub_factor_out<NN, T>), grid_for((size_t)W * b.N), 0, st, b.N, W, b.d_bsrc, (const double *)b.fv, b.bval);
+    LAUNCH((k::sub_factor_out<NN, T>), grid_for((size_t)b.N), 0, st, b.N, 1, b.d_dsrc, (const double *)b.fv, b.bdinv);
+    int *h = static_cast<int *>(stg.get(sizeof(int)));
+    PS_HIP(hipMemcpyAsync(h, b.flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    PS_HIP(hipStreamSynchronize(st));
+    if (*h) throw Error(PS_ESINGULAR, "singular BILU(0) pivot block");
 }
 
 // A level matrix of the device-built pressure hierarchy as a kernel operand: index arrays
@@ -748,7 +847,7 @@ static void adopt_hierarchy(DHierarchy<T> &d, const Hierarchy &H, const PresStor
 
 template <typename T>
 void update_flow_values(DFlow<T> &d, const FlowSetup &f, const System &s, const DSystem &S, const Options &o,
-                        Staging &stg, bool afu_changed) {
+                        Staging &stg, bool afu_changed, bool factor_on_device) {
     const int nf = s.nf, nc = s.n_cells, nn = nf * nf;
     static const std::vector<double> none;
     if (!d.layout) {
@@ -791,6 +890,10 @@ void update_flow_values(DFlow<T> &d, const FlowSetup &f, const System &s, const 
         };
         if (o.ml_kind == PS_BILU0 && layout_sub_bilu(d, f, s)) {
             d.sub = true;
+            if (d.sff_dslot && !device_factor_off()) {
+                HostSell hs = sell_from_bsr(f.Sff.rp, f.Sff.ci, none, nc, nf, nf, nullptr, nullptr, false);
+                layout_sub_factor(d, f, hs);
+            }
         } else if (o.ml_kind == PS_BILU0) {
             std::vector<int> of = order(f.sched.fwd_ptr, f.sched.fwd_rows, d.lchunk_f);
             std::vector<int> ob = order(f.sched.bwd_ptr, f.sched.bwd_rows, d.lchunk_b);
@@ -835,18 +938,27 @@ void update_flow_values(DFlow<T> &d, const FlowSetup &f, const System &s, const 
     }
     std::vector<double> dinv((size_t)nc * nn);
     if (d.sub) {
-        // each array is copied while the next one is scattered
-        TraceTick tt("values subdomain BILU");
         const SubBilu<T> &b = d.sb;
-        const size_t ne = (size_t)b.W * nn * nc, nd = (size_t)nn * nc;
-        T *out = static_cast<T *>(stg.get((2 * ne + nd) * sizeof(T)));
-        scatter_ell(out, b.fsrc, b.W, nc, nn, f.ml.v);
-        stg.copy_async(b.fval, out, ne * sizeof(T));
-        scatter_ell(out + ne, b.bsrc, b.W, nc, nn, f.ml.v);
-        stg.copy_async(b.bval, out + ne, ne * sizeof(T));
-        scatter_ell(out + 2 * ne, b.dsrc, 1, nc, nn, f.ml.v);
-        stg.copy_async(b.bdinv, out + 2 * ne, nd * sizeof(T));
-        stg.wait();
+        if (factor_on_device) {
+            if (!b.dev_factor) throw Error(PS_EDEVICE, "no device BILU(0) layout");
+            TraceTick tt("factor subdomain BILU");
+            if (nf == 2 && b.W == 3) factor_sub_device<2, 3, T>(d, S, stg);
+            else if (nf == 2) factor_sub_device<2, 8, T>(d, S, stg);
+            else if (b.W == 3) factor_sub_device<3, 3, T>(d, S, stg);
+            else factor_sub_device<3, 8, T>(d, S, stg);
+        } else {
+            // each array is copied while the next one is scattered
+            TraceTick tt("values subdomain BILU");
+            const size_t ne = (size_t)b.W * nn * nc, nd = (size_t)nn * nc;
+            T *out = static_cast<T *>(stg.get((2 * ne + nd) * sizeof(T)));
+            scatter_ell(out, b.fsrc, b.W, nc, nn, f.ml.v);
+            stg.copy_async(b.fval, out, ne * sizeof(T));
+            scatter_ell(out + ne, b.bsrc, b.W, nc, nn, f.ml.v);
+            stg.copy_async(b.bval, out + ne, ne * sizeof(T));
+            scatter_ell(out + 2 * ne, b.dsrc, 1, nc, nn, f.ml.v);
+            stg.copy_async(b.bdinv, out + 2 * ne, nd * sizeof(T));
+            stg.wait();
+        }
         dinv.clear();
     } else if (o.ml_kind == PS_BILU0) {
         upload_values(d.lf_val, d.src_lf, nn, f.ml.v, stg);
@@ -1420,9 +1532,9 @@ template Sell<float> upload_sell<float>(Arena &, const HostSell &);
 template std::unique_ptr<DHierarchy<double>> upload_hierarchy<double>(const Hierarchy &, int, bool);
 template std::unique_ptr<DHierarchy<float>> upload_hierarchy<float>(const Hierarchy &, int, bool);
 template void update_flow_values<double>(DFlow<double> &, const FlowSetup &, const System &, const DSystem &,
-                                         const Options &, Staging &, bool);
+                                         const Options &, Staging &, bool, bool);
 template void update_flow_values<float>(DFlow<float> &, const FlowSetup &, const System &, const DSystem &,
-                                        const Options &, Staging &, bool);
+                                        const Options &, Staging &, bool, bool);
 template void update_flow_pressure<double>(DFlow<double> &, const FlowSetup &, const Options &, const PresStore *);
 template void update_flow_pressure<float>(DFlow<float> &, const FlowSetup &, const Options &, const PresStore *);
 template void alloc_prec_work<double>(PrecWork<double> &, const DHierarchy<double> &, const DFlow<double> &, int);

@@ -1060,8 +1060,9 @@ void build_flow_operators(const System &s, FlowSetup &f) {
     quasi_impes(s, f.Sff, f.Spp, f.dss_inv);
 }
 
-void build_flow_local(const System &s, const Options &o, FlowSetup &f) {
+void build_flow_local(const System &s, const Options &o, FlowSetup &f, bool pattern_only) {
     Tick t("local stage factor");
+    if (o.ml_kind == PS_BILU0 && pattern_only && !f.sched.fwd_ptr.empty() && !f.ml.rp.empty()) return;
     if (o.ml_kind == PS_BILU0) {
         if (!s.ml_part.empty()) {
             restrict_to_parts(f.Sff, s.ml_part, f.ml);

@@ -98,7 +98,9 @@ BiluSchedule bilu_schedule(const Bsr &S);
 BiluSchedule color_schedule(const Bsr &S);             // colour groups in fwd_ptr/fwd_rows
 void build_flow(const System &s, const Options &o, FlowSetup &f);
 void build_flow_operators(const System &s, FlowSetup &f);            // S_ff^(fs), S_pp, D_ss^{-1}
-void build_flow_local(const System &s, const Options &o, FlowSetup &f);  // local-stage factors
+// local-stage factors; pattern_only: a BILU(0) factor whose pattern and schedule exist
+// is left to the device (f.ml keeps its pattern, its values are not recomputed)
+void build_flow_local(const System &s, const Options &o, FlowSetup &f, bool pattern_only = false);
 
 // Run f(begin, end, part) over [0, n) split into contiguous parts on host threads.
 void parallel_for(int n, const std::function<void(int, int, int)> &f);

@@ -938,6 +938,165 @@ __global__ __launch_bounds__(512) void bilu_sub(SubLayout L, const T *__restrict
     }
 }
 
+// Setup, processor-local BILU(0) (Sec. 5.3) on the device: the host's block ILU(0) of
+// the subdomain-restricted S_ff, operation for operation (no contraction), so that the
+// factor is bitwise the host's.
+struct SubFactorLayout {
+    int N, nml;
+    const int *ml_src, *ml_fs, *fdiag, *lo_t, *lo_d, *up_u, *up_q;
+};
+
+// factor values := restricted S_ff: A_ff's value plus, in a diagonal block's last column,
+// the fixed-stress term
+template <int NF>
+__global__ __launch_bounds__(WG) void sub_factor_init(SubFactorLayout F, const double *__restrict__ aff,
+                                                     const double *__restrict__ d_sp,
+                                                     const double *__restrict__ d_pp, double *__restrict__ fv) {
+    const int t = blockIdx.x * WG + threadIdx.x;
+    if (t >= F.nml) return;
+    const int c = F.ml_fs[t];
+    const size_t src = (size_t)F.ml_src[t];
+#pragma unroll
+    for (int e = 0; e < NF * NF; ++e) {
+        double v = aff[src + (size_t)e * 64];
+        if (c >= 0 && e % NF == NF - 1) v += e / NF < NF - 1 ? d_sp[(size_t)c * (NF - 1) + e / NF] : d_pp[c];
+        fv[(size_t)t * NF * NF + e] = v;
+    }
+}
+
+template <int NF>
+__device__ __forceinline__ void fac_mm(const double *a, const double *b, double *c) {
+#pragma clang fp contract(off)
+#pragma unroll
+    for (int i = 0; i < NF; ++i)
+#pragma unroll
+        for (int j = 0; j < NF; ++j) {
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < NF; ++k) s += a[i * NF + k] * b[k * NF + j];
+            c[i * NF + j] = s;
+        }
+}
+
+// Gauss-Jordan with partial pivoting (first largest |pivot|), as the host's small inverse
+template <int NF>
+__device__ __forceinline__ bool fac_inv(const double *a, double *inv) {
+#pragma clang fp contract(off)
+    double m[NF][2 * NF];
+#pragma unroll
+    for (int i = 0; i < NF; ++i)
+#pragma unroll
+        for (int j = 0; j < 2 * NF; ++j) m[i][j] = j < NF ? a[i * NF + j] : (j - NF == i ? 1.0 : 0.0);
+#pragma unroll
+    for (int c = 0; c < NF; ++c) {
+        int piv = c;
+#pragma unroll
+        for (int r = c + 1; r < NF; ++r)
+            if (fabs(m[r][c]) > fabs(m[piv][c])) piv = r;
+        double pv = 0.0;
+#pragma unroll
+        for (int r = 0; r < NF; ++r)
+            if (r == piv) pv = m[r][c];
+        if (pv == 0.0 || !isfinite(pv)) return false;
+        if (piv != c) {
+#pragma unroll
+            for (int r = c + 1; r < NF; ++r)
+                if (r == piv)
+#pragma unroll
+                    for (int j = 0; j < 2 * NF; ++j) {
+                        const double x = m[c][j];
+                        m[c][j] = m[r][j];
+                        m[r][j] = x;
+                    }
+        }
+        const double d = m[c][c];
+#pragma unroll
+        for (int j = 0; j < 2 * NF; ++j) m[c][j] /= d;
+#pragma unroll
+        for (int r = 0; r < NF; ++r) {
+            if (r == c) continue;
+            const double f = m[r][c];
+            if (f == 0.0) continue;
+#pragma unroll
+            for (int j = 0; j < 2 * NF; ++j) m[r][j] -= f * m[c][j];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NF; ++i)
+#pragma unroll
+        for (int j = 0; j < NF; ++j) {
+            inv[i * NF + j] = m[i][NF + j];
+            if (!isfinite(inv[i * NF + j])) return false;
+        }
+    return true;
+}
+
+// One workgroup per subdomain walks its forward levels; a row's blocks are its own during
+// its level and final after it (the barrier orders the levels).
+template <int NF, int W>
+__global__ __launch_bounds__(512) void sub_factor(SubLayout L, SubFactorLayout F, double *__restrict__ fv,
+                                                  int *__restrict__ flag) {
+#pragma clang fp contract(off)
+    constexpr int NN = NF * NF;
+    const int d = blockIdx.x, tid = threadIdx.x, bs = blockDim.x;
+    const size_t N = (size_t)F.N;
+    const int fb = L.flev_off[d], nfl = L.flev_off[d + 1] - fb;
+    for (int l = 0; l + 1 < nfl; ++l) {
+        const int r0 = L.flev[fb + l], r1 = L.flev[fb + l + 1];
+        for (int r = r0 + tid; r < r1; r += bs) {
+            for (int k = 0; k < W; ++k) {
+                const int t = F.lo_t[k * N + r];
+                if (t < 0) break;
+                const int kd = F.lo_d[k * N + r];
+                double a[NN], dk[NN], lk[NN];
+#pragma unroll
+                for (int e = 0; e < NN; ++e) {
+                    a[e] = fv[(size_t)t * NN + e];
+                    dk[e] = fv[(size_t)kd * NN + e];
+                }
+                fac_mm<NF>(a, dk, lk);                         // L_ik = A_ik D_k^-1
+#pragma unroll
+                for (int e = 0; e < NN; ++e) fv[(size_t)t * NN + e] = lk[e];
+                for (int m = 0; m < W; ++m) {
+                    const size_t slot = ((size_t)k * W + m) * N + r;
+                    const int u = F.up_u[slot];
+                    if (u < 0) break;
+                    const int q = F.up_q[slot];
+                    double ub[NN], pr[NN];
+#pragma unroll
+                    for (int e = 0; e < NN; ++e) ub[e] = fv[(size_t)u * NN + e];
+                    fac_mm<NF>(lk, ub, pr);                    // A_ij -= L_ik U_kj
+#pragma unroll
+                    for (int e = 0; e < NN; ++e) fv[(size_t)q * NN + e] = fv[(size_t)q * NN + e] - pr[e];
+                }
+            }
+            const int dd = F.fdiag[r];
+            double a[NN], inv[NN];
+#pragma unroll
+            for (int e = 0; e < NN; ++e) a[e] = fv[(size_t)dd * NN + e];
+            if (fac_inv<NF>(a, inv)) {
+#pragma unroll
+                for (int e = 0; e < NN; ++e) fv[(size_t)dd * NN + e] = inv[e];    // D_i^-1
+            } else {
+                flag[0] = 1;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ELL planes of the sweeps from the factor: out[(s*NN + q)*N + r] = fv[src[s*N + r]], as T
+template <int NN, typename T>
+__global__ __launch_bounds__(WG) void sub_factor_out(int N, int W, const int *__restrict__ src,
+                                                    const double *__restrict__ fv, T *__restrict__ out) {
+    const size_t g = (size_t)blockIdx.x * WG + threadIdx.x;
+    if (g >= (size_t)W * N) return;
+    const size_t s = g / N, r = g % N;
+    const int t = src[g];
+#pragma unroll
+    for (int q = 0; q < NN; ++q) out[(s * NN + q) * N + r] = t < 0 ? T(0) : (T)fv[(size_t)t * NN + q];
+}
+
 // Block-Jacobi sweep: delta = D^{-1}(w - S dz_in) (FIRST: D^{-1} w); dz_out = dz_in + delta;
 // FINAL: zout = [z_s; z_p] + dz_out.
 template <int NF, typename T, bool FIRST, bool FINAL>

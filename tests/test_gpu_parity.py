@@ -266,6 +266,41 @@ def test_subdomain_bilu_kernel_matches_level_kernels(ctx, case, precision, monke
         assert np.linalg.norm(za - ref) / np.linalg.norm(ref) <= 1e-10
 
 
+@pytest.mark.parametrize("precision", [ps.PS_FP64, ps.PS_FP32_PREC])
+@pytest.mark.parametrize("case", list(SUB_CASES))
+def test_device_bilu_factor_equals_host_factor(ctx, case, precision, monkeypatch):
+    """From the second setup of a handle on, the subdomain BILU(0) factor is computed on
+    the device from A_ff and the fixed-stress terms; it is the host's factor bit for bit,
+    also after new flow values arrive through ps_update_flow."""
+    from synth.jacobian import box_partition
+    spec, box, sweeps = SUB_CASES[case]
+    s, _ = workload(**spec)
+    s.ml_part = box_partition(*spec["grid"], *box)
+    s2, _ = workload(**dict(spec, seed=spec["seed"] + 10))
+    v = dev(np.random.default_rng(8).standard_normal(s.N))
+    out = []
+    for mode in ("host", None):
+        if mode:
+            monkeypatch.setenv("PS_BILU_FACTOR", mode)
+        else:
+            monkeypatch.delenv("PS_BILU_FACTOR", raising=False)
+        sv = make_solver(ctx, s, precision=precision, ml_sweeps=sweeps)   # first setup: host factor
+        sv.setup()                                                         # then the device's
+        z1 = dev(np.zeros(s.N))
+        sv.apply_precond(v, z1)
+        ps.ps_update_flow(sv.h, s2.Afu.vals, s2.Aff.vals, s2.d_sp, s2.d_pp)
+        sv.setup()
+        z2 = dev(np.zeros(s.N))
+        sv.apply_precond(v, z2)
+        out.append((host(z1), host(z2)))
+        sv.close()
+    monkeypatch.delenv("PS_BILU_FACTOR", raising=False)
+    (a1, a2), (b1, b2) = out
+    assert np.array_equal(a1, b1)
+    assert np.array_equal(a2, b2)
+    assert not np.array_equal(a1, a2)
+
+
 def test_solves_are_deterministic(ctx):
     s, b = small("grf12")
     sv = make_solver(ctx, s)
