@@ -174,6 +174,11 @@ bool galerkin_on_device() {
 
 bool use_fp32(const ps_handle *h) { return h->opt.precision == PS_FP32_PREC; }
 
+bool host_operators_forced() {
+    const char *e = std::getenv("PS_OPERATORS");
+    return e && std::string(e) == "host";
+}
+
 void ensure_mech_device(ps_handle *h, bool need64, bool need32) {
     std::lock_guard<std::mutex> lk(h->mech->mu);
     if (!h->mech->built) {
@@ -334,6 +339,11 @@ int ps_setup(ps_handle *h) {
         // the device from S_ff's values (the host keeps the pattern only)
         auto dev_factor_ready = [](const auto &fl) { return fl && fl->sub && fl->sb.dev_factor; };
         const bool dev_factor = (!f64 || dev_factor_ready(h->fl64)) && (!f32 || dev_factor_ready(h->fl32));
+        // and S_pp, D_ss (quasi-IMPES) and the pressure hierarchy come from the system on the
+        // device, with no host work in front of the pressure hierarchy (PS_OPERATORS=host:
+        // fixed stress and quasi-IMPES on the host at every setup)
+        const bool dev_ops = dev_factor && dev_rap && h->opt.smoother == PS_L1JAC &&
+                             h->pstore.npat == h->sys.n_cells && !host_operators_forced();
         // layouts (first call) and values of the flow stage that do not depend on the
         // pressure hierarchy, for the precisions in use
         auto flow_values = [&] {
@@ -341,17 +351,17 @@ int ps_setup(ps_handle *h) {
             if (f64) {
                 if (!h->fl64) h->fl64 = std::make_unique<DFlow<double>>();
                 update_flow_values<double>(*h->fl64, h->flow, h->sys, h->dsys, h->opt, h->staging, h->afu_changed,
-                                           dev_factor);
+                                           dev_factor, dev_ops);
             }
             if (f32) {
                 if (!h->fl32) h->fl32 = std::make_unique<DFlow<float>>();
                 update_flow_values<float>(*h->fl32, h->flow, h->sys, h->dsys, h->opt, h->staging, h->afu_changed,
-                                          dev_factor);
+                                          dev_factor, dev_ops);
             }
         };
         {
             PhaseTimer pt("flow setup");
-            build_flow_operators(h->sys, h->flow);
+            if (!dev_ops) build_flow_operators(h->sys, h->flow);
             if (dev_rap) {
                 // local-stage factors and the flow-stage value uploads on a host thread
                 // while the pressure hierarchy is built (its own copies run on the null
@@ -369,7 +379,13 @@ int ps_setup(ps_handle *h) {
                 });
                 try {
                     PhaseTimer pt2("pressure AMG (device)");
-                    build_pressure(h->flow.Spp, h->opt, h->flow.pres, h->pstore);
+                    if (dev_ops) {
+                        build_pressure_from_system(h->sys, h->dsys, h->opt, h->flow.pres, h->pstore);
+                    } else {
+                        build_pressure(h->flow.Spp, h->opt, h->flow.pres, h->pstore);
+                        if (h->opt.smoother == PS_L1JAC && h->pstore.npat == 0)
+                            layout_pressure_operator(h->sys, h->pstore);
+                    }
                 } catch (...) {
                     local.join();
                     throw;

@@ -130,6 +130,20 @@ struct DevCsr {
 // C = A B on the device, bitwise equal to the host product (galerkin.hip).
 void spgemm_device(const DevCsr &A, const DevCsr &B, DevCsr &C, Arena &out, Arena &tmp, hipStream_t st);
 
+// Pinned host buffer for value uploads, and the (non-blocking) stream its copies use, so
+// that uploads from a setup thread do not wait on work queued on the null stream.
+struct Staging {
+    void *p = nullptr;
+    size_t bytes = 0;
+    hipStream_t st = nullptr;
+    void *get(size_t n);
+    void copy_to_device(void *dev, const void *host, size_t n);   // returns when done
+    void copy_async(void *dev, const void *host, size_t n);       // queued; see wait()
+    void wait();
+    hipStream_t stream();                                          // created on first use
+    ~Staging();
+};
+
 // Pressure hierarchy whose Galerkin products are formed on the device: host levels in H
 // (operators copied back for the next coarsening and for inspection), FP64 device copies of
 // every A_l, P_l, R_l here, shared by the FP64 and FP32 preconditioners.
@@ -140,6 +154,13 @@ struct PresStore {
                                        // in H carry sizes only; cf and dinv are here
     std::vector<signed char *> cf;     // C/F splitting per level (1 C, -1 F)
     std::vector<double *> dinv;        // l1-Jacobi 1 / (a_ii + sum |a_ij|) per level
+    // S_pp formed on the device (quasi-IMPES from the system's A_ff and the fixed-stress
+    // terms) once its pattern, A_ff's block pattern, is laid out here (npat rows)
+    Arena pat;                         // kept across setups
+    int npat = 0, nnzpat = 0;
+    int *spp_rp = nullptr, *spp_ci = nullptr, *aff_dslot = nullptr, *flag = nullptr;
+    double *fs = nullptr;              // d_sp (n * (nf-1)) then d_pp (n)
+    Staging stg;
 };
 void build_pressure(const Csr &Spp, const Options &o, Hierarchy &H, PresStore &S);
 // operator and splitting of level lvl copied to the host (zeros on the coarsest level)
@@ -240,18 +261,6 @@ struct TraceTick {
     ~TraceTick();
 };
 
-// Pinned host buffer for value uploads, and the (non-blocking) stream its copies use, so
-// that uploads from a setup thread do not wait on work queued on the null stream.
-struct Staging {
-    void *p = nullptr;
-    size_t bytes = 0;
-    hipStream_t st = nullptr;
-    void *get(size_t n);
-    void copy_to_device(void *dev, const void *host, size_t n);   // returns when done
-    void copy_async(void *dev, const void *host, size_t n);       // queued; see wait()
-    void wait();
-    ~Staging();
-};
 
 template <typename T>
 struct PrecWork {                 // per-handle work vectors for Algorithm 1
@@ -263,6 +272,17 @@ struct PrecWork {                 // per-handle work vectors for Algorithm 1
     T *w = nullptr, *t = nullptr, *dz = nullptr, *r2 = nullptr;    // steps 6-8
     Arena arena;
 };
+
+struct DSystem;
+// S_pp's pattern and A_ff's diagonal slots (the first setup, after build_pressure)
+void layout_pressure_operator(const System &s, PresStore &S);
+// S_pp on the device from the system (S.npat > 0), then the hierarchy as build_pressure
+// (l1-Jacobi smoothing)
+void build_pressure_from_system(const System &s, const DSystem &D, const Options &o, Hierarchy &H, PresStore &S);
+// D_ss^{-1} of the quasi-IMPES reduction (Sec. 5.2) on the device, as T: dslot[i] is the
+// slot of row i's diagonal block in the SELL A_ff
+template <typename T>
+void dss_inverse_device(const DSystem &D, const int *dslot, T *dss_inv, hipStream_t st);
 
 struct DSystem {                  // FP64 system matrix for A z and the true residual
     int n_nodes = 0, n_cells = 0, nf = 0;
@@ -318,9 +338,12 @@ void upload_hierarchy_into(DHierarchy<T> &d, const Hierarchy &H, int smoother, b
 // device copies of the pressure hierarchy, adopted rather than uploaded, or nullptr).
 // factor_on_device: the local-stage BILU(0) factor is computed on the device from S_ff's
 // values (f.ml holds the pattern only); possible once d.sb.dev_factor is set.
+// operators_on_device: S_pp and D_ss are formed on the device too (f.Sff, f.dss_inv are not
+// recomputed on the host).
 template <typename T>
 void update_flow_values(DFlow<T> &d, const FlowSetup &f, const System &s, const DSystem &S, const Options &o,
-                        Staging &stg, bool afu_changed, bool factor_on_device = false);
+                        Staging &stg, bool afu_changed, bool factor_on_device = false,
+                        bool operators_on_device = false);
 template <typename T>
 void update_flow_pressure(DFlow<T> &d, const FlowSetup &f, const Options &o, const PresStore *ps);
 void upload_system(const System &s, DSystem &d);

@@ -410,9 +410,13 @@ void *Staging::get(size_t n) {
     return p;
 }
 
-void Staging::copy_async(void *dev, const void *host, size_t n) {
+hipStream_t Staging::stream() {
     if (!st) PS_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-    if (n) PS_HIP(hipMemcpyAsync(dev, host, n, hipMemcpyHostToDevice, st));
+    return st;
+}
+
+void Staging::copy_async(void *dev, const void *host, size_t n) {
+    if (n) PS_HIP(hipMemcpyAsync(dev, host, n, hipMemcpyHostToDevice, stream()));
 }
 
 void Staging::wait() {
@@ -738,7 +742,7 @@ template <int NF, int W, typename T>
 static void factor_sub_device(DFlow<T> &d, const DSystem &S, Staging &stg) {
     SubBilu<T> &b = d.sb;
     constexpr int NN = NF * NF;
-    const hipStream_t st = stg.st;
+    const hipStream_t st = stg.stream();
     const size_t nsp = (size_t)d.nc * (NF - 1);
     k::SubFactorLayout F{b.N, b.nml, b.ml_src, b.ml_fs, b.fdiag, b.lo_t, b.lo_d, b.up_u, b.up_q};
     k::SubLayout L{b.N, b.sub_off, b.flev_off, b.blev_off, b.flev, b.blev, b.bpos, b.ncell, b.npos, b.fcol, b.bcol};
@@ -847,7 +851,7 @@ static void adopt_hierarchy(DHierarchy<T> &d, const Hierarchy &H, const PresStor
 
 template <typename T>
 void update_flow_values(DFlow<T> &d, const FlowSetup &f, const System &s, const DSystem &S, const Options &o,
-                        Staging &stg, bool afu_changed, bool factor_on_device) {
+                        Staging &stg, bool afu_changed, bool factor_on_device, bool operators_on_device) {
     const int nf = s.nf, nc = s.n_cells, nn = nf * nf;
     static const std::vector<double> none;
     if (!d.layout) {
@@ -925,16 +929,22 @@ void update_flow_values(DFlow<T> &d, const FlowSetup &f, const System &s, const 
             stg.copy_to_device(d.d_fs, h, (size_t)nc * nf * sizeof(double));
             const unsigned g = grid_for((size_t)S.Aff.nchunks * 64);
             if (nf == 2)
-                LAUNCH((k::sff_from_aff<2, T>), g, 0, stg.st, S.Aff, (const double *)d.d_fs,
+                LAUNCH((k::sff_from_aff<2, T>), g, 0, stg.stream(), S.Aff, (const double *)d.d_fs,
                        (const double *)d.d_fs + nsp, d.sff_dslot, d.sff_val);
             else
-                LAUNCH((k::sff_from_aff<3, T>), g, 0, stg.st, S.Aff, (const double *)d.d_fs,
+                LAUNCH((k::sff_from_aff<3, T>), g, 0, stg.stream(), S.Aff, (const double *)d.d_fs,
                        (const double *)d.d_fs + nsp, d.sff_dslot, d.sff_val);
-            PS_HIP(hipStreamSynchronize(stg.st));
+            stg.wait();
         } else {
             upload_values(d.sff_val, d.src_sff, nn, f.Sff.v, stg);
         }
-        upload_dense(d.dss_inv, f.dss_inv, stg);
+        if (operators_on_device) {
+            if (!d.sff_dslot) throw Error(PS_EDEVICE, "no device S_ff layout");
+            dss_inverse_device<T>(S, d.sff_dslot, d.dss_inv, stg.stream());
+            stg.wait();
+        } else {
+            upload_dense(d.dss_inv, f.dss_inv, stg);
+        }
     }
     std::vector<double> dinv((size_t)nc * nn);
     if (d.sub) {
@@ -1532,9 +1542,9 @@ template Sell<float> upload_sell<float>(Arena &, const HostSell &);
 template std::unique_ptr<DHierarchy<double>> upload_hierarchy<double>(const Hierarchy &, int, bool);
 template std::unique_ptr<DHierarchy<float>> upload_hierarchy<float>(const Hierarchy &, int, bool);
 template void update_flow_values<double>(DFlow<double> &, const FlowSetup &, const System &, const DSystem &,
-                                         const Options &, Staging &, bool, bool);
+                                         const Options &, Staging &, bool, bool, bool);
 template void update_flow_values<float>(DFlow<float> &, const FlowSetup &, const System &, const DSystem &,
-                                        const Options &, Staging &, bool, bool);
+                                        const Options &, Staging &, bool, bool, bool);
 template void update_flow_pressure<double>(DFlow<double> &, const FlowSetup &, const Options &, const PresStore *);
 template void update_flow_pressure<float>(DFlow<float> &, const FlowSetup &, const Options &, const PresStore *);
 template void alloc_prec_work<double>(PrecWork<double> &, const DHierarchy<double> &, const DFlow<double> &, int);

@@ -479,6 +479,67 @@ void spgemm_device(const DevCsr &A, const DevCsr &B, DevCsr &C, Arena &out, Aren
     PS_HIP(hipStreamSynchronize(st));
 }
 
+// Quasi-IMPES reduction (Sec. 5.2) from the system's A_ff in SELL-64 (one lane per cell
+// row) and the fixed-stress terms: the same operations as the host's, without contraction.
+// D_ss^{-1} into dss (if given); S_pp's values, on A_ff's block pattern (rp), into spp (if
+// given): the pressure-row, pressure-column entry of each S_ff block less t_i times its
+// saturation-row entries, t_i = D_ps,i D_ss,i^{-1}.  flag (if given) is set for a singular D_ss.
+template <int NF, typename TD>
+__global__ void qimpes_k(Sell<double> A, const int *__restrict__ rp, const int *__restrict__ dslot,
+                         const double *__restrict__ d_sp, const double *__restrict__ d_pp, int n,
+                         double *__restrict__ spp, TD *__restrict__ dss, int *__restrict__ flag) {
+#pragma clang fp contract(off)
+    constexpr int NN = NF * NF;
+    const int i = blockIdx.x * TB + threadIdx.x;
+    if (i >= n) return;
+    const int lane = i & 63, s0 = A.cptr[i >> 6], ds = dslot[i];
+    auto val = [&](int k, int e) { return A.val[((size_t)(s0 + k) * NN + e) * 64 + lane]; };
+    double t0 = 0.0, t1 = 0.0;
+    if (NF == 2) {
+        const double dss_ = val(ds, 0), dps = val(ds, NF * (NF - 1) + 0);
+        if (dss_ == 0.0) {
+            if (flag) flag[0] = 1;
+            return;
+        }
+        t0 = dps / dss_;
+        if (dss) dss[i] = (TD)(1.0 / dss_);
+    } else {
+        const double a = val(ds, 0 * NF + 0), b = val(ds, 0 * NF + 1), c = val(ds, 1 * NF + 0), d = val(ds, 1 * NF + 1);
+        const double det = a * d - b * c;
+        if (det == 0.0 || !isfinite(det)) {
+            if (flag) flag[0] = 1;
+            return;
+        }
+        const double i00 = d / det, i01 = -b / det, i10 = -c / det, i11 = a / det;
+        const double p0 = val(ds, (NF - 1) * NF + 0), p1 = val(ds, (NF - 1) * NF + 1);
+        t0 = p0 * i00 + p1 * i10;
+        t1 = p0 * i01 + p1 * i11;
+        if (dss) {
+            dss[(size_t)i * 4 + 0] = (TD)i00;
+            dss[(size_t)i * 4 + 1] = (TD)i01;
+            dss[(size_t)i * 4 + 2] = (TD)i10;
+            dss[(size_t)i * 4 + 3] = (TD)i11;
+        }
+    }
+    if (!spp) return;
+    const int r0 = rp[i], len = rp[i + 1] - r0;
+    for (int k = 0; k < len; ++k) {
+        double app = val(k, (NF - 1) * NF + NF - 1), sp0 = val(k, 0 * NF + NF - 1);
+        double sp1 = NF == 3 ? val(k, 1 * NF + NF - 1) : 0.0;
+        if (k == ds) {                      // fixed-stress terms of the diagonal block
+            sp0 += d_sp[(size_t)i * (NF - 1) + 0];
+            if (NF == 3) sp1 += d_sp[(size_t)i * (NF - 1) + 1];
+            app += d_pp[i];
+        }
+        if (NF == 2) {
+            spp[r0 + k] = app - t0 * sp0;
+        } else {
+            const double s0v = t0 * sp0, s1v = t1 * sp1;
+            spp[r0 + k] = app - (s0v + s1v);
+        }
+    }
+}
+
 static DevCsr upload(Arena &ar, const Csr &A) {
     DevCsr d;
     d.n = A.n;
@@ -541,13 +602,13 @@ static void build_pressure_hybrid(const Csr &Spp, const Options &o, Hierarchy &H
 // same results as the host build; only counts come back per step, and the coarsest
 // operator at the end for its dense inverse.  H holds the level sizes and the coarse
 // inverse; the operators, splittings and smoother data stay in S.
-static void build_pressure_device(const Csr &Spp, const Options &o, Hierarchy &H, PresStore &S) {
+// Levels of the l1-Jacobi hierarchy from the level-0 operator A, all on the device.
+static void build_pressure_levels(DevCsr A, const Options &o, Hierarchy &H, PresStore &S) {
     const hipStream_t st = 0;
     auto zero = [&](int *p, long long n) {
         hipLaunchKernelGGL(fill_int, dim3(blocks(n)), dim3(TB), 0, st, p, 0, n);
     };
     int *ctr = S.arena.alloc<int>(4);
-    DevCsr A = upload(S.arena, Spp);
     while (A.n > o.coarse_max && (int)H.lev.size() + 1 < o.max_levels) {
         const int n = A.n, nnz = A.nnz;
         TraceTick lt("pressure level");
@@ -658,7 +719,7 @@ static void build_pressure_device(const Csr &Spp, const Options &o, Hierarchy &H
     coarse_level(download(A), H);
 }
 
-void build_pressure(const Csr &Spp, const Options &o, Hierarchy &H, PresStore &S) {
+static void clear_store(Hierarchy &H, PresStore &S) {
     H = Hierarchy();
     S.arena.recycle();
     S.A.clear();
@@ -666,11 +727,82 @@ void build_pressure(const Csr &Spp, const Options &o, Hierarchy &H, PresStore &S
     S.R.clear();
     S.cf.clear();
     S.dinv.clear();
+}
+
+void build_pressure(const Csr &Spp, const Options &o, Hierarchy &H, PresStore &S) {
+    clear_store(H, S);
     S.on_device = o.smoother == PS_L1JAC;
-    if (S.on_device) build_pressure_device(Spp, o, H, S);
+    if (S.on_device) build_pressure_levels(upload(S.arena, Spp), o, H, S);
     else build_pressure_hybrid(Spp, o, H, S);
     S.arena.trim();          // blocks of an earlier, larger hierarchy that were not reused
 }
+
+void layout_pressure_operator(const System &s, PresStore &S) {
+    const Bsr &A = s.Aff;
+    const int n = A.nbr;
+    std::vector<int> dslot(n, -1);
+    for (int i = 0; i < n; ++i)
+        for (int t = A.rp[i]; t < A.rp[i + 1]; ++t)
+            if (A.ci[t] == i) dslot[i] = t - A.rp[i];
+    for (int i = 0; i < n; ++i)
+        if (dslot[i] < 0) throw Error(PS_EINVAL, "A_ff row without a diagonal block");
+    S.pat.release();
+    S.spp_rp = S.pat.upload(A.rp.data(), A.rp.size());
+    S.spp_ci = S.pat.upload(A.ci.data(), A.ci.size());
+    S.aff_dslot = S.pat.upload(dslot.data(), dslot.size());
+    S.fs = S.pat.alloc<double>((size_t)n * s.nf);
+    S.flag = S.pat.alloc<int>(1);
+    S.nnzpat = A.rp[n];
+    S.npat = n;
+}
+
+void build_pressure_from_system(const System &s, const DSystem &D, const Options &o, Hierarchy &H, PresStore &S) {
+    if (S.npat != s.n_cells || o.smoother != PS_L1JAC) throw Error(PS_EDEVICE, "pressure operator not laid out");
+    clear_store(H, S);
+    S.on_device = true;
+    const int n = s.n_cells, nf = s.nf;
+    const size_t nsp = (size_t)n * (nf - 1);
+    double *h = static_cast<double *>(S.stg.get((size_t)n * nf * sizeof(double)));
+    std::memcpy(h, s.d_sp.data(), nsp * sizeof(double));
+    std::memcpy(h + nsp, s.d_pp.data(), (size_t)n * sizeof(double));
+    S.stg.copy_to_device(S.fs, h, (size_t)n * nf * sizeof(double));
+    DevCsr A;
+    A.n = A.m = n;
+    A.nnz = S.nnzpat;
+    A.rp = S.spp_rp;
+    A.ci = S.spp_ci;
+    A.v = S.arena.alloc<double>(S.nnzpat);
+    const hipStream_t st = 0;
+    hipLaunchKernelGGL(fill_int, dim3(1), dim3(TB), 0, st, S.flag, 0, 1ll);
+    if (nf == 2)
+        hipLaunchKernelGGL((qimpes_k<2, double>), dim3(blocks(n)), dim3(TB), 0, st, D.Aff, (const int *)S.spp_rp,
+                           (const int *)S.aff_dslot, (const double *)S.fs, (const double *)S.fs + nsp, n, A.v,
+                           (double *)nullptr, S.flag);
+    else
+        hipLaunchKernelGGL((qimpes_k<3, double>), dim3(blocks(n)), dim3(TB), 0, st, D.Aff, (const int *)S.spp_rp,
+                           (const int *)S.aff_dslot, (const double *)S.fs, (const double *)S.fs + nsp, n, A.v,
+                           (double *)nullptr, S.flag);
+    if (read_back(S.flag, st)) throw Error(PS_ESINGULAR, nf == 2 ? "zero D_ss entry" : "singular D_ss block");
+    build_pressure_levels(A, o, H, S);
+    S.arena.trim();
+}
+
+template <typename T>
+void dss_inverse_device(const DSystem &D, const int *dslot, T *dss_inv, hipStream_t st) {
+    const int n = D.n_cells;
+    if (D.nf == 2)
+        hipLaunchKernelGGL((qimpes_k<2, T>), dim3(blocks(n)), dim3(TB), 0, st, D.Aff, (const int *)nullptr, dslot,
+                           (const double *)nullptr, (const double *)nullptr, n, (double *)nullptr, dss_inv,
+                           (int *)nullptr);
+    else
+        hipLaunchKernelGGL((qimpes_k<3, T>), dim3(blocks(n)), dim3(TB), 0, st, D.Aff, (const int *)nullptr, dslot,
+                           (const double *)nullptr, (const double *)nullptr, n, (double *)nullptr, dss_inv,
+                           (int *)nullptr);
+    PS_HIP(hipGetLastError());
+}
+
+template void dss_inverse_device<double>(const DSystem &, const int *, double *, hipStream_t);
+template void dss_inverse_device<float>(const DSystem &, const int *, float *, hipStream_t);
 
 void download_level(const PresStore &S, int lvl, Csr &A, std::vector<int8_t> &cf) {
     A = download(S.A.at(lvl));

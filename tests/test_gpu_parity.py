@@ -301,6 +301,53 @@ def test_device_bilu_factor_equals_host_factor(ctx, case, precision, monkeypatch
     assert not np.array_equal(a1, a2)
 
 
+@pytest.mark.parametrize("precision", [ps.PS_FP64, ps.PS_FP32_PREC])
+@pytest.mark.parametrize("case", ["grf_boxes", "three_phase"])
+def test_device_operators_equal_host_operators(ctx, case, precision, monkeypatch):
+    """From the second setup of an l1-Jacobi handle on, S_pp and D_ss (quasi-IMPES) and
+    the local-stage factor are formed on the device from the system's A_ff and the
+    fixed-stress terms: every pressure level, the preconditioner and the solve are those
+    of the host-formed operators bit for bit, also after ps_update_flow."""
+    from synth.jacobian import box_partition
+    spec, box, sweeps = SUB_CASES[case]
+    s, b = workload(**spec)
+    s.ml_part = box_partition(*spec["grid"], *box)
+    s2, _ = workload(**dict(spec, seed=spec["seed"] + 10))
+    v = dev(np.random.default_rng(9).standard_normal(s.N))
+    out = []
+    for mode in ("host", None):
+        for var in ("PS_OPERATORS", "PS_BILU_FACTOR"):
+            if mode:
+                monkeypatch.setenv(var, mode)
+            else:
+                monkeypatch.delenv(var, raising=False)
+        sv = make_solver(ctx, s, precision=precision, ml_sweeps=sweeps, smoother=ps.PS_L1JAC)
+        res = []
+        for new_values in (False, True):
+            if new_values:
+                ps.ps_update_flow(sv.h, s2.Afu.vals, s2.Aff.vals, s2.d_sp, s2.d_pp)
+            sv.setup()
+            nl = sv.pressure_level(0)["nlevels"]
+            levels = [sv.pressure_level(l) for l in range(nl)]
+            z = dev(np.zeros(s.N))
+            sv.apply_precond(v, z)
+            x = dev(np.zeros(s.N))
+            r = sv.solve(dev(b), x, 1e-8)
+            res.append((levels, host(z), r, host(x)))
+        out.append(res)
+        sv.close()
+    for var in ("PS_OPERATORS", "PS_BILU_FACTOR"):
+        monkeypatch.delenv(var, raising=False)
+    for (la, za, ra, xa), (lb, zb, rb, xb) in zip(out[0], out[1]):
+        assert len(la) == len(lb)
+        for p, q in zip(la, lb):
+            for key in ("rowptr", "colind", "vals", "cf"):
+                assert np.array_equal(p[key], q[key]), key
+        assert np.array_equal(za, zb)
+        assert ra["status"] == rb["status"] and ra["iterations"] == rb["iterations"]
+        assert np.array_equal(xa, xb)
+
+
 def test_solves_are_deterministic(ctx):
     s, b = small("grf12")
     sv = make_solver(ctx, s)
