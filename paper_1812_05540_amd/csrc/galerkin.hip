@@ -69,11 +69,14 @@ __global__ void segment_starts(const long long *__restrict__ h, const long long 
     if (p == 0) start[sid[n - 1]] = n;
 }
 
-__global__ void segment_sums(const long long *__restrict__ start, long long S, const double *__restrict__ vals,
-                             double *__restrict__ sum, long long *__restrict__ nz) {
+// (S, the number of segments, is read from the device; nz is defined on 0..P, zero from S
+// on, so that its scan over P + 1 entries ends with the number of nonzero sums)
+__global__ void segment_sums(const long long *__restrict__ start, const long long *__restrict__ Sp, long long P,
+                             const double *__restrict__ vals, double *__restrict__ sum, long long *__restrict__ nz) {
     long long s = (long long)blockIdx.x * TB + threadIdx.x;
-    if (s > S) return;
-    if (s == S) {
+    const long long S = *Sp;
+    if (s > P) return;
+    if (s >= S) {
         nz[s] = 0;
         return;
     }
@@ -83,12 +86,12 @@ __global__ void segment_sums(const long long *__restrict__ start, long long S, c
     nz[s] = acc != 0.0 ? 1 : 0;
 }
 
-__global__ void scatter(const long long *__restrict__ start, long long S, const unsigned long long *__restrict__ keys,
-                        const double *__restrict__ sum, const long long *__restrict__ nz,
-                        const long long *__restrict__ pos, int cbits, int *__restrict__ ci,
-                        double *__restrict__ v, int *__restrict__ rowcnt) {
+__global__ void scatter(const long long *__restrict__ start, const long long *__restrict__ Sp,
+                        const unsigned long long *__restrict__ keys, const double *__restrict__ sum,
+                        const long long *__restrict__ nz, const long long *__restrict__ pos, int cbits,
+                        int *__restrict__ ci, double *__restrict__ v, int *__restrict__ rowcnt) {
     long long s = (long long)blockIdx.x * TB + threadIdx.x;
-    if (s >= S || !nz[s]) return;
+    if (s >= *Sp || !nz[s]) return;
     const unsigned long long key = keys[start[s]];
     const long long q = pos[s];
     ci[q] = (int)(key & ((1ull << cbits) - 1));
@@ -436,7 +439,7 @@ void spgemm_device(const DevCsr &A, const DevCsr &B, DevCsr &C, Arena &out, Aren
         exclusive_scan(tmp, cnt, off, (size_t)A.nnz + 1, st);
         P = read_back(off + A.nnz, st);
     }
-    long long S = 0, *start = nullptr, *nz = nullptr, *pos = nullptr;
+    long long *start = nullptr, *nz = nullptr, *pos = nullptr, *Sp = nullptr;
     unsigned long long *kout = nullptr;
     double *sum = nullptr;
     if (P > 0) {
@@ -458,23 +461,25 @@ void spgemm_device(const DevCsr &A, const DevCsr &B, DevCsr &C, Arena &out, Aren
         PS_HIP(rocprim::inclusive_scan(nullptr, sb, h, sid, (size_t)P, rocprim::plus<long long>(), st));
         void *w2 = tmp.alloc<char>(sb);
         PS_HIP(rocprim::inclusive_scan(w2, sb, h, sid, (size_t)P, rocprim::plus<long long>(), st));
-        S = read_back(sid + P - 1, st);
-        start = tmp.alloc<long long>((size_t)S + 1);
+        // the segment count S = sid[P-1] stays on the device: the segment arrays are sized P
+        Sp = sid + P - 1;
+        start = tmp.alloc<long long>((size_t)P + 1);
         hipLaunchKernelGGL(segment_starts, dim3(blocks(P)), dim3(TB), 0, st, h, sid, P, start);
-        sum = tmp.alloc<double>(S);
-        nz = tmp.alloc<long long>((size_t)S + 1);
-        pos = tmp.alloc<long long>((size_t)S + 1);
-        hipLaunchKernelGGL(segment_sums, dim3(blocks(S + 1)), dim3(TB), 0, st, start, S, vout, sum, nz);
-        exclusive_scan(tmp, nz, pos, (size_t)S + 1, st);
+        sum = tmp.alloc<double>(P);
+        nz = tmp.alloc<long long>((size_t)P + 1);
+        pos = tmp.alloc<long long>((size_t)P + 1);
+        hipLaunchKernelGGL(segment_sums, dim3(blocks(P + 1)), dim3(TB), 0, st, start, (const long long *)Sp, P, vout,
+                           sum, nz);
+        exclusive_scan(tmp, nz, pos, (size_t)P + 1, st);
     }
-    const long long nnz = S > 0 ? read_back(pos + S, st) : 0;
+    const long long nnz = P > 0 ? read_back(pos + P, st) : 0;
     if (nnz >= (1ll << 31)) throw Error(PS_EINVAL, "Galerkin product exceeds 2^31 entries");
     C.nnz = (int)nnz;
     C.ci = out.alloc<int>((size_t)nnz);
     C.v = out.alloc<double>((size_t)nnz);
     if (nnz > 0)
-        hipLaunchKernelGGL(scatter, dim3(blocks(S)), dim3(TB), 0, st, start, S, kout, sum, nz, pos, cbits, C.ci,
-                           C.v, rowcnt);
+        hipLaunchKernelGGL(scatter, dim3(blocks(P)), dim3(TB), 0, st, start, (const long long *)Sp, kout, sum, nz, pos,
+                           cbits, C.ci, C.v, rowcnt);
     exclusive_scan(tmp, rowcnt, C.rp, (size_t)A.n + 1, st);
     PS_HIP(hipStreamSynchronize(st));
 }
@@ -609,6 +614,8 @@ static void build_pressure_levels(DevCsr A, const Options &o, Hierarchy &H, Pres
         hipLaunchKernelGGL(fill_int, dim3(blocks(n)), dim3(TB), 0, st, p, 0, n);
     };
     int *ctr = S.arena.alloc<int>(4);
+    int *zdiag = ctr + 1;                 // a zero diagonal on some level (checked once, at the end)
+    zero(zdiag, 1);
     while (A.n > o.coarse_max && (int)H.lev.size() + 1 < o.max_levels) {
         const int n = A.n, nnz = A.nnz;
         TraceTick lt("pressure level");
@@ -629,8 +636,8 @@ static void build_pressure_levels(DevCsr A, const Options &o, Hierarchy &H, Pres
         int *srp = S.work.alloc<int>((size_t)n + 1), *trp = S.work.alloc<int>((size_t)n + 1);
         exclusive_scan(S.tmp, scount, srp, (size_t)n + 1, st);
         exclusive_scan(S.tmp, lam, trp, (size_t)n + 1, st);
-        const int ns = read_back(srp + n, st);
-        int *sci = S.work.alloc<int>(ns), *tci = S.work.alloc<int>(ns), *cur = S.work.alloc<int>(n);
+        // S and S^T hold at most nnz entries (no read-back of the exact count)
+        int *sci = S.work.alloc<int>(nnz), *tci = S.work.alloc<int>(nnz), *cur = S.work.alloc<int>(n);
         hipLaunchKernelGGL(fill_s_k, dim3(blocks(n)), dim3(TB), 0, st, A.rp, A.ci, smask, n, srp, sci);
         PS_HIP(hipMemcpyAsync(cur, trp, sizeof(int) * n, hipMemcpyDeviceToDevice, st));
         hipLaunchKernelGGL(fill_st_k, dim3(blocks(n)), dim3(TB), 0, st, srp, sci, n, cur, tci);
@@ -639,10 +646,10 @@ static void build_pressure_levels(DevCsr A, const Options &o, Hierarchy &H, Pres
         signed char *cf = S.arena.alloc<signed char>(n), *newc = S.work.alloc<signed char>(n);
         zero(ctr, 1);
         hipLaunchKernelGGL(pmis_init_k, dim3(blocks(n)), dim3(TB), 0, st, trp, n, w, cf, ctr);
-        // two rounds per read-back of the undecided count (a round with nothing undecided
-        // changes nothing)
+        // two rounds per read-back of the undecided count, the first two before any (a round
+        // with nothing undecided changes nothing)
         int rounds = 0;
-        for (int und = read_back(ctr, st); und > 0; und = read_back(ctr, st)) {
+        for (int und = n > 0 ? 1 : 0; und > 0; und = read_back(ctr, st)) {
             for (int k = 0; k < 2; ++k) {
                 if (++rounds > n + 1) throw Error(PS_EDEVICE, "PMIS did not terminate");   // each round decides >= 1 point
                 hipLaunchKernelGGL(pmis_select_k, dim3(blocks(n)), dim3(TB), 0, st, cf, w, srp, sci, trp, tci, n, newc);
@@ -655,7 +662,7 @@ static void build_pressure_levels(DevCsr A, const Options &o, Hierarchy &H, Pres
         zero(ctr, 1);
         hipLaunchKernelGGL(promo_init_k, dim3(blocks(n)), dim3(TB), 0, st, cf, srp, sci, n, cs, ctr);
         rounds = 0;
-        for (int und = read_back(ctr, st); und > 0; und = read_back(ctr, st)) {
+        for (int und = n > 0 ? 1 : 0; und > 0; und = read_back(ctr, st)) {
             for (int k = 0; k < 2; ++k) {
                 if (++rounds > n + 1) throw Error(PS_EDEVICE, "C-promotion did not terminate");
                 zero(ctr, 1);
@@ -696,9 +703,7 @@ static void build_pressure_levels(DevCsr A, const Options &o, Hierarchy &H, Pres
         hipLaunchKernelGGL(sort_rows_k, dim3(blocks(nc)), dim3(TB), 0, st, R.rp, nc, R.ci, R.v);
         // smoother diagonal
         double *dinv = S.arena.alloc<double>(n);
-        zero(ctr, 1);
-        hipLaunchKernelGGL(l1_inv_k, dim3(blocks(n)), dim3(TB), 0, st, A.rp, A.ci, A.v, n, dinv, ctr);
-        if (read_back(ctr, st) != 0) throw Error(PS_ESINGULAR, "zero diagonal in an AMG level");
+        hipLaunchKernelGGL(l1_inv_k, dim3(blocks(n)), dim3(TB), 0, st, A.rp, A.ci, A.v, n, dinv, zdiag);
         // Galerkin product
         DevCsr AP, Ac;
         S.tmp.recycle();
@@ -716,6 +721,7 @@ static void build_pressure_levels(DevCsr A, const Options &o, Hierarchy &H, Pres
         A = Ac;
     }
     S.A.push_back(A);
+    if (read_back(zdiag, st) != 0) throw Error(PS_ESINGULAR, "zero diagonal in an AMG level");
     coarse_level(download(A), H);
 }
 
