@@ -1354,7 +1354,11 @@ __global__ __launch_bounds__(WG) void gemv_sub_mdot(const double *__restrict__ V
     __shared__ double hs[SUBDOT_MAXV];
     __shared__ double part[4][64];
     __shared__ double wn[64];
+    __shared__ double part2[WG];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    // V_k . w over a tile: nq threads per vector, each over 64 / nq consecutive elements
+    // (eight when at most 32 vectors leave most threads idle; measured slower for more)
+    const int nq = nv <= 32 ? 8 : 1, span = 64 / nq, kq = tid / nq, part_ = tid % nq;
     for (int t = tid; t < nv; t += WG) hs[t] = h[t];
     const size_t i0 = (size_t)blockIdx.x * chunk;
     const int len = i0 < n ? (int)((n - i0) < (size_t)chunk ? (n - i0) : (size_t)chunk) : 0;
@@ -1394,15 +1398,23 @@ __global__ __launch_bounds__(WG) void gemv_sub_mdot(const double *__restrict__ V
             wn[lane] = wv;
         }
         __syncthreads();
-        if (tid < nv) {
+        if (kq < nv) {
             double d = 0.0;
+            const int e0p = part_ * span;
 #pragma unroll 8
-            for (int e = 0; e < 64; ++e) d += tile[tid * 65 + e] * wn[e];
+            for (int e = 0; e < span; ++e) d += tile[kq * 65 + e0p + e] * wn[e0p + e];
             acc += d;
         }
         __syncthreads();
     }
-    if (tid < nv) partial[(size_t)tid * nblk + blockIdx.x] = acc;
+    // the nq partial dot products of each vector, added in order
+    part2[tid] = acc;
+    __syncthreads();
+    if (tid < nv) {
+        double d = part2[tid * nq];
+        for (int q = 1; q < nq; ++q) d += part2[tid * nq + q];
+        partial[(size_t)tid * nblk + blockIdx.x] = d;
+    }
 }
 
 // Givens update of Hessenberg column j (column-major, leading dimension m+1).
