@@ -170,14 +170,15 @@ void download_level(const PresStore &S, int lvl, Csr &A, std::vector<int8_t> &cf
 // power of two chosen from the mean row length).  G <= 0: SELL-64, one lane per row; entry
 // k of row i at (cptr[i / 64] + k) * 64 + i % 64 of ci and v (padding never read), the
 // row's length from rp; G == -1: the columns stored as 16-bit offsets from the row (cd)
-// instead of ci.  An operator A takes SELL-64 when its slices pad it little.
+// instead of ci.  G > 64: CSR with G - 64 lanes per row and 16-bit column offsets (cd).  An
+// operator A takes SELL-64 when its slices pad it little.
 template <typename T>
 struct DCsr {
     int n = 0, G = 1;
     const int *rp = nullptr, *ci = nullptr;
     const T *v = nullptr;
     const int *cptr = nullptr;    // SELL-64 only: first slot of each 64-row slice
-    const short *cd = nullptr;    // G == -1 only: column - row per slot
+    const short *cd = nullptr;    // G == -1 or G > 64: column - row per stored entry
 };
 
 template <typename T>

@@ -281,7 +281,27 @@ static DCsr<T> upload_csr(Arena &ar, const Csr &A, bool sell) {
         d.v = ar.upload(v.data(), v.size());
         return d;
     }
-    d.ci = ar.upload(A.ci.data(), A.ci.size());
+    // an operator's columns as 16-bit offsets from the row when every one fits
+    bool fits = sell && A.n > 0;
+    std::vector<short> cd;
+    if (fits) {
+        cd.resize(A.ci.size());
+        for (int i = 0; i < A.n && fits; ++i)
+            for (int t = A.rp[i]; t < A.rp[i + 1]; ++t) {
+                const int dlt = A.ci[t] - i;
+                if (dlt < -32768 || dlt > 32767) {
+                    fits = false;
+                    break;
+                }
+                cd[t] = (short)dlt;
+            }
+    }
+    if (fits) {
+        d.G += 64;
+        d.cd = ar.upload(cd.data(), cd.size());
+    } else {
+        d.ci = ar.upload(A.ci.data(), A.ci.size());
+    }
     std::vector<T> v(A.v.begin(), A.v.end());
     d.v = ar.upload(v.data(), v.size());
     return d;
@@ -1060,7 +1080,14 @@ static void with_G(int G, F &&f) {
     case 4: f(std::integral_constant<int, 4>{}); break;
     case 8: f(std::integral_constant<int, 8>{}); break;
     case 16: f(std::integral_constant<int, 16>{}); break;
-    default: f(std::integral_constant<int, 32>{}); break;
+    case 32: f(std::integral_constant<int, 32>{}); break;
+    case 65: f(std::integral_constant<int, 65>{}); break;
+    case 66: f(std::integral_constant<int, 66>{}); break;
+    case 68: f(std::integral_constant<int, 68>{}); break;
+    case 72: f(std::integral_constant<int, 72>{}); break;
+    case 80: f(std::integral_constant<int, 80>{}); break;
+    case 96: f(std::integral_constant<int, 96>{}); break;
+    default: throw Error(PS_EDEVICE, "level matrix layout");
     }
 }
 
@@ -1068,7 +1095,7 @@ template <int MODE, typename T>
 static void csr_spmv(const DCsr<T> &A, const T *x, const T *b, T *y, hipStream_t st) {
     with_G(A.G, [&](auto Gc) {
         constexpr int G = decltype(Gc)::value;
-        LAUNCH((k::csr_spmv<G, MODE, T>), grid_for((size_t)A.n * (G > 0 ? G : 1)), 0, st, A, x, b, y);
+        LAUNCH((k::csr_spmv<G, MODE, T>), grid_for((size_t)A.n * k::lanes_of<G>()), 0, st, A, x, b, y);
     });
 }
 
@@ -1084,7 +1111,7 @@ static void vcycle(const DHierarchy<T> &H, HierWork<T> &W, int l, const T *b, T 
     const bool cheb = H.smoother == PS_CHEB2;
     with_G(L.A.G, [&](auto Gc) {
         constexpr int G = decltype(Gc)::value;
-        unsigned g = grid_for((size_t)L.n * (G > 0 ? G : 1));
+        unsigned g = grid_for((size_t)L.n * k::lanes_of<G>());
         if (cheb) {
             LAUNCH((k::csr_cheb_pre<G, T>), g, 0, st, L.A, b, L.c0, L.c1, L.cm, W.x[l]);
             LAUNCH((k::csr_spmv<G, 1, T>), g, 0, st, L.A, (const T *)W.x[l], b, W.r[l]);
@@ -1097,7 +1124,7 @@ static void vcycle(const DHierarchy<T> &H, HierWork<T> &W, int l, const T *b, T 
     if (!cheb && l + 1 < last) {
         with_G(L.R.G, [&](auto Gc) {
             constexpr int G = decltype(Gc)::value;
-            LAUNCH((k::csr_restrict_l1<G, T>), grid_for((size_t)L.R.n * (G > 0 ? G : 1)), 0, st, L.R,
+            LAUNCH((k::csr_restrict_l1<G, T>), grid_for((size_t)L.R.n * k::lanes_of<G>()), 0, st, L.R,
                    (const T *)W.r[l], H.lev[l + 1].dinv, W.b[l + 1], W.x[l + 1]);
         });
     } else {
@@ -1107,7 +1134,7 @@ static void vcycle(const DHierarchy<T> &H, HierWork<T> &W, int l, const T *b, T 
     csr_spmv<2, T>(L.P, (const T *)W.e[l + 1], (const T *)nullptr, W.x[l], st);
     with_G(L.A.G, [&](auto Gc) {
         constexpr int G = decltype(Gc)::value;
-        unsigned g = grid_for((size_t)L.n * (G > 0 ? G : 1));
+        unsigned g = grid_for((size_t)L.n * k::lanes_of<G>());
         if (cheb) {
             LAUNCH((k::csr_cheb_post1<G, T>), g, 0, st, L.A, b, (const T *)W.x[l], L.c0, W.x1[l], W.d[l]);
             LAUNCH((k::csr_cheb_post2<G, T>), g, 0, st, L.A, b, (const T *)W.x1[l], (const T *)W.d[l], L.c1,
@@ -1434,10 +1461,8 @@ void Fgmres::enqueue_iteration() {
         LAUNCH((k::gemv_sub<true>), K_.nblk, 0, st_, (const double *)K_.V, N, nv, (const double *)K_.h2, w, N,
                K_.chunk, K_.partial);
     }
-    LAUNCH(k::reduce_rows, 1, 0, st_, (const double *)K_.partial, K_.nblk, K_.nw2, (const double *)nullptr,
-           (double *)nullptr);
     LAUNCH(k::givens, 1, 0, st_, j, m, (const double *)K_.hsum, (const double *)(K_.h1 + nv),
-           (const double *)K_.nw2, K_.H, K_.cs, K_.sn, K_.g, K_.scal, K_.hostscal);
+           (const double *)K_.partial, K_.nblk, K_.H, K_.cs, K_.sn, K_.g, K_.scal, K_.hostscal);
     phase_ = ITER;
 }
 

@@ -306,35 +306,44 @@ __global__ __launch_bounds__(WG) void csr_to_sell(const int *__restrict__ rp, co
 // (four of a lane's entries are loaded before any is used, so their index loads and
 // gathers overlap; past the row's end the loads repeat its last entry and are not added;
 // the sum still runs in increasing t)
+// lanes per row of a level kernel: G for CSR (G + 64: CSR with 16-bit column offsets from
+// the row in cd), one for SELL-64 (G <= 0)
+template <int G>
+constexpr int lanes_of() {
+    return G <= 0 ? 1 : G > 64 ? G - 64 : G;
+}
+
 template <int G, bool S, typename T>
 __device__ __forceinline__ T csr_dot(const DCsr<T> &A, int i, int g, const T *__restrict__ x,
                                      const T *__restrict__ s) {
     if constexpr (G <= 0) {
         return sell_dot<S, G == -1>(A, i, x, s);
     } else {
+        constexpr int GL = lanes_of<G>();
+        constexpr bool DELTA = G > 64;
         T acc = T(0);
         const int e = A.rp[i + 1];
-        for (int t = A.rp[i] + g; t < e; t += 4 * G) {
+        for (int t = A.rp[i] + g; t < e; t += 4 * GL) {
             int c[4];
             T a[4], xv[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int tt = t + u * G < e ? t + u * G : e - 1;
-                c[u] = A.ci[tt];
+                const int tt = t + u * GL < e ? t + u * GL : e - 1;
+                c[u] = DELTA ? i + (int)A.cd[tt] : A.ci[tt];
                 a[u] = A.v[tt];
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) xv[u] = S ? x[c[u]] * s[c[u]] : x[c[u]];
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-                if (t + u * G < e) acc += a[u] * xv[u];
+                if (t + u * GL < e) acc += a[u] * xv[u];
         }
-        return group_sum<G>(acc);
+        return group_sum<GL>(acc);
     }
 }
 
 #define PS_CSR_ROW(G)                                         \
-    constexpr int LPR_ = G > 0 ? G : 1;                       \
+    constexpr int LPR_ = lanes_of<G>();                       \
     int gid = blockIdx.x * WG + threadIdx.x;                  \
     int i = gid / LPR_, g = gid % LPR_;                       \
     if (i >= A.n) return;
@@ -1418,18 +1427,26 @@ __global__ __launch_bounds__(WG) void gemv_sub_mdot(const double *__restrict__ V
 }
 
 // Givens update of Hessenberg column j (column-major, leading dimension m+1).
-// h: j+1 orthogonalisation coefficients; nrm[0] = |A z_j|^2, nrm[1] = |w|^2.
+// h: j+1 orthogonalisation coefficients; naz2[0] = |A z_j|^2; |w|^2 is the sum of the nblk
+// chunk partials wpart, added as reduce_rows adds them (the same bits).
 // scal out: [0] |g_{j+1}|, [1] h_{j+1,j}, [2] |A z_j|, [3] breakdown flag.
 __global__ __launch_bounds__(WG) void givens(int j, int m, const double *__restrict__ h,
-                                            const double *__restrict__ naz2, const double *__restrict__ nw2,
-                                            double *__restrict__ H, double *__restrict__ cs,
+                                            const double *__restrict__ naz2, const double *__restrict__ wpart,
+                                            int nblk, double *__restrict__ H, double *__restrict__ cs,
                                             double *__restrict__ sn, double *__restrict__ g,
                                             double *__restrict__ scal, double *__restrict__ hscal) {
     // the column and the previous rotations are staged in LDS by the workgroup; one thread
     // applies the rotations in order (a dependent chain), the workgroup writes back
     __shared__ double col[MAXV + 1], c[MAXV], s[MAXV];
-    __shared__ double out[4];
+    __shared__ double out[4], red[4];
+    __shared__ double nw2[1];
     const int tid = threadIdx.x;
+    {
+        double a = 0.0;
+        for (int b = tid; b < nblk; b += WG) a += wpart[b];
+        a = block_sum(a, red);
+        if (tid == 0) nw2[0] = a;
+    }
     for (int i = tid; i <= j; i += WG) {
         col[i] = h[i];
         if (i < j) {
