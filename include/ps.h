@@ -136,7 +136,10 @@ int  ps_update_flow(ps_handle *h, const double *afu_vals, const double *aff_vals
 /* Setup phase (Sec. 5.4): fixed-stress and quasi-IMPES operators, pressure AMG,
  * BILU(0) factors, FP32 mirrors; the mechanics AMG is built on the first call
  * (or taken from another handle with the same mech_key) and kept.  Every call
- * rebuilds the flow stage.  Synchronous. */
+ * rebuilds the flow stage: the first on host threads and the device (it also lays out
+ * the patterns), later ones, with l1-Jacobi smoothing and subdomain BILU(0), on the
+ * device from the system's A_ff and fixed-stress terms, with the same results bit for
+ * bit.  Synchronous. */
 int  ps_setup(ps_handle *h);
 
 /* Solve A x = rhs to |b - A x| <= rtol |b| with FGMRES(restart) and Algorithm 1.
