@@ -1,5 +1,5 @@
 """GPU checks at the full sizes of the benchmark workloads, in the configuration bench.py
-times (processor-local BILU(0) on 32x32x16-cell subdomains, l1-Jacobi smoothing).
+times (processor-local BILU(0) on 32x16x16-cell subdomains, l1-Jacobi smoothing).
 
 The oracle cannot run the whole solve at these sizes, so the checks are the ones that
 hold at any size: the system SpMV on sampled rows computed one by one from the block
@@ -44,7 +44,7 @@ def big(name):
     if name not in _cache:
         s, b = workload(name)
         nx, ny, nz = s.meta["grid"]
-        s.ml_part = box_partition(nx, ny, nz, 32, 32, 16)
+        s.ml_part = box_partition(nx, ny, nz, 32, 16, 16)
         _cache[name] = (s, b)
     return _cache[name]
 
