@@ -382,14 +382,33 @@ __global__ void transpose_fill_k(const int *__restrict__ rp, const int *__restri
     }
 }
 
+// Each row's entries in increasing column order (stable), one wavefront per row: a row of
+// at most 64 entries is held one entry per lane and each lane's rank is counted with
+// shuffles; a longer row is insertion-sorted by its first lane.
 __global__ void sort_rows_k(const int *__restrict__ rp, int n, int *__restrict__ ci, double *__restrict__ v) {
-    int r = blockIdx.x * TB + threadIdx.x;
-    if (r >= n) return;
-    for (int a = rp[r] + 1; a < rp[r + 1]; ++a) {
+    const int r = (int)(((long long)blockIdx.x * TB + threadIdx.x) >> 6), lane = threadIdx.x & 63;
+    if (r >= n) return;                      // uniform over the wavefront
+    const int r0 = rp[r], len = rp[r + 1] - r0;
+    if (len <= 64) {
+        const int c = lane < len ? ci[r0 + lane] : 0x7fffffff;
+        const double x = lane < len ? v[r0 + lane] : 0.0;
+        int rank = 0;
+        for (int k = 0; k < len; ++k) {
+            const int ck = __shfl(c, k, 64);
+            rank += ck < c || (ck == c && k < lane);
+        }
+        if (lane < len) {
+            ci[r0 + rank] = c;
+            v[r0 + rank] = x;
+        }
+        return;
+    }
+    if (lane != 0) return;
+    for (int a = r0 + 1; a < r0 + len; ++a) {
         const int c = ci[a];
         const double x = v[a];
         int b = a - 1;
-        while (b >= rp[r] && ci[b] > c) {
+        while (b >= r0 && ci[b] > c) {
             ci[b + 1] = ci[b];
             v[b + 1] = v[b];
             --b;
@@ -700,7 +719,7 @@ static void build_pressure_levels(DevCsr A, const Options &o, Hierarchy &H, Pres
         R.v = S.arena.alloc<double>(R.nnz);
         PS_HIP(hipMemcpyAsync(rcur, R.rp, sizeof(int) * nc, hipMemcpyDeviceToDevice, st));
         hipLaunchKernelGGL(transpose_fill_k, dim3(blocks(n)), dim3(TB), 0, st, P.rp, P.ci, P.v, n, rcur, R.ci, R.v);
-        hipLaunchKernelGGL(sort_rows_k, dim3(blocks(nc)), dim3(TB), 0, st, R.rp, nc, R.ci, R.v);
+        hipLaunchKernelGGL(sort_rows_k, dim3(blocks((long long)nc * 64)), dim3(TB), 0, st, R.rp, nc, R.ci, R.v);
         // smoother diagonal
         double *dinv = S.arena.alloc<double>(n);
         hipLaunchKernelGGL(l1_inv_k, dim3(blocks(n)), dim3(TB), 0, st, A.rp, A.ci, A.v, n, dinv, zdiag);
