@@ -1438,18 +1438,29 @@ void Fgmres::enqueue_iteration() {
     if (nv >= 16 && nv <= k::SUBDOT_MAXV) {          // below ~16 vectors two passes are as fast
         ktime::Scope ts(ktime::CGS2_FUSED, st_, (nv + 2) * vb);
         const size_t shm = (size_t)nv * 65 * sizeof(double);
-        if (nv <= 32)
-            LAUNCH((k::gemv_sub_mdot<8>), K_.nblk, shm, st_, (const double *)K_.V, N, nv, (const double *)K_.h1, w,
+        // RW rows per wavefront: above 32 vectors the next even number of at least nv / 4, so
+        // that few loads repeat a row past nv (measured: 4% faster for 33..64 vectors, the same
+        // above; at most 32 vectors RW = 8 throughout is as fast as the finer choice)
+        auto fused = [&](auto rwc) {
+            constexpr int RW = decltype(rwc)::value;
+            LAUNCH((k::gemv_sub_mdot<RW>), K_.nblk, shm, st_, (const double *)K_.V, N, nv, (const double *)K_.h1, w,
                    N, K_.chunk, K_.partial, K_.nblk);
-        else if (nv <= 64)
-            LAUNCH((k::gemv_sub_mdot<16>), K_.nblk, shm, st_, (const double *)K_.V, N, nv, (const double *)K_.h1, w,
-                   N, K_.chunk, K_.partial, K_.nblk);
-        else if (nv <= 96)
-            LAUNCH((k::gemv_sub_mdot<24>), K_.nblk, shm, st_, (const double *)K_.V, N, nv, (const double *)K_.h1, w,
-                   N, K_.chunk, K_.partial, K_.nblk);
-        else
-            LAUNCH((k::gemv_sub_mdot<28>), K_.nblk, shm, st_, (const double *)K_.V, N, nv, (const double *)K_.h1, w,
-                   N, K_.chunk, K_.partial, K_.nblk);
+        };
+        switch ((nv + 7) / 8) {
+        case 2:
+        case 3:
+        case 4: fused(std::integral_constant<int, 8>{}); break;
+        case 5: fused(std::integral_constant<int, 10>{}); break;
+        case 6: fused(std::integral_constant<int, 12>{}); break;
+        case 7: fused(std::integral_constant<int, 14>{}); break;
+        case 8: fused(std::integral_constant<int, 16>{}); break;
+        case 9: fused(std::integral_constant<int, 18>{}); break;
+        case 10: fused(std::integral_constant<int, 20>{}); break;
+        case 11: fused(std::integral_constant<int, 22>{}); break;
+        case 12: fused(std::integral_constant<int, 24>{}); break;
+        case 13: fused(std::integral_constant<int, 26>{}); break;
+        default: fused(std::integral_constant<int, 28>{}); break;
+        }
     } else {
         LAUNCH((k::gemv_sub<false>), K_.nblk, 0, st_, (const double *)K_.V, N, nv, (const double *)K_.h1, w, N,
                K_.chunk, K_.partial);
