@@ -129,7 +129,8 @@ void ps_ctx_destroy(ps_ctx *ctx);
 int  ps_create(ps_ctx *ctx, const ps_system *sys, const ps_options *opts, ps_handle **out);
 
 /* Replace the flow blocks (Afu, Aff values and d_sp, d_pp; same patterns) as
- * after a Newton step; the next ps_setup rebuilds the flow stage only. */
+ * after a Newton step: the values are copied into the device layout in place (the
+ * displacement blocks stay); the next ps_setup rebuilds the flow stage only. */
 int  ps_update_flow(ps_handle *h, const double *afu_vals, const double *aff_vals,
                     const double *d_sp, const double *d_pp);
 

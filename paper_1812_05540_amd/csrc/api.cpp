@@ -306,16 +306,8 @@ int ps_update_flow(ps_handle *h, const double *afu, const double *aff, const dou
         take(s.d_sp, d_sp);
         take(s.d_pp, d_pp);
         set_device(h->ctx->device);
-        DSystem fresh;
-        upload_system(s, fresh);
-        h->dsys.arena = std::move(fresh.arena);
-        h->dsys.Auu = fresh.Auu;
-        h->dsys.Auf = fresh.Auf;
-        h->dsys.Afu = fresh.Afu;
-        h->dsys.Aff = fresh.Aff;
-        h->dsys.n_nodes = fresh.n_nodes;
-        h->dsys.n_cells = fresh.n_cells;
-        h->dsys.nf = fresh.nf;
+        // only the flow blocks' values cross PCIe, into the resident layout
+        update_system_flow_values(s, h->dsys, h->staging);
         h->ready = false;
         return PS_OK;
     });

@@ -289,6 +289,7 @@ struct DSystem {                  // FP64 system matrix for A z and the true res
     int n_nodes = 0, n_cells = 0, nf = 0;
     Sell<double> Auu, Auf, Afu, Aff;
     double mat_bytes = 0.0;       // algorithmic bytes of the four blocks (values, columns, row pointers)
+    std::vector<int> src_afu, src_aff;   // SELL slot -> block of A_fu, A_ff (host), for new values
     Arena arena;
 };
 
@@ -348,6 +349,8 @@ void update_flow_values(DFlow<T> &d, const FlowSetup &f, const System &s, const 
 template <typename T>
 void update_flow_pressure(DFlow<T> &d, const FlowSetup &f, const Options &o, const PresStore *ps);
 void upload_system(const System &s, DSystem &d);
+// new values of A_fu and A_ff (same patterns) into d's layout, through stg
+void update_system_flow_values(const System &s, DSystem &d, Staging &stg);
 template <typename T>
 void alloc_prec_work(PrecWork<T> &w, const DHierarchy<T> &sdc, const DFlow<T> &fl, int n_nodes);
 void alloc_krylov(Krylov &k, size_t N, int m, bool z_fp32);

@@ -1018,10 +1018,23 @@ void upload_system(const System &s, DSystem &d) {
     d.nf = s.nf;
     d.Auu = upload_sell<double>(d.arena, sell_from_bsr(s.Auu.rp, s.Auu.ci, s.Auu.v, s.n_nodes, 3, 3));
     d.Auf = upload_sell<double>(d.arena, sell_from_bsr(s.Auf.rp, s.Auf.ci, s.Auf.v, s.n_nodes, 3, s.nf));
-    d.Afu = upload_sell<double>(d.arena, sell_from_bsr(s.Afu.rp, s.Afu.ci, s.Afu.v, s.n_cells, s.nf, 3));
-    d.Aff = upload_sell<double>(d.arena, sell_from_bsr(s.Aff.rp, s.Aff.ci, s.Aff.v, s.n_cells, s.nf, s.nf));
+    {
+        HostSell h = sell_from_bsr(s.Afu.rp, s.Afu.ci, s.Afu.v, s.n_cells, s.nf, 3);
+        d.Afu = upload_sell<double>(d.arena, h);
+        d.src_afu = std::move(h.src);
+    }
+    {
+        HostSell h = sell_from_bsr(s.Aff.rp, s.Aff.ci, s.Aff.v, s.n_cells, s.nf, s.nf);
+        d.Aff = upload_sell<double>(d.arena, h);
+        d.src_aff = std::move(h.src);
+    }
     auto blk = [](const Bsr &b) { return (double)b.nb() * (b.br * b.bc * 8 + 4) + 4.0 * b.rp.size(); };
     d.mat_bytes = blk(s.Auu) + blk(s.Auf) + blk(s.Afu) + blk(s.Aff);
+}
+
+void update_system_flow_values(const System &s, DSystem &d, Staging &stg) {
+    upload_values(const_cast<double *>(d.Afu.val), d.src_afu, s.nf * 3, s.Afu.v, stg);
+    upload_values(const_cast<double *>(d.Aff.val), d.src_aff, s.nf * s.nf, s.Aff.v, stg);
 }
 
 template <typename T>
