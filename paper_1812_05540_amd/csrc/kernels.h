@@ -472,7 +472,8 @@ __global__ __launch_bounds__(WG) void step23(Sell<T> Afu, const double *__restri
 #pragma unroll
         for (int r = 0; r < NF; ++r)
 #pragma unroll
-            for (int e = 0; e < 3; ++e) acc[r] += val[((size_t)k * (NF * 3) + r * 3 + e) * 64] * xv[e];
+            for (int e = 0; e < 3; ++e)
+                acc[r] += __builtin_nontemporal_load(&val[((size_t)k * (NF * 3) + r * 3 + e) * 64]) * xv[e];
     }
     T yv[NF];
 #pragma unroll
@@ -534,7 +535,8 @@ __global__ __launch_bounds__(WG) void step6(Sell<T> S, const T *__restrict__ y, 
 #pragma unroll
         for (int r = 0; r < NF; ++r)
 #pragma unroll
-            for (int e = 0; e < NF; ++e) acc[r] += val[((size_t)k * (NF * NF) + r * NF + e) * 64] * xv[e];
+            for (int e = 0; e < NF; ++e)
+                acc[r] += __builtin_nontemporal_load(&val[((size_t)k * (NF * NF) + r * NF + e) * 64]) * xv[e];
     }
 #pragma unroll
     for (int r = 0; r < NF; ++r) wout[(size_t)i * NF + r] = y[(size_t)i * NF + r] - acc[r];
@@ -563,7 +565,8 @@ __global__ __launch_bounds__(WG) void bilu_fwd(Sell<T> L, int pos0, int pos1, co
 #pragma unroll
         for (int r = 0; r < NF; ++r)
 #pragma unroll
-            for (int e = 0; e < NF; ++e) acc[r] += val[((size_t)k * (NF * NF) + r * NF + e) * 64] * xv[e];
+            for (int e = 0; e < NF; ++e)
+                acc[r] += __builtin_nontemporal_load(&val[((size_t)k * (NF * NF) + r * NF + e) * 64]) * xv[e];
     }
 #pragma unroll
     for (int r = 0; r < NF; ++r) t[(size_t)row * NF + r] = win[(size_t)row * NF + r] - acc[r];
@@ -597,7 +600,8 @@ __global__ __launch_bounds__(WG) void bilu_bwd(Sell<T> U, int pos0, int pos1, T 
 #pragma unroll
         for (int r = 0; r < NF; ++r)
 #pragma unroll
-            for (int e = 0; e < NF; ++e) acc[r] += val[((size_t)k * (NF * NF) + r * NF + e) * 64] * xv[e];
+            for (int e = 0; e < NF; ++e)
+                acc[r] += __builtin_nontemporal_load(&val[((size_t)k * (NF * NF) + r * NF + e) * 64]) * xv[e];
     }
     T rv[NF], dl[NF];
 #pragma unroll
@@ -647,7 +651,8 @@ __device__ __forceinline__ void bilu_row_fwd(const Sell<T> &L, int pos, const T 
 #pragma unroll
         for (int r = 0; r < NF; ++r)
 #pragma unroll
-            for (int e = 0; e < NF; ++e) acc[r] += val[((size_t)k * (NF * NF) + r * NF + e) * 64] * xv[e];
+            for (int e = 0; e < NF; ++e)
+                acc[r] += __builtin_nontemporal_load(&val[((size_t)k * (NF * NF) + r * NF + e) * 64]) * xv[e];
     }
 #pragma unroll
     for (int r = 0; r < NF; ++r) t[(size_t)row * NF + r] = win[(size_t)row * NF + r] - acc[r];
@@ -685,7 +690,8 @@ __device__ __forceinline__ void bilu_row_bwd(const Sell<T> &U, int pos, T *__res
 #pragma unroll
         for (int r = 0; r < NF; ++r)
 #pragma unroll
-            for (int e = 0; e < NF; ++e) acc[r] += val[((size_t)k * (NF * NF) + r * NF + e) * 64] * xv[e];
+            for (int e = 0; e < NF; ++e)
+                acc[r] += __builtin_nontemporal_load(&val[((size_t)k * (NF * NF) + r * NF + e) * 64]) * xv[e];
     }
     T rv[NF], dl[NF];
 #pragma unroll
