@@ -62,8 +62,12 @@ def _strength_matrix(A, smask):
                          shape=(n, n))
 
 
-def pmis(A, smask):
-    """C/F splitting (array of C_PT / F_PT), PMIS followed by C-promotion."""
+def pmis(A, smask, rounds=None, promote=True):
+    """C/F splitting (array of C_PT / F_PT), PMIS followed by C-promotion.
+
+    rounds: stop after this many PMIS rounds (undecided points stay UNDEC); promote:
+    apply the C-promotion pass.  Both exist so that tests can inspect the rounds.
+    """
     n = A.shape[0]
     S = _strength_matrix(A, smask)
     ST = S.T.tocsr()
@@ -74,7 +78,9 @@ def pmis(A, smask):
     state[lam == 0] = F_PT
     G = (S + ST).tocoo()
     gi, gj = G.row, G.col
-    while np.any(state == UNDEC):
+    done = 0
+    while np.any(state == UNDEC) and (rounds is None or done < rounds):
+        done += 1
         und = state == UNDEC
         e = und[gi] & und[gj]
         bigger = (w[gj] > w[gi]) | ((w[gj] == w[gi]) & (gj > gi))
@@ -84,6 +90,8 @@ def pmis(A, smask):
         state[newc] = C_PT
         hit = (S @ newc.astype(np.int32)) > 0
         state[(state == UNDEC) & hit] = F_PT
+    if not promote:
+        return state
     # C-promotion, sequential in increasing i
     hasc = (S @ (state == C_PT).astype(np.int32)) > 0
     for i in np.nonzero((state == F_PT) & (nS > 0) & ~hasc)[0]:

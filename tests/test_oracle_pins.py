@@ -252,9 +252,122 @@ def test_pmis_split_invariants():
     hasc[rows[smask & (state[A.indices] == amg.C_PT)]] = True
     nS = np.bincount(rows[smask], minlength=A.shape[0])
     assert np.all(hasc | (state == amg.C_PT) | (nS == 0))
-    # points chosen in the first PMIS round are never strongly connected to each other
     nC = np.sum(state == amg.C_PT)
     assert 0.1 * A.shape[0] < nC < 0.6 * A.shape[0]
+    # C points before promotion are never strongly connected to each other
+    pre = amg.pmis(A, smask, promote=False)
+    cpos = rows[smask]
+    assert not np.any((pre[cpos] == amg.C_PT) & (pre[A.indices[smask]] == amg.C_PT))
+
+
+def _aniso_graph(nx=7, ny=6, seed=5):
+    """Non-symmetric 9-point operator on an nx x ny grid with random, anisotropic
+    couplings, so that S is not symmetric and the weights differ from point to point."""
+    rng = np.random.default_rng(seed)
+    n = nx * ny
+    A = sp.lil_matrix((n, n))
+    for j in range(ny):
+        for i in range(nx):
+            r = i + nx * j
+            for dj in (-1, 0, 1):
+                for di in (-1, 0, 1):
+                    ii, jj = i + di, j + dj
+                    if (di, dj) == (0, 0) or not (0 <= ii < nx and 0 <= jj < ny):
+                        continue
+                    base = 1.0 if dj == 0 else (0.35 if di == 0 else 0.12)
+                    A[r, ii + nx * jj] = -base * (0.5 + rng.random())
+            A[r, r] = 6.0
+    A = A.tocsr()
+    A.sort_indices()
+    return A
+
+
+def _brute_pmis(A, theta):
+    """PMIS (De Sterck, Yang, Heys) written out point by point from its definition:
+    returns (state after round 1, state after all rounds, state after C-promotion),
+    each a dict i -> 'C' | 'F' | 'U'."""
+    from oracle.rng import unit
+    n = A.shape[0]
+    Ad = A.toarray()
+    S = []
+    for i in range(n):
+        offs = {j: -Ad[i, j] for j in range(n) if j != i and A[i, j] != 0}
+        m = max(offs.values()) if offs else -np.inf
+        S.append({j for j, v in offs.items() if m > 0 and v >= theta * m})
+    ST = [{k for k in range(n) if i in S[k]} for i in range(n)]
+    w = [len(ST[i]) + float(unit(np.uint64(i))) for i in range(n)]
+    state = {i: ("F" if len(ST[i]) == 0 else "U") for i in range(n)}
+    snaps = []
+    while any(v == "U" for v in state.values()):
+        und = [i for i in range(n) if state[i] == "U"]
+        newc = [i for i in und
+                if all((w[i], i) > (w[j], j) for j in (S[i] | ST[i]) if state[j] == "U")]
+        for i in newc:
+            state[i] = "C"
+        for k in und:
+            if state[k] == "U" and any(state[c] == "C" and c in newc for c in S[k]):
+                state[k] = "F"
+        snaps.append(dict(state))
+    after = dict(state)
+    for i in range(n):
+        if state[i] == "F" and S[i] and not any(state[j] == "C" for j in S[i]):
+            state[i] = "C"
+    return snaps[0], after, dict(state), S
+
+
+def _as_letters(state):
+    return {i: {amg.C_PT: "C", amg.F_PT: "F", amg.UNDEC: "U"}[int(v)] for i, v in enumerate(state)}
+
+
+def test_pmis_brute_force_rounds():
+    """PMIS round by round against a point-by-point brute force on a small
+    non-symmetric graph: the first round's C set is exactly the points whose (w_i, i)
+    beats every undecided neighbour in S_i u S_i^T, its F set the undecided points that
+    strongly depend on a new C point; the final splitting (before and after C-promotion)
+    matches, and C before promotion is independent in S u S^T."""
+    A = _aniso_graph()
+    smask = amg.strength(A, 0.25)
+    first, before, final, S = _brute_pmis(A, 0.25)
+    assert sum(v == "U" for v in first.values()) > 0          # the graph needs several rounds
+    assert _as_letters(amg.pmis(A, smask, rounds=1, promote=False)) == first
+    assert _as_letters(amg.pmis(A, smask, promote=False)) == before
+    assert _as_letters(amg.pmis(A, smask)) == final
+    C = [i for i, v in before.items() if v == "C"]
+    for i in C:
+        for j in C:
+            assert j not in S[i], (i, j)
+    # every F point with strong connections depends on a C point after promotion
+    for i, v in final.items():
+        if v == "F" and S[i]:
+            assert any(final[j] == "C" for j in S[i])
+
+
+def test_direct_interpolation_hand_computed_row():
+    """One F row of direct interpolation worked by hand (Stueben): row 0 has a strong C
+    neighbour (col 1, -2), a weak C neighbour (col 2, -0.3 < 0.25 * 2), a positive entry
+    (col 3, +0.5) and a strong F neighbour (col 4, -1).
+      atil_00 = 4 + 0.5 = 4.5 (positive entries lumped into the diagonal)
+      alpha_0 = (-2 - 0.3 - 1) / (-2) = 1.65
+      P_01    = -alpha_0 * (-2) / atil_00 = 3.3 / 4.5
+    and no weight on the weak C neighbour or on the positive entry's column."""
+    A = sp.csr_matrix(np.array([
+        [4.0, -2.0, -0.3, 0.5, -1.0],
+        [-1.0, 3.0, -1.0, 0.0, 0.0],
+        [0.0, -1.0, 3.0, -1.0, 0.0],
+        [0.0, 0.0, -1.0, 3.0, -1.0],
+        [-1.0, 0.0, 0.0, -1.5, 4.0],
+    ]))
+    A.sort_indices()
+    smask = amg.strength(A, 0.25)
+    state = np.array([amg.F_PT, amg.C_PT, amg.C_PT, amg.C_PT, amg.F_PT], np.int8)
+    P_ = dense(amg.direct_interpolation(A, smask, state))
+    assert P_.shape == (5, 3)
+    assert abs(P_[0, 0] - 3.3 / 4.5) < 1e-15
+    assert P_[0, 1] == 0.0 and P_[0, 2] == 0.0
+    # row 4: strong neighbours 0 (F, -1) and 3 (C, -1.5); no positive entries
+    #   alpha = (-1 - 1.5) / (-1.5), P_43 = -alpha * (-1.5) / 4 = 2.5 / 4
+    assert abs(P_[4, 2] - 2.5 / 4.0) < 1e-15
+    assert np.array_equal(P_[1:4], np.eye(3))
 
 
 def test_strength_definition_brute_force():
