@@ -213,6 +213,7 @@ def cpu_baseline(s, b, its_gpu, budget_s, args):
     t_it = (time.perf_counter() - t0) / n_it
     per_solve = t_setup + its_gpu * t_it
     return dict(value=round(1.0 / per_solve, 6), unit="solves/s", cores=1, kind="oracle",
+                nproc=os.cpu_count(),
                 sample="oracle on the same workload: flow-stage setup (%.1f s) + %d FGMRES "
                        "iteration(s) (%.2f s each), extrapolated to %d iterations; mechanics AMG "
                        "(%.1f s, once) excluded as on the GPU" % (t_setup, n_it, t_it, its_gpu, t_mech))
@@ -351,7 +352,8 @@ def main():
     ap.add_argument("--workload", default="grf64")
     ap.add_argument("--precision", default="both", choices=["fp32", "fp64", "both"])
     ap.add_argument("--rtol", type=float, default=1e-8)
-    ap.add_argument("--ml-sweeps", type=int, default=1)
+    ap.add_argument("--ml-sweeps", type=int, default=2,
+                    help="local-stage sweeps (2: measured fastest to rtol 1e-8 on grf64)")
     ap.add_argument("--smoother", default="l1jac", choices=["cheb2", "l1jac"])
     ap.add_argument("--ml-kind", default="bilu0", choices=["bilu0", "bjacobi", "mcgs"])
     ap.add_argument("--ml-part", default="32,16,16",
@@ -372,6 +374,7 @@ def main():
     args.ml_kind_code = {"bilu0": 0, "bjacobi": 1, "mcgs": 2}[args.ml_kind]
 
     from synth import workload
+    from synth.configs import LOG10K_MAX
     t0 = time.perf_counter()
     s, b = workload(args.workload)
     if args.ml_part and args.ml_part != "global":
@@ -400,9 +403,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 preconditioner, f64 Krylov" if "fp32" in g else "f64",
         "data": "synthetic",
-        "config": {"workload": "%s: %dx%dx%d-cell two-phase poromechanics Jacobian, N=%d, FGMRES(100) + "
-                               "two-stage preconditioner, rtol %g; step = flow-stage setup + solve"
-                               % (args.workload, *s.meta["grid"], s.N, args.rtol),
+        "config": {"workload": "%s: %dx%dx%d-cell %s-phase poromechanics Jacobian, N=%d, FGMRES(100) + "
+                               "two-stage preconditioner, rtol %g; step = flow-stage setup + solve; "
+                               "log10 permeability clipped above at %.1f (about 20 D); state: line-drive "
+                               "pressure solved through the permeability field"
+                               % (args.workload, *s.meta["grid"], "two" if s.nf == 2 else "three", s.N,
+                                  args.rtol, LOG10K_MAX),
                    "precision": "fp32-preconditioner" if "fp32" in g else "fp64",
                    "ml_sweeps": args.ml_sweeps, "smoother": args.smoother, "ml_kind": args.ml_kind,
                    "ml_part": args.ml_part if args.ml_part else "global"},

@@ -58,6 +58,15 @@ extern "C" {
 #define PS_BILU0      0    /* local stage M_L: block ILU(0) on S_ff^(fs) */
 #define PS_BJACOBI    1    /* local stage M_L: block Jacobi on S_ff^(fs) */
 #define PS_MCGS       2    /* local stage M_L: hybrid block Gauss-Seidel in multicolour order */
+#define PS_FGMRES      0   /* outer iteration: right-preconditioned flexible GMRES (Sec. 4) */
+#define PS_RICHARDSON  1   /* outer iteration: x += M^-1 (b - A x), the sequential fixed-stress
+                              scheme (remark after Algorithm 1) */
+#define PS_QUASI_IMPES 0   /* D_ss, D_ps: diagonal (cell) blocks of A_ss, A_ps (Sec. 5.3) */
+#define PS_TRUE_IMPES  1   /* D_ss, D_ps: column-sum lumping, eq. CPR_CSL (Sec. 5.3) */
+#define PS_FS_GIVEN    0   /* fixed-stress diagonals: the system's d_sp, d_pp (eq. FS_Dps_Dpp) */
+#define PS_FS_RSL      1   /* fixed-stress diagonals by row-sum lumping, eq. FS_RSL: -diag(A_fu
+                              A_uu^-1 A_up e), with A_uu^-1 approximated by fs_iters Richardson
+                              steps preconditioned by the mechanics V-cycle */
 
 /* Block CSR matrix (host arrays).  Row-major br x bc blocks; rowptr has nbrows+1
  * entries starting at 0; colind sorted and unique within each block row. */
@@ -80,7 +89,11 @@ typedef struct {
  * nf: 2 or 3.  p_index: which cell dof is the pressure (and which cell row the
  * pressure equation); this library requires p_index == nf - 1.
  * mech_key: non-zero -> handles created with the same key in one context have
- * identical A_uu and share one mechanics AMG hierarchy.
+ * identical A_uu and share one mechanics AMG hierarchy (Sec. 5.2: set up once).
+ * Handles whose hierarchy options differ (smoother, theta, coarse_max,
+ * max_levels) get a hierarchy of their own; a handle whose A_uu pattern (node
+ * count, block count, row pointers and columns) differs from the one the shared
+ * hierarchy was built for is refused by ps_create with PS_EINVAL.
  * ml_part: optional (NULL = none) subdomain id of each cell.  With it the BILU(0)
  * local stage is processor-local as in the paper's second example (Sec. 6): the
  * factorisation drops the couplings between cells of different subdomains, which
@@ -105,6 +118,10 @@ typedef struct {
     int32_t max_levels;   /* AMG: at most this many levels                (25)        */
     int32_t fp32_fallback;/* FP32 path: retry in FP64 on PS_EPRECISION    (0)         */
     double  theta;        /* AMG strength threshold                       (0.25)      */
+    int32_t method;       /* PS_FGMRES | PS_RICHARDSON                    (PS_FGMRES) */
+    int32_t reduction;    /* PS_QUASI_IMPES | PS_TRUE_IMPES               (quasi)     */
+    int32_t fixed_stress; /* PS_FS_GIVEN | PS_FS_RSL                      (given)     */
+    int32_t fs_iters;     /* PS_FS_RSL: V-cycle iterations for A_uu^-1    (10)        */
 } ps_options;
 
 typedef struct {
@@ -128,11 +145,14 @@ void ps_ctx_destroy(ps_ctx *ctx);
  * matrix is uploaded to the device.  opts may be NULL (defaults). */
 int  ps_create(ps_ctx *ctx, const ps_system *sys, const ps_options *opts, ps_handle **out);
 
-/* Replace the flow blocks (Afu, Aff values and d_sp, d_pp; same patterns) as
- * after a Newton step: the values are copied into the device layout in place (the
- * displacement blocks stay); the next ps_setup rebuilds the flow stage only. */
+/* Replace the state-dependent blocks (Afu, Aff values, d_sp, d_pp and optionally
+ * Auf; same patterns; NULL = unchanged) as after a Newton step (Sec. 4): the values are
+ * copied into the device layout in place, A_uu and the mechanics hierarchy stay (Sec.
+ * 5.2: built once); the next ps_setup rebuilds the flow stage only (Sec. 5.4).  Host
+ * arrays, copied; PS_EINVAL on a non-finite value, PS_EBUSY while a request is in
+ * flight. */
 int  ps_update_flow(ps_handle *h, const double *afu_vals, const double *aff_vals,
-                    const double *d_sp, const double *d_pp);
+                    const double *d_sp, const double *d_pp, const double *auf_vals);
 
 /* Setup phase (Sec. 5.4): fixed-stress and quasi-IMPES operators, pressure AMG,
  * BILU(0) factors, FP32 mirrors; the mechanics AMG is built on the first call
@@ -143,8 +163,11 @@ int  ps_update_flow(ps_handle *h, const double *afu_vals, const double *aff_vals
  * bit.  Synchronous. */
 int  ps_setup(ps_handle *h);
 
-/* Solve A x = rhs to |b - A x| <= rtol |b| with FGMRES(restart) and Algorithm 1.
- * rhs, x: device pointers (N doubles); x is overwritten (x0 = 0).  stream: a
+/* Solve A x = rhs to |b - A x| <= rtol |b| with FGMRES(restart) and Algorithm 1
+ * (Sec. 4, right preconditioning), or with options.method = PS_RICHARDSON by the
+ * preconditioned Richardson iteration x += M^-1 (b - A x) (the sequential fixed-stress
+ * scheme of the remark after Algorithm 1; `iterations` counts its steps, `restarts` is
+ * 0).  rhs, x: device pointers (N doubles); x is overwritten (x0 = 0).  stream: a
  * hipStream_t or NULL for the legacy default stream.  Blocking; res may be NULL. */
 int  ps_solve(ps_handle *h, const double *rhs, double *x, double rtol, void *stream,
               ps_result *res);
@@ -158,9 +181,11 @@ int  ps_apply_precond(ps_handle *h, const double *v, double *z, void *stream);
  * Stream-ordered like ps_apply_precond. */
 int  ps_spmv(ps_handle *h, const double *x, double *y, void *stream);
 
-/* Serving: enqueue a solve; rhs/x must stay valid until completion.  The
+/* Serving: enqueue a solve (FGMRES only: PS_EINVAL for PS_RICHARDSON); rhs/x must
+ * stay valid until completion.  The
  * context's scheduler admits requests by device-memory footprint and advances
- * all admitted requests one FGMRES iteration per tick (continuous batching).
+ * each admitted request by one FGMRES iteration (or cycle end) as soon as its
+ * previous one has completed, on the request's own stream (continuous batching).
  * Work already enqueued on `stream` (e.g. the copy that fills rhs) completes
  * before the request starts; NULL = legacy default stream. */
 int  ps_submit(ps_handle *h, const double *rhs, double *x, double rtol, void *stream, uint64_t *ticket);
@@ -193,6 +218,13 @@ int  ps_kernel_stats(int idx, char *name, size_t len, int64_t *launches, double 
 int  ps_pressure_level(ps_handle *h, int lvl, int32_t *nlevels, int32_t *n, int32_t *nnz, int32_t *rowptr,
                        int32_t *colind, double *vals, int8_t *cf);
 
+/* Release a handle.  A handle created with a non-zero mech_key and set up is kept by
+ * its context (at most 4 per key, within a quarter of the context's budget) and given to
+ * the next ps_create whose system has the same mech_key, options, sizes, block patterns
+ * and ml_part: that handle keeps the device layouts and workspaces, takes the new
+ * system's values, and its first ps_setup runs the device path (what serving requests on
+ * an already-served grid need).  Other handles are freed; ps_ctx_destroy frees the kept
+ * ones. */
 void ps_destroy(ps_handle *h);
 const char *ps_strerror(int status);
 /* Message of the last error raised on the calling thread ("" if none). */

@@ -109,13 +109,49 @@ def fgmres(matvec, precond, b, rtol=1e-8, restart=100, maxit=1000, record_iterat
         cycles += 1
 
 
+def richardson(matvec, precond, b, rtol=1e-8, maxit=1000, record_iterates=False):
+    """Preconditioned Richardson iteration x_{k+1} = x_k + M^{-1}(b - A x_k), x_0 = 0.
+
+    The paper's remark after Algorithm 1: the two-stage preconditioner inside a
+    fixed-point (Richardson) iteration is the sequential fixed-stress scheme -- step 1
+    corrects the displacement, steps 2-8 then update the flow unknowns.  Stops when the
+    FP64 residual |b - A x_k| <= rtol |b| (checked after every step) or after maxit steps.
+    history[k] = |b - A x_{k+1}| / |b|; iterates[k] = x_{k+1} when recorded.
+    """
+    b = np.asarray(b, np.float64)
+    x = np.zeros(b.shape[0])
+    beta_b = np.linalg.norm(b)
+    res = dict(x=x, iterations=0, restarts=0, status=OK, rel_residual=0.0, history=[],
+               iterates=[] if record_iterates else None)
+    if beta_b == 0.0:
+        return res
+    r = b.copy()
+    its = 0
+    while True:
+        x = x + precond(r)
+        r = b - matvec(x)
+        its += 1
+        rel = np.linalg.norm(r) / beta_b
+        res["history"].append(rel)
+        if record_iterates:
+            res["iterates"].append(x.copy())
+        if rel <= rtol or its >= maxit:
+            res.update(x=x, iterations=its, rel_residual=rel, status=OK if rel <= rtol else EMAXIT)
+            return res
+
+
 def solve(system, b, rtol=1e-8, opts=None, setup_result=None, record_iterates=False):
-    """FGMRES with the two-stage preconditioner on a synthetic system."""
+    """FGMRES (or, with opts.method == "richardson", the preconditioned Richardson
+    iteration) with the two-stage preconditioner on a synthetic system."""
     from .precond import setup as _setup, apply_precond, Options
     opts = opts or Options()
     st = setup_result or _setup(system, opts)
     A = st.mats["A"]
-    out = fgmres(lambda v: A @ v, lambda v: apply_precond(st, v), b, rtol=rtol,
-                 restart=opts.restart, maxit=opts.maxit, record_iterates=record_iterates)
+    if getattr(opts, "method", "fgmres") == "richardson":
+        out = richardson(lambda v: A @ v, lambda v: apply_precond(st, v), b, rtol=rtol,
+                         maxit=opts.maxit, record_iterates=record_iterates)
+    else:
+        out = fgmres(lambda v: A @ v, lambda v: apply_precond(st, v), b, rtol=rtol,
+                     restart=opts.restart, maxit=opts.maxit, record_iterates=record_iterates)
     out["setup"] = st
     return out

@@ -22,6 +22,9 @@ Readings:
     use Cramer's rule.  nf = 2: t_i = D_ps,i / D_ss,i; nf = 3: t_i = D_ps,i D_ss,i^{-1}.
     S_pp[i, j] = A_pp^(fs)[i, j] - t_i . A_sp^(fs)[i, j] on the TPFA pattern.
   * Step 6 uses S_ff^(fs) (the matrix M_ff approximates), not A_ff.
+  * Alternatives of Sec. 5.1 / 5.3: true-IMPES (column-sum lumping, eq. CPR_CSL; cell
+    blocks summed over the block column for nf = 3) and the row-sum-lumped fixed-stress
+    diagonals (eq. FS_RSL, A_uu^{-1} approximated by Richardson steps with M_uu).
   * The local stage acts on all flow (cell) unknowns; displacement is untouched.
 Test infrastructure only.
 """
@@ -43,6 +46,10 @@ class Options:
     smoother: str = "cheb2"        # "cheb2" | "l1jac"
     ml_kind: str = "bilu0"         # "bilu0" | "bjacobi" | "mcgs"
     ml_sweeps: int = 1             # sweeps of the local stage (BILU(0) or block Jacobi)
+    method: str = "fgmres"         # "fgmres" | "richardson" (sequential fixed-stress scheme)
+    reduction: str = "quasi"       # "quasi" | "true" (IMPES reduction, Sec. 5.3)
+    fixed_stress: str = "given"    # "given" (the system's d_sp, d_pp) | "rsl" (eq. FS_RSL)
+    fs_iters: int = 10             # RSL: Richardson steps with the mechanics V-cycle for A_uu^-1
 
 
 def bsr_to_csr(rowptr, colind, vals, ncols_blocks):
@@ -81,15 +88,48 @@ def _diag_positions(rowptr, colind):
     return pos
 
 
-def fixed_stress(system):
-    """Block values of S_ff^(fs) (eq. Schur_1_FS with the diagonals of eq. FS_Dps_Dpp)."""
+def fixed_stress(system, d_sp=None, d_pp=None):
+    """Block values of S_ff^(fs) (eq. Schur_1_FS with the diagonals of eq. FS_Dps_Dpp,
+    or the given ones)."""
     nf = system.nf
+    d_sp = system.d_sp if d_sp is None else d_sp
+    d_pp = system.d_pp if d_pp is None else d_pp
     vals = np.array(system.Aff.vals, np.float64, copy=True)
     dpos = _diag_positions(system.Aff.rowptr, system.Aff.colind)
     for l in range(nf - 1):
-        vals[dpos, l, nf - 1] += system.d_sp[:, l]
-    vals[dpos, nf - 1, nf - 1] += system.d_pp
+        vals[dpos, l, nf - 1] += d_sp[:, l]
+    vals[dpos, nf - 1, nf - 1] += d_pp
     return vals
+
+
+def rsl_diagonals(system, mats, sdc, smoother, iters):
+    """Fixed-stress diagonals by row-sum lumping (remark after eq. FS_Dps_Dpp, eq. FS_RSL):
+    D_sp = -diag(A_su A_uu^{-1} A_up e), D_pp = -diag(A_pu A_uu^{-1} A_up e), e = 1 on the
+    pressure unknowns.  The paper allows a good preconditioner of A_uu in place of the
+    inverse; reading: y = A_uu^{-1} g is approximated by `iters` Richardson steps
+    y += M_uu^{-1}(g - A_uu y) from y = 0, M_uu the mechanics V-cycle of step 1.
+    Returns (d_sp (n_cells, nf-1), d_pp (n_cells,))."""
+    nf, nc = system.nf, system.n_cells
+    e = np.zeros(nf * nc)
+    e[nf - 1::nf] = 1.0
+    g = mats["Auf"] @ e                      # A_up e (the saturation columns get 0)
+    Auu = mats["Auu"]
+    y = np.zeros(g.shape[0])
+    for _ in range(iters):
+        y = y + _sdc_apply(sdc, g - Auu @ y, smoother)
+    w = (mats["Afu"] @ y).reshape(nc, nf)     # rows s and p of A_fu y
+    return -w[:, : nf - 1].copy(), -w[:, nf - 1].copy()
+
+
+def column_sum_blocks(system):
+    """Per cell i the sum over block rows k of A_ff[k, i] (nf x nf), rows k in increasing
+    order: the column-sum lumping of eq. CPR_CSL (true-IMPES), whose s-column part gives
+    D_ss = diag(A_ss^T e) and D_ps = diag(A_ps^T e); for nf = 3 the cell blocks of the
+    multi-component remark (Sec. 5.3)."""
+    nf = system.nf
+    out = np.zeros((system.n_cells, nf, nf))
+    np.add.at(out, system.Aff.colind, system.Aff.vals)
+    return out
 
 
 def inv2(a, b, c, d):
@@ -98,14 +138,19 @@ def inv2(a, b, c, d):
     return d / det, -b / det, -c / det, a / det
 
 
-def quasi_impes(system, sff_vals):
-    """Quasi-IMPES pressure matrix S_pp (scalar CSR on the cell pattern) and D_ss^{-1}."""
+def quasi_impes(system, sff_vals, reduction="quasi"):
+    """IMPES-reduced pressure matrix S_pp (scalar CSR on the cell pattern) and D_ss^{-1}:
+    quasi-IMPES (D_ss, D_ps from the diagonal cell blocks, diagm) or true-IMPES (from the
+    column sums, eq. CPR_CSL)."""
     nf = system.nf
     rowptr, colind = system.Aff.rowptr, system.Aff.colind
     aff = system.Aff.vals
-    dpos = _diag_positions(rowptr, colind)
-    Dss = aff[dpos, : nf - 1, : nf - 1]
-    Dps = aff[dpos, nf - 1, : nf - 1]
+    if reduction == "true":
+        D = column_sum_blocks(system)
+    else:
+        D = aff[_diag_positions(rowptr, colind)]
+    Dss = D[:, : nf - 1, : nf - 1]
+    Dps = D[:, nf - 1, : nf - 1]
     if nf == 2:
         t = (Dps[:, 0] / Dss[:, 0, 0])[:, None]
         dss_inv = (1.0 / Dss[:, 0, 0])[:, None, None]
@@ -165,16 +210,20 @@ def setup(system, opts=None, mechanics=None):
     if system.p_index != system.nf - 1:
         raise ValueError("pressure must be the last cell dof")
     mats = system_matrices(system)
-    sff_vals = fixed_stress(system)
+    kw = dict(theta=opts.theta, coarse_max=opts.coarse_max, max_levels=opts.max_levels,
+              smoother=opts.smoother)
+    sdc = mechanics if mechanics is not None else amg.build(sdc_matrix(system), **kw)
+    if opts.fixed_stress == "rsl":
+        d_sp, d_pp = rsl_diagonals(system, mats, sdc, opts.smoother, opts.fs_iters)
+    else:
+        d_sp, d_pp = system.d_sp, system.d_pp
+    sff_vals = fixed_stress(system, d_sp, d_pp)
     Sff = bsr_to_csr(system.Aff.rowptr, system.Aff.colind, sff_vals, system.n_cells)
-    Spp, dss_inv = quasi_impes(system, sff_vals)
+    Spp, dss_inv = quasi_impes(system, sff_vals, opts.reduction)
     nf = system.nf
     # A_ps: pressure rows, saturation columns of A_ff (unchanged by fixed stress)
     Aps = bsr_to_csr(system.Aff.rowptr, system.Aff.colind,
                      np.ascontiguousarray(system.Aff.vals[:, nf - 1: nf, : nf - 1]), system.n_cells)
-    kw = dict(theta=opts.theta, coarse_max=opts.coarse_max, max_levels=opts.max_levels,
-              smoother=opts.smoother)
-    sdc = mechanics if mechanics is not None else amg.build(sdc_matrix(system), **kw)
     pres = amg.build(Spp, **kw)
     part = getattr(system, "ml_part", None)
     if opts.ml_kind == "bilu0" and part is not None:

@@ -9,7 +9,9 @@
 #include <map>
 #include <exception>
 #include <mutex>
+#include <string>
 #include <thread>
+#include <tuple>
 
 #include "../../include/ps.h"
 #include "../../include/ps_host.h"
@@ -68,6 +70,9 @@ struct PhaseTimer {
 // handles with the same mech_key (Sec. 5.2: the elasticity AMG is set up once).
 struct Mech {
     std::mutex mu;
+    // what the hierarchy was built for: a handle that shares the key must match it
+    int n_nodes = 0, nblocks = 0;
+    uint64_t pattern_hash = 0;
     Hierarchy host;
     bool built = false;
     std::unique_ptr<DHierarchy<double>> d64;
@@ -83,7 +88,15 @@ struct ps_ctx {
     int device = 0;
     size_t budget = 0;
     std::mutex mu;
-    std::map<uint64_t, std::weak_ptr<Mech>> mech_cache;
+    // key: (mech_key, smoother, theta, coarse_max, max_levels) -- the options that shape
+    // the hierarchy, so that handles with other options build their own
+    std::map<std::tuple<uint64_t, int, double, int, int>, std::weak_ptr<Mech>> mech_cache;
+    // Set-up handles released by ps_destroy, kept for a later ps_create of a system with the
+    // same mech_key, options and block patterns: it takes the handle's device layouts and
+    // workspaces, uploads only its own values, and its first ps_setup runs the device path.
+    // key -> handles (most recent last); at most kMaxParked per key, parked_bytes <= budget / 4.
+    std::map<std::string, std::vector<ps_handle *>> parked;
+    size_t parked_bytes = 0;
     // serving
     std::condition_variable cv, done_cv;
     std::deque<Request *> queue;
@@ -110,12 +123,15 @@ struct ps_handle {
     bool afu_changed = true;          // A_fu values changed since the last upload
     PrecWork<double> w64;
     PrecWork<float> w32;
+    RslWork rsl;                      // fixed_stress = PS_FS_RSL: vectors of the lumping
     std::unique_ptr<Krylov> K;
     double *ztmp = nullptr;           // FP32 z -> FP64 staging for ps_apply_precond
     Arena aux;
     bool ready = false;
     std::atomic<bool> busy{false};
     double setup_s = 0.0;
+    std::string park_key;             // non-empty: reusable by a later ps_create (mech_key set)
+    size_t parked_bytes = 0;
     size_t krylov_bytes(bool z32) const {
         size_t N = sys.N(), m = opt.restart;
         return (m + 1) * N * 8 + m * N * (z32 ? 4 : 8) + N * 8 + (m + 2) * 1024 * 8;
@@ -124,7 +140,7 @@ struct ps_handle {
         return dsys.arena.bytes() + (mech ? mech->bytes() : 0) + (fl64 ? fl64->bytes() : 0) +
                (fl32 ? fl32->bytes() : 0) + w64.arena.bytes() + w32.arena.bytes() +
                (K ? K->arena.bytes() : 0) + aux.bytes() + pstore.arena.bytes() + pstore.work.bytes() +
-               pstore.tmp.bytes();
+               pstore.tmp.bytes() + rsl.arena.bytes();
     }
 };
 
@@ -179,14 +195,64 @@ bool host_operators_forced() {
     return e && std::string(e) == "host";
 }
 
+// FNV-1a over A_uu's row pointers and column indices: handles sharing a mechanics
+// hierarchy must agree on the pattern it was built for.
+uint64_t pattern_hash(const Bsr &U) {
+    uint64_t x = 1469598103934665603ull;
+    auto mix = [&x](const std::vector<int> &a) {
+        for (int v : a) {
+            x ^= (uint32_t)v;
+            x *= 1099511628211ull;
+        }
+    };
+    mix(U.rp);
+    mix(U.ci);
+    return x;
+}
+
+constexpr size_t kMaxParked = 4;
+
+// What a parked handle must share with a new system to be reused: the mechanics key, every
+// option, the sizes, and the four block patterns and the subdomain partition.
+std::string park_key(const System &s, const Options &o) {
+    uint64_t part = 1469598103934665603ull;
+    for (int v : s.ml_part) {
+        part ^= (uint32_t)v;
+        part *= 1099511628211ull;
+    }
+    char buf[512];
+    std::snprintf(buf, sizeof buf,
+                  "%llu|%d,%d,%d,%d,%d,%d,%d,%d,%d,%.17g,%d,%d,%d,%d|%d,%d,%d|%llx,%llx,%llx,%llx,%llx",
+                  (unsigned long long)s.mech_key, o.precision, o.restart, o.maxit, o.smoother, o.ml_kind,
+                  o.ml_sweeps, o.coarse_max, o.max_levels, o.fp32_fallback, o.theta, o.method, o.reduction,
+                  o.fixed_stress, o.fs_iters, s.n_nodes, s.n_cells, s.nf, (unsigned long long)pattern_hash(s.Auu),
+                  (unsigned long long)pattern_hash(s.Auf), (unsigned long long)pattern_hash(s.Afu),
+                  (unsigned long long)pattern_hash(s.Aff), (unsigned long long)part);
+    return buf;
+}
+
+std::shared_ptr<Mech> new_mech(int n_nodes, int nblocks, uint64_t phash) {
+    auto m = std::make_shared<Mech>();
+    m->n_nodes = n_nodes;
+    m->nblocks = nblocks;
+    m->pattern_hash = phash;
+    return m;
+}
+
 void ensure_mech_device(ps_handle *h, bool need64, bool need32) {
     std::lock_guard<std::mutex> lk(h->mech->mu);
     if (!h->mech->built) {
         h->mech->host = amg_build(sdc_matrix(h->sys), h->opt);
         h->mech->built = true;
     }
-    if (need64 && !h->mech->d64) h->mech->d64 = upload_hierarchy<double>(h->mech->host, h->opt.smoother, true);
-    if (need32 && !h->mech->d32) h->mech->d32 = upload_hierarchy<float>(h->mech->host, h->opt.smoother, true);
+    if (need64 && !h->mech->d64) {
+        h->mech->d64 = upload_hierarchy<double>(h->mech->host, h->opt.smoother, true);
+        h->mech->d64->ktag = ktime::SDC_PRE;
+    }
+    if (need32 && !h->mech->d32) {
+        h->mech->d32 = upload_hierarchy<float>(h->mech->host, h->opt.smoother, true);
+        h->mech->d32->ktag = ktime::SDC_PRE;
+    }
 }
 
 }  // namespace
@@ -225,6 +291,10 @@ void ps_default_options(ps_options *o) {
     o->max_levels = 25;
     o->fp32_fallback = 0;
     o->theta = 0.25;
+    o->method = PS_FGMRES;
+    o->reduction = PS_QUASI_IMPES;
+    o->fixed_stress = PS_FS_GIVEN;
+    o->fs_iters = 10;
 }
 
 int ps_ctx_create(int device, size_t budget, ps_ctx **out) {
@@ -258,6 +328,10 @@ void ps_ctx_destroy(ps_ctx *c) {
     }
     c->cv.notify_all();
     if (c->worker.joinable()) c->worker.join();
+    (void)hipSetDevice(c->device);
+    for (auto &kv : c->parked)
+        for (ps_handle *h : kv.second) delete h;
+    c->parked.clear();
     delete c;
 }
 
@@ -265,31 +339,71 @@ int ps_create(ps_ctx *ctx, const ps_system *sys, const ps_options *opts, ps_hand
     return guard([&] {
         if (!ctx || !out) throw Error(PS_EINVAL, "ctx/out is NULL");
         *out = nullptr;
-        auto h = std::make_unique<ps_handle>();
-        h->ctx = ctx;
         ps_options def;
         ps_default_options(&def);
-        h->opt = options_from(opts ? opts : &def);
-        validate_and_copy(sys, h->sys);
+        Options opt = options_from(opts ? opts : &def);
+        System vs;
+        validate_and_copy(sys, vs);
+        std::string key;
+        if (vs.mech_key != 0) {
+            key = park_key(vs, opt);
+            ps_handle *reuse = nullptr;
+            {
+                std::lock_guard<std::mutex> lk(ctx->mu);
+                auto it = ctx->parked.find(key);
+                if (it != ctx->parked.end() && !it->second.empty()) {
+                    reuse = it->second.back();
+                    it->second.pop_back();
+                    ctx->parked_bytes -= reuse->parked_bytes;
+                    reuse->parked_bytes = 0;
+                }
+            }
+            if (reuse) {
+                // same patterns and options: keep the layouts, take this system's values (A_uu
+                // is the shared one by the mech_key contract)
+                std::unique_ptr<ps_handle> h(reuse);
+                h->sys = std::move(vs);
+                set_device(ctx->device);
+                update_system_flow_values(h->sys, h->dsys, h->staging, true);
+                h->afu_changed = true;
+                h->ready = false;
+                h->setup_s = 0.0;
+                *out = h.release();
+                return PS_OK;
+            }
+        }
+        auto h = std::make_unique<ps_handle>();
+        h->ctx = ctx;
+        h->opt = opt;
+        h->sys = std::move(vs);
+        h->park_key = key;
         set_device(ctx->device);
         upload_system(h->sys, h->dsys);
+        const Bsr &U = h->sys.Auu;
+        const uint64_t phash = pattern_hash(U);
         if (h->sys.mech_key != 0) {
             std::lock_guard<std::mutex> lk(ctx->mu);
-            auto it = ctx->mech_cache.find(h->sys.mech_key);
+            auto key = std::make_tuple(h->sys.mech_key, (int)h->opt.smoother, h->opt.theta,
+                                       (int)h->opt.coarse_max, (int)h->opt.max_levels);
+            auto it = ctx->mech_cache.find(key);
             if (it != ctx->mech_cache.end()) h->mech = it->second.lock();
+            if (h->mech && (h->mech->n_nodes != h->sys.n_nodes || h->mech->nblocks != U.nb() ||
+                            h->mech->pattern_hash != phash))
+                throw Error(PS_EINVAL, "mech_key names a mechanics hierarchy built for another A_uu pattern");
             if (!h->mech) {
-                h->mech = std::make_shared<Mech>();
-                ctx->mech_cache[h->sys.mech_key] = h->mech;
+                h->mech = new_mech(h->sys.n_nodes, U.nb(), phash);
+                ctx->mech_cache[key] = h->mech;
             }
         } else {
-            h->mech = std::make_shared<Mech>();
+            h->mech = new_mech(h->sys.n_nodes, U.nb(), phash);
         }
         *out = h.release();
         return PS_OK;
     });
 }
 
-int ps_update_flow(ps_handle *h, const double *afu, const double *aff, const double *d_sp, const double *d_pp) {
+int ps_update_flow(ps_handle *h, const double *afu, const double *aff, const double *d_sp, const double *d_pp,
+                   const double *auf) {
     return guard([&] {
         if (!h) throw Error(PS_EINVAL, "handle is NULL");
         if (h->busy) throw Error(PS_EBUSY, "handle has a request in flight");
@@ -300,6 +414,7 @@ int ps_update_flow(ps_handle *h, const double *afu, const double *aff, const dou
                 if (!std::isfinite(src[i])) throw Error(PS_EINVAL, "non-finite value");
             std::memcpy(dst.data(), src, dst.size() * sizeof(double));
         };
+        take(s.Auf.v, auf);
         take(s.Afu.v, afu);
         if (afu) h->afu_changed = true;
         take(s.Aff.v, aff);
@@ -307,7 +422,7 @@ int ps_update_flow(ps_handle *h, const double *afu, const double *aff, const dou
         take(s.d_pp, d_pp);
         set_device(h->ctx->device);
         // only the flow blocks' values cross PCIe, into the resident layout
-        update_system_flow_values(s, h->dsys, h->staging);
+        update_system_flow_values(s, h->dsys, h->staging, auf != nullptr);
         h->ready = false;
         return PS_OK;
     });
@@ -322,9 +437,14 @@ int ps_setup(ps_handle *h) {
         h->ready = false;
         bool f32 = use_fp32(h);
         bool f64 = !f32 || h->opt.fp32_fallback;
+        const bool rsl = h->opt.fixed_stress == PS_FS_RSL;
         {
             PhaseTimer pt("mechanics (if not built)");
-            ensure_mech_device(h, f64, f32);
+            ensure_mech_device(h, f64 || rsl, f32);      // RSL runs the FP64 mechanics V-cycle
+        }
+        if (rsl) {
+            PhaseTimer pt("RSL fixed-stress diagonals");
+            rsl_diagonals(h->dsys, *h->mech->d64, h->rsl, h->opt.fs_iters, h->sys.d_sp, h->sys.d_pp, nullptr);
         }
         const bool dev_rap = galerkin_on_device();
         // after the first setup has laid out the subdomain BILU(0), its factorization runs on
@@ -334,8 +454,10 @@ int ps_setup(ps_handle *h) {
         // and S_pp, D_ss (quasi-IMPES) and the pressure hierarchy come from the system on the
         // device, with no host work in front of the pressure hierarchy (PS_OPERATORS=host:
         // fixed stress and quasi-IMPES on the host at every setup)
+        // (quasi-IMPES only: the true-IMPES column sums are formed on the host)
         const bool dev_ops = dev_factor && dev_rap && h->opt.smoother == PS_L1JAC &&
-                             h->pstore.npat == h->sys.n_cells && !host_operators_forced();
+                             h->opt.reduction == PS_QUASI_IMPES && h->pstore.npat == h->sys.n_cells &&
+                             !host_operators_forced();
         // layouts (first call) and values of the flow stage that do not depend on the
         // pressure hierarchy, for the precisions in use
         auto flow_values = [&] {
@@ -353,7 +475,7 @@ int ps_setup(ps_handle *h) {
         };
         {
             PhaseTimer pt("flow setup");
-            if (!dev_ops) build_flow_operators(h->sys, h->flow);
+            if (!dev_ops) build_flow_operators(h->sys, h->opt, h->flow);
             if (dev_rap) {
                 // local-stage factors and the flow-stage value uploads on a host thread
                 // while the pressure hierarchy is built (its own copies run on the null
@@ -412,12 +534,17 @@ int ps_setup(ps_handle *h) {
     });
 }
 
+// Krylov workspace columns an outer iteration needs: the restart length for FGMRES, one
+// correction vector for Richardson.
+static int workspace_m(const ps_handle *h) { return h->opt.method == PS_RICHARDSON ? 1 : h->opt.restart; }
+
 static SolveOut run_solve(ps_handle *h, Krylov &K, bool fp32, const double *rhs, double *x, double rtol,
                           hipStream_t st) {
-    std::unique_ptr<PrecFn> M;
-    if (fp32) M = std::make_unique<Prec32>(h);
-    else M = std::make_unique<Prec64>(h);
-    Fgmres run(h->dsys, K, *M, rhs, x, rtol, h->opt.maxit, st);
+    Prec32 m32(h);
+    Prec64 m64(h);
+    PrecFn &M = fp32 ? static_cast<PrecFn &>(m32) : static_cast<PrecFn &>(m64);
+    if (h->opt.method == PS_RICHARDSON) return richardson_blocking(h->dsys, K, M, rhs, x, rtol, h->opt.maxit, st);
+    Fgmres run(h->dsys, K, M, rhs, x, rtol, h->opt.maxit, st);
     return fgmres_blocking(run, st);
 }
 
@@ -441,14 +568,15 @@ int ps_solve(ps_handle *h, const double *rhs, double *x, double rtol, void *stre
         hipStream_t st = (hipStream_t)stream;
         double t0 = now_s();
         bool f32 = use_fp32(h);
-        if (!h->K || h->K->z_fp32 != f32) {
+        const int m = workspace_m(h);
+        if (!h->K || h->K->z_fp32 != f32 || h->K->m != m) {
             h->K = std::make_unique<Krylov>();
-            alloc_krylov(*h->K, h->sys.N(), h->opt.restart, f32);
+            alloc_krylov(*h->K, h->sys.N(), m, f32);
         }
         SolveOut o = run_solve(h, *h->K, f32, rhs, x, rtol, st);
         if (o.status == PS_EPRECISION && f32 && h->opt.fp32_fallback) {
             Krylov K64;
-            alloc_krylov(K64, h->sys.N(), h->opt.restart, false);
+            alloc_krylov(K64, h->sys.N(), m, false);
             o = run_solve(h, K64, false, rhs, x, rtol, st);
         }
         if (res) {
@@ -508,8 +636,20 @@ int ps_footprint(ps_handle *h, size_t *bytes) {
 
 void ps_destroy(ps_handle *h) {
     if (!h) return;
-    (void)hipSetDevice(h->ctx->device);
+    ps_ctx *c = h->ctx;
+    (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
+    if (!h->park_key.empty() && h->ready && !h->busy) {
+        const size_t b = h->bytes();
+        std::lock_guard<std::mutex> lk(c->mu);
+        auto &v = c->parked[h->park_key];
+        if (!c->stop && v.size() < kMaxParked && c->parked_bytes + b <= c->budget / 4) {
+            h->parked_bytes = b;
+            c->parked_bytes += b;
+            v.push_back(h);
+            return;
+        }
+    }
     delete h;
 }
 
@@ -518,6 +658,7 @@ int ps_submit(ps_handle *h, const double *rhs, double *x, double rtol, void *str
     return guard([&] {
         check_solve_args(h, rhs, x, rtol);
         if (!ticket) throw Error(PS_EINVAL, "ticket is NULL");
+        if (h->opt.method != PS_FGMRES) throw Error(PS_EINVAL, "ps_submit runs FGMRES only (method PS_FGMRES)");
         bool expected = false;
         if (!h->busy.compare_exchange_strong(expected, true)) throw Error(PS_EBUSY, "handle has a request in flight");
         ps_ctx *c = h->ctx;
@@ -629,10 +770,10 @@ int ps_wait(ps_ctx *c, uint64_t ticket, ps_result *res) {
 
 }  // extern "C"
 
-// Iteration-level continuous batching: each tick advances every admitted request by
-// one piece of FGMRES work (one iteration or one cycle end) on its own stream, so the
-// device overlaps requests; queued requests are admitted whenever their device
-// footprint fits the budget, and finished ones leave at the tick boundary.
+// Iteration-level continuous batching: every admitted request advances by one piece of
+// FGMRES work (one iteration or one cycle end) on its own stream as soon as its previous
+// piece has completed, so the device overlaps requests; queued requests are admitted
+// whenever their device footprint fits the budget, and finished ones leave at once.
 void ps_ctx::scheduler() {
     (void)hipSetDevice(device);
     auto finish = [this](Request *r, int status, const SolveOut *o) {
@@ -703,11 +844,22 @@ void ps_ctx::scheduler() {
             if (code != PS_OK) finish(r, code, nullptr);
             else active.push_back(r);
         }
+        // Completion-driven: a request whose stream has drained (its scalars are on the
+        // host) advances by one piece of work; the others keep running, so a small request
+        // is not held to the pace of a large one.  When nothing was ready the loop waits a
+        // few microseconds (or for a new submission) instead of spinning.
         std::vector<Request *> still;
+        bool progressed = false;
         for (Request *r : active) {
+            const hipError_t q = hipStreamQuery(r->st);
+            if (q == hipErrorNotReady) {
+                still.push_back(r);
+                continue;
+            }
+            progressed = true;
             bool more = false;
             int code = guard([&] {
-                PS_HIP(hipStreamSynchronize(r->st));
+                if (q != hipSuccess) PS_HIP(q);
                 more = r->run->advance();
                 return PS_OK;
             });
@@ -722,6 +874,10 @@ void ps_ctx::scheduler() {
             }
         }
         active.swap(still);
+        if (!progressed && !admitted.size()) {
+            std::unique_lock<std::mutex> lk(mu);
+            cv.wait_for(lk, std::chrono::microseconds(20), [&] { return stop || !queue.empty(); });
+        }
     }
 }
 

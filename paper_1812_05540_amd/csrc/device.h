@@ -175,6 +175,7 @@ void download_level(const PresStore &S, int lvl, Csr &A, std::vector<int8_t> &cf
 template <typename T>
 struct DCsr {
     int n = 0, G = 1;
+    long long nnz = 0;            // stored entries (padding excluded)
     const int *rp = nullptr, *ci = nullptr;
     const T *v = nullptr;
     const int *cptr = nullptr;    // SELL-64 only: first slot of each 64-row slice
@@ -195,6 +196,7 @@ struct DHierarchy {
     const double *cinv = nullptr; // dense inverse of the coarsest operator (FP64)
     int cn = 0;
     int smoother = PS_CHEB2;
+    int ktag = -1;                // ktime id of level 0's first phase (SDC_PRE / PRES_PRE), -1: none
     Arena arena;
     size_t bytes() const { return arena.bytes(); }
 };
@@ -289,7 +291,7 @@ struct DSystem {                  // FP64 system matrix for A z and the true res
     int n_nodes = 0, n_cells = 0, nf = 0;
     Sell<double> Auu, Auf, Afu, Aff;
     double mat_bytes = 0.0;       // algorithmic bytes of the four blocks (values, columns, row pointers)
-    std::vector<int> src_afu, src_aff;   // SELL slot -> block of A_fu, A_ff (host), for new values
+    std::vector<int> src_auf, src_afu, src_aff;   // SELL slot -> block of A_uf, A_fu, A_ff (host), for new values
     Arena arena;
 };
 
@@ -297,7 +299,15 @@ struct DSystem {                  // FP64 system matrix for A z and the true res
 // instrumented launch records an event before and after it on the stream it runs on and
 // adds its algorithmic bytes.  Off by default; a launch then costs one atomic load.
 namespace ktime {
-enum Id { SPMV, CGS2_PROJECT, CGS2_FUSED, CGS2_SUBTRACT, BILU_SUB, NUM };
+enum Id {
+    SPMV, CGS2_PROJECT, CGS2_FUSED, CGS2_SUBTRACT, BILU_SUB,
+    // level 0 of the two V-cycles: pre-smoothing sweep (with the residual), restriction,
+    // prolongation (x += P e), post-smoothing sweep
+    SDC_PRE, SDC_RESTRICT, SDC_PROLONG, SDC_POST,
+    PRES_PRE, PRES_RESTRICT, PRES_PROLONG, PRES_POST,
+    NUM
+};
+// first id of the four level-0 V-cycle phases of a hierarchy: SDC_PRE or PRES_PRE
 const char *name(int id);
 bool enabled();
 void set_enabled(bool on);          // clears the totals
@@ -326,6 +336,7 @@ struct Krylov {                   // FGMRES workspace (FP64 basis, Z in the prec
     double *partial = nullptr;    // (m+2) x nblk reduction partials
     double *r = nullptr;          // true residual
     double *hostscal = nullptr;   // pinned host mirror of scal
+    bool own_hostscal = true;     // false: hostscal belongs to the caller
     Arena arena;
     ~Krylov();
 };
@@ -349,11 +360,13 @@ void update_flow_values(DFlow<T> &d, const FlowSetup &f, const System &s, const 
 template <typename T>
 void update_flow_pressure(DFlow<T> &d, const FlowSetup &f, const Options &o, const PresStore *ps);
 void upload_system(const System &s, DSystem &d);
-// new values of A_fu and A_ff (same patterns) into d's layout, through stg
-void update_system_flow_values(const System &s, DSystem &d, Staging &stg);
+// new values of A_fu and A_ff (and A_uf when `auf`; same patterns) into d's layout, through stg
+void update_system_flow_values(const System &s, DSystem &d, Staging &stg, bool auf = false);
 template <typename T>
 void alloc_prec_work(PrecWork<T> &w, const DHierarchy<T> &sdc, const DFlow<T> &fl, int n_nodes);
 void alloc_krylov(Krylov &k, size_t N, int m, bool z_fp32);
+// bytes of device memory a Krylov workspace takes (arrays 256-byte aligned)
+size_t krylov_bytes(size_t N, int m, bool z_fp32);
 
 // y = A x (FP64), or y = b - A x when b != nullptr; x of type TX.
 template <typename TX>
@@ -409,6 +422,22 @@ class Fgmres {
     bool breakdown_ = false;
 };
 SolveOut fgmres_blocking(Fgmres &run, hipStream_t st);
+// Fixed-stress diagonals by row-sum lumping (eq. FS_RSL): d_sp = -(A_su y), d_pp = -(A_pu y)
+// with y ~ A_uu^{-1} A_up e from `iters` Richardson steps y += M_uu^{-1}(A_up e - A_uu y)
+// preconditioned by the FP64 mechanics V-cycle; all products with the device system.
+// Results (host, n_cells x (nf-1) and n_cells) are written into d_sp, d_pp.
+struct RslWork {
+    Arena arena;
+    double *e = nullptr, *y = nullptr, *g = nullptr, *t = nullptr, *z = nullptr;
+    HierWork<double> hw;
+    bool ready = false;
+};
+void rsl_diagonals(const DSystem &S, const DHierarchy<double> &sdc, RslWork &w, int iters,
+                   std::vector<double> &d_sp, std::vector<double> &d_pp, hipStream_t st);
+
+// Preconditioned Richardson iteration (blocking); K needs restart >= 1.
+SolveOut richardson_blocking(const DSystem &S, Krylov &K, PrecFn &M, const double *b, double *x, double rtol,
+                             int maxit, hipStream_t st);
 
 void fill_zero(double *p, size_t n, hipStream_t st);
 void widen_f32(const float *in, double *out, size_t n, hipStream_t st);

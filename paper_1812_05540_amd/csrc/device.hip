@@ -8,6 +8,7 @@
 #include <cstring>
 #include <mutex>
 #include <numeric>
+#include <optional>
 #include <string>
 
 #include "kernels.h"
@@ -74,7 +75,9 @@ void drain_locked() {
 
 const char *name(int id) {
     static const char *n[NUM] = {"system_spmv", "cgs2_project", "cgs2_subtract_project", "cgs2_subtract_norm",
-                                 "bilu_subdomain"};
+                                 "bilu_subdomain", "sdc_l0_presmooth", "sdc_l0_restrict", "sdc_l0_prolong",
+                                 "sdc_l0_postsmooth", "pres_l0_presmooth", "pres_l0_restrict",
+                                 "pres_l0_prolong", "pres_l0_postsmooth"};
     return id >= 0 && id < NUM ? n[id] : "";
 }
 
@@ -91,7 +94,7 @@ void set_enabled(bool on) {
 }
 
 Scope::Scope(int i, hipStream_t s, double b) : id(i), st(s), bytes(b) {
-    if (!enabled()) return;
+    if (!enabled() || id < 0) return;
     e0 = get_event();
     PS_HIP(hipEventRecord(e0, st));
 }
@@ -248,6 +251,7 @@ template <typename T>
 static DCsr<T> upload_csr(Arena &ar, const Csr &A, bool sell) {
     DCsr<T> d;
     d.n = A.n;
+    d.nnz = A.nnz();
     d.G = lanes_per_row(A.n, A.nnz());
     d.rp = ar.upload(A.rp.data(), A.rp.size());
     std::vector<int> w((A.n + 63) / 64, 0);
@@ -788,6 +792,7 @@ template <typename T>
 static DCsr<T> adopt_csr(Arena &ar, const DevCsr &c, const int *w) {
     DCsr<T> d;
     d.n = c.n;
+    d.nnz = c.nnz;
     d.G = lanes_per_row(c.n, c.nnz);
     d.rp = c.rp;
     if (w && c.n && take_sell(sell_padding(w, c.n, c.nnz), c.n, c.nnz)) {
@@ -935,6 +940,7 @@ void update_flow_values(DFlow<T> &d, const FlowSetup &f, const System &s, const 
         d.dss_inv = d.arena.template alloc<T>(f.dss_inv.size());
         d.dinv = d.arena.template alloc<T>((size_t)nc * nn);
         d.pres = std::make_unique<DHierarchy<T>>();
+        d.pres->ktag = ktime::PRES_PRE;
         d.layout = true;
         afu_changed = true;
     }
@@ -1017,7 +1023,11 @@ void upload_system(const System &s, DSystem &d) {
     d.n_cells = s.n_cells;
     d.nf = s.nf;
     d.Auu = upload_sell<double>(d.arena, sell_from_bsr(s.Auu.rp, s.Auu.ci, s.Auu.v, s.n_nodes, 3, 3));
-    d.Auf = upload_sell<double>(d.arena, sell_from_bsr(s.Auf.rp, s.Auf.ci, s.Auf.v, s.n_nodes, 3, s.nf));
+    {
+        HostSell h = sell_from_bsr(s.Auf.rp, s.Auf.ci, s.Auf.v, s.n_nodes, 3, s.nf);
+        d.Auf = upload_sell<double>(d.arena, h);
+        d.src_auf = std::move(h.src);
+    }
     {
         HostSell h = sell_from_bsr(s.Afu.rp, s.Afu.ci, s.Afu.v, s.n_cells, s.nf, 3);
         d.Afu = upload_sell<double>(d.arena, h);
@@ -1032,7 +1042,8 @@ void upload_system(const System &s, DSystem &d) {
     d.mat_bytes = blk(s.Auu) + blk(s.Auf) + blk(s.Afu) + blk(s.Aff);
 }
 
-void update_system_flow_values(const System &s, DSystem &d, Staging &stg) {
+void update_system_flow_values(const System &s, DSystem &d, Staging &stg, bool auf) {
+    if (auf) upload_values(const_cast<double *>(d.Auf.val), d.src_auf, 3 * s.nf, s.Auf.v, stg);
     upload_values(const_cast<double *>(d.Afu.val), d.src_afu, s.nf * 3, s.Afu.v, stg);
     upload_values(const_cast<double *>(d.Aff.val), d.src_aff, s.nf * s.nf, s.Aff.v, stg);
 }
@@ -1112,6 +1123,16 @@ static void csr_spmv(const DCsr<T> &A, const T *x, const T *b, T *y, hipStream_t
     });
 }
 
+// Algorithmic bytes of one pass over a level operator: values and column indices of the
+// stored entries (16-bit columns count 2 bytes), row pointers, and `vecs` vectors of the
+// operator's row count (read or written once each; gathers counted once).
+template <typename T>
+static double op_bytes(const DCsr<T> &A, double vecs_rows, double vecs_cols = 0.0, double ncols = 0.0) {
+    const double cb = A.cd ? 2.0 : 4.0;
+    return (double)A.nnz * (sizeof(T) + cb) + 4.0 * (A.n + 1) + vecs_rows * A.n * sizeof(T) +
+           vecs_cols * ncols * sizeof(T);
+}
+
 template <typename T>
 static void vcycle(const DHierarchy<T> &H, HierWork<T> &W, int l, const T *b, T *out, hipStream_t st) {
     const int last = (int)H.lev.size() - 1;
@@ -1122,6 +1143,17 @@ static void vcycle(const DHierarchy<T> &H, HierWork<T> &W, int l, const T *b, T 
     }
     const DLevel<T> &L = H.lev[l];
     const bool cheb = H.smoother == PS_CHEB2;
+    // level 0 is timed when kernel timing is on (ktag: the hierarchy's first phase id)
+    const int tag = l == 0 ? H.ktag : -1;
+    auto scope = [&](std::optional<ktime::Scope> &o, int phase, double bytes) {
+        if (tag >= 0 && ktime::enabled()) o.emplace(tag + phase, st, bytes);
+    };
+    const int nc = H.lev[l + 1].n;
+    {
+        // l1-Jacobi: b, D^-1 (gathered) in, x and r out; Chebyshev: the first step (b, c0
+        // gathered, c1, cm in, x out) and the residual (x, b in, r out)
+        std::optional<ktime::Scope> ts;
+        scope(ts, 0, cheb ? op_bytes(L.A, 5) + op_bytes(L.A, 3) : op_bytes(L.A, l > 0 ? 3 : 4));
     with_G(L.A.G, [&](auto Gc) {
         constexpr int G = decltype(Gc)::value;
         unsigned g = grid_for((size_t)L.n * k::lanes_of<G>());
@@ -1134,17 +1166,31 @@ static void vcycle(const DHierarchy<T> &H, HierWork<T> &W, int l, const T *b, T 
             LAUNCH((k::csr_l1_pre<G, T>), g, 0, st, L.A, b, L.dinv, W.x[l], W.r[l]);
         }
     });
+    }
     if (!cheb && l + 1 < last) {
+        // R r (r gathered) with the coarse level's D^-1 in, b and x = D^-1 b out
+        std::optional<ktime::Scope> ts;
+        scope(ts, 1, op_bytes(L.R, 3, 1, L.n));
         with_G(L.R.G, [&](auto Gc) {
             constexpr int G = decltype(Gc)::value;
             LAUNCH((k::csr_restrict_l1<G, T>), grid_for((size_t)L.R.n * k::lanes_of<G>()), 0, st, L.R,
                    (const T *)W.r[l], H.lev[l + 1].dinv, W.b[l + 1], W.x[l + 1]);
         });
     } else {
+        std::optional<ktime::Scope> ts;
+        scope(ts, 1, op_bytes(L.R, 1, 1, L.n));
         csr_spmv<0, T>(L.R, (const T *)W.r[l], (const T *)nullptr, W.b[l + 1], st);
     }
     vcycle(H, W, l + 1, W.b[l + 1], W.e[l + 1], st);
-    csr_spmv<2, T>(L.P, (const T *)W.e[l + 1], (const T *)nullptr, W.x[l], st);
+    {
+        std::optional<ktime::Scope> ts;
+        scope(ts, 2, op_bytes(L.P, 2, 1, nc));             // e (gathered) in, x read and written
+        csr_spmv<2, T>(L.P, (const T *)W.e[l + 1], (const T *)nullptr, W.x[l], st);
+    }
+    // l1-Jacobi: b, x (gathered), D^-1 in, out written; Chebyshev: two sweeps (x, b, c0 in,
+    // x1, d0 out; x1, b, d0, c1, cm in, out written)
+    std::optional<ktime::Scope> ts;
+    scope(ts, 3, cheb ? op_bytes(L.A, 5) + op_bytes(L.A, 6) : op_bytes(L.A, 4));
     with_G(L.A.G, [&](auto Gc) {
         constexpr int G = decltype(Gc)::value;
         unsigned g = grid_for((size_t)L.n * k::lanes_of<G>());
@@ -1173,15 +1219,15 @@ template <int NF, int W, typename T, bool ACC, bool FINAL, bool GY>
 static void launch_sub_y(const SubBilu<T> &b, const T *src, PrecWork<T> &w, T *zf, hipStream_t st) {
     auto kern = k::bilu_sub<NF, W, T, ACC, FINAL, GY>;
     if (b.lds > 65536) {
-        static bool raised = false;          // per instantiation: allow the device's LDS maximum
-        if (!raised) {
+        // once per instantiation, also when several threads launch: allow the device's LDS maximum
+        static std::once_flag raised;
+        std::call_once(raised, [&] {
             int dev = 0, mx = 0;
             PS_HIP(hipGetDevice(&dev));
             PS_HIP(hipDeviceGetAttribute(&mx, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
             PS_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, mx));
-            raised = true;
-        }
+        });
     }
     k::SubLayout L{b.N, b.sub_off, b.flev_off, b.blev_off, b.flev, b.blev, b.bpos, b.ncell, b.npos, b.fcol, b.bcol};
     ktime::Scope ts(ktime::BILU_SUB, st, b.bytes);
@@ -1344,36 +1390,55 @@ void spmv_full(const DSystem &S, const TX *x, const double *b, double *y, hipStr
 
 // ------------------------------------------------------------------ Krylov workspace
 Krylov::~Krylov() {
-    if (hostscal) (void)hipHostFree(hostscal);
+    if (hostscal && own_hostscal) (void)hipHostFree(hostscal);
 }
 
-void alloc_krylov(Krylov &K, size_t N, int m, bool z_fp32) {
-    K.arena.release();
-    if (K.hostscal) {
-        (void)hipHostFree(K.hostscal);
-        K.hostscal = nullptr;
-    }
+// The workspace's arrays in one fixed order, each 256-byte aligned; `take(bytes)` hands
+// out the memory (an arena, or a bump pointer in caller-provided memory).
+template <typename Take>
+static void layout_krylov(Krylov &K, size_t N, int m, bool z_fp32, Take take) {
     K.m = m;
     K.N = N;
     K.z_fp32 = z_fp32;
     K.nblk = (int)std::min<size_t>(1024, std::max<size_t>(1, (N + 255) / 256));
     size_t chunk = (N + K.nblk - 1) / K.nblk;
     K.chunk = (int)((chunk + 63) / 64 * 64);
-    K.V = K.arena.alloc<double>((size_t)(m + 1) * N);
-    K.Z = z_fp32 ? (void *)K.arena.alloc<float>((size_t)m * N) : (void *)K.arena.alloc<double>((size_t)m * N);
-    K.H = K.arena.alloc<double>((size_t)(m + 1) * m);
-    K.cs = K.arena.alloc<double>(m);
-    K.sn = K.arena.alloc<double>(m);
-    K.g = K.arena.alloc<double>(m + 1);
-    K.y = K.arena.alloc<double>(m);
-    K.h1 = K.arena.alloc<double>(m + 2);
-    K.h2 = K.arena.alloc<double>(m + 2);
-    K.hsum = K.arena.alloc<double>(m + 2);
-    K.nw2 = K.arena.alloc<double>(2);
-    K.scal = K.arena.alloc<double>(8);
-    K.partial = K.arena.alloc<double>((size_t)(m + 2) * K.nblk);
-    K.r = K.arena.alloc<double>(N);
+    auto d = [&](size_t n) { return static_cast<double *>(take(n * sizeof(double))); };
+    K.V = d((size_t)(m + 1) * N);
+    K.Z = take((size_t)m * N * (z_fp32 ? sizeof(float) : sizeof(double)));
+    K.H = d((size_t)(m + 1) * m);
+    K.cs = d(m);
+    K.sn = d(m);
+    K.g = d(m + 1);
+    K.y = d(m);
+    K.h1 = d(m + 2);
+    K.h2 = d(m + 2);
+    K.hsum = d(m + 2);
+    K.nw2 = d(2);
+    K.scal = d(8);
+    K.partial = d((size_t)(m + 2) * K.nblk);
+    K.r = d(N);
+}
+
+static size_t round256(size_t b) { return ((b ? b : 1) + 255) / 256 * 256; }
+
+void alloc_krylov(Krylov &K, size_t N, int m, bool z_fp32) {
+    K.arena.release();
+    if (K.hostscal && K.own_hostscal) (void)hipHostFree(K.hostscal);
+    K.hostscal = nullptr;
+    layout_krylov(K, N, m, z_fp32, [&](size_t bytes) { return (void *)K.arena.alloc<char>(round256(bytes)); });
     PS_HIP(hipHostMalloc((void **)&K.hostscal, 8 * sizeof(double), hipHostMallocDefault));
+    K.own_hostscal = true;
+}
+
+size_t krylov_bytes(size_t N, int m, bool z_fp32) {
+    Krylov K;
+    size_t used = 0;
+    layout_krylov(K, N, m, z_fp32, [&](size_t bytes) {
+        used += round256(bytes);
+        return (void *)nullptr;
+    });
+    return used;
 }
 
 // partial[...] <- chunk sums; rows = nv (+1 for |w|^2)
@@ -1573,6 +1638,92 @@ bool Fgmres::advance() {
     }
     default:
         return false;
+    }
+}
+
+void rsl_diagonals(const DSystem &S, const DHierarchy<double> &sdc, RslWork &w, int iters,
+                   std::vector<double> &d_sp, std::vector<double> &d_pp, hipStream_t st) {
+    const int nf = S.nf, nc = S.n_cells;
+    const size_t nu = (size_t)3 * S.n_nodes, N = nu + (size_t)nf * nc;
+    if (!w.ready) {
+        std::vector<double> e(N, 0.0);                       // 1 on the pressure unknowns
+        for (int i = 0; i < nc; ++i) e[nu + (size_t)i * nf + nf - 1] = 1.0;
+        w.e = w.arena.upload(e.data(), N);
+        w.y = w.arena.alloc<double>(N);
+        w.g = w.arena.alloc<double>(N);
+        w.t = w.arena.alloc<double>(N);
+        w.z = w.arena.alloc<double>(nu);
+        alloc_hier_work(w.hw, sdc, w.arena);
+        w.ready = true;
+    }
+    fill_zero(w.y, N, st);                                   // y = 0 (its flow part stays 0)
+    fill_zero(w.g, N, st);
+    spmv_full<double>(S, w.e, nullptr, w.t, st);             // node rows: A_uu 0 + A_up e
+    PS_HIP(hipMemcpyAsync(w.g, w.t, nu * sizeof(double), hipMemcpyDeviceToDevice, st));
+    for (int it = 0; it < iters; ++it) {
+        spmv_full<double>(S, w.y, w.g, w.t, st);             // node rows: g - A_uu y
+        vcycle(sdc, w.hw, 0, (const double *)w.t, w.z, st);   // z = M_uu^{-1} (g - A_uu y)
+        LAUNCH((k::add_to<double>), grid_for(nu), 0, st, w.y, (const double *)w.z, nu);
+    }
+    spmv_full<double>(S, w.y, nullptr, w.t, st);             // cell rows: A_fu y
+    std::vector<double> h((size_t)nf * nc);
+    PS_HIP(hipMemcpyAsync(h.data(), w.t + nu, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    PS_HIP(hipStreamSynchronize(st));
+    d_sp.assign((size_t)nc * (nf - 1), 0.0);
+    d_pp.assign(nc, 0.0);
+    for (int i = 0; i < nc; ++i) {
+        for (int l = 0; l < nf - 1; ++l) d_sp[(size_t)i * (nf - 1) + l] = -h[(size_t)i * nf + l];
+        d_pp[i] = -h[(size_t)i * nf + nf - 1];
+    }
+}
+
+// Preconditioned Richardson iteration x_{k+1} = x_k + M^{-1}(b - A x_k) from x_0 = 0: the
+// two-stage preconditioner as a sequential (fixed-point) scheme, steps 1 and 2-8 of
+// Algorithm 1 alternating mechanics and flow updates (remark after Algorithm 1).  Stops when
+// |b - A x_k| <= rtol |b| (FP64 residual, checked every iteration) or after maxit steps.
+// Uses K.r (residual), the first column of K.Z (the correction) and K.scal.
+SolveOut richardson_blocking(const DSystem &S, Krylov &K, PrecFn &M, const double *b, double *x, double rtol,
+                             int maxit, hipStream_t st) {
+    SolveOut o;
+    const size_t N = K.N;
+    auto read_norm = [&](const double *v) {
+        norm2_dev(K, v, K.scal + 5, st);
+        PS_HIP(hipMemcpyAsync(K.hostscal, K.scal, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
+        PS_HIP(hipStreamSynchronize(st));
+        return std::sqrt(K.hostscal[5]);
+    };
+    const double beta_b = read_norm(b);
+    fill_zero(x, N, st);
+    if (!std::isfinite(beta_b)) {
+        o.status = PS_EINVAL;
+        return o;
+    }
+    if (beta_b == 0.0) {
+        PS_HIP(hipStreamSynchronize(st));
+        return o;
+    }
+    const double *r = b;                      // r_0 = b (x_0 = 0)
+    for (;;) {
+        M(r, K.Z, st);                        // z = M^-1 r
+        if (K.z_fp32) LAUNCH((k::add_to<float>), grid_for(N), 0, st, x, (const float *)K.Z, N);
+        else LAUNCH((k::add_to<double>), grid_for(N), 0, st, x, (const double *)K.Z, N);
+        spmv_full<double>(S, x, b, K.r, st);  // r = b - A x
+        r = K.r;
+        ++o.iterations;
+        const double rel = read_norm(K.r) / beta_b;
+        o.rel_residual = rel;
+        if (!std::isfinite(rel)) {
+            o.status = K.z_fp32 ? PS_EPRECISION : PS_EBREAKDOWN;
+            return o;
+        }
+        if (rel <= rtol) {
+            o.status = PS_OK;
+            return o;
+        }
+        if (o.iterations >= maxit) {
+            o.status = PS_EMAXIT;
+            return o;
+        }
     }
 }
 

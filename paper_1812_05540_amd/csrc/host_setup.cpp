@@ -249,7 +249,15 @@ Options options_from(const ps_options *o) {
     r.max_levels = o->max_levels;
     r.fp32_fallback = o->fp32_fallback;
     r.theta = o->theta;
+    r.method = o->method;
+    r.reduction = o->reduction;
+    r.fixed_stress = o->fixed_stress;
+    r.fs_iters = o->fs_iters;
     if (r.precision != PS_FP64 && r.precision != PS_FP32_PREC) throw Error(PS_EINVAL, "precision");
+    if (r.method != PS_FGMRES && r.method != PS_RICHARDSON) throw Error(PS_EINVAL, "method");
+    if (r.reduction != PS_QUASI_IMPES && r.reduction != PS_TRUE_IMPES) throw Error(PS_EINVAL, "reduction");
+    if (r.fixed_stress != PS_FS_GIVEN && r.fixed_stress != PS_FS_RSL) throw Error(PS_EINVAL, "fixed_stress");
+    if (r.fs_iters < 1 || r.fs_iters > 100) throw Error(PS_EINVAL, "fs_iters must be in 1..100");
     if (r.restart < 1 || r.restart > 200) throw Error(PS_EINVAL, "restart must be in 1..200");
     if (r.maxit < 1) throw Error(PS_EINVAL, "maxit must be positive");
     if (r.smoother != PS_CHEB2 && r.smoother != PS_L1JAC) throw Error(PS_EINVAL, "smoother");
@@ -437,15 +445,28 @@ Bsr fixed_stress(const System &s) {
     return S;
 }
 
-void quasi_impes(const System &s, const Bsr &Sff, Csr &Spp, std::vector<double> &dss_inv) {
+void quasi_impes(const System &s, const Bsr &Sff, Csr &Spp, std::vector<double> &dss_inv, int reduction) {
     int nf = s.nf, nn = nf * nf, m = nf - 1, nc = s.n_cells;
     std::vector<int> dpos = diag_positions(s.Aff);
+    // true-IMPES (eq. CPR_CSL): the cell blocks summed down each block column of A_ff, rows
+    // in increasing order; quasi-IMPES: the diagonal cell blocks
+    std::vector<double> csum;
+    if (reduction == PS_TRUE_IMPES) {
+        csum.assign((size_t)nc * nn, 0.0);
+        for (int k = 0; k < nc; ++k)
+            for (int t = s.Aff.rp[k]; t < s.Aff.rp[k + 1]; ++t) {
+                double *o = &csum[(size_t)s.Aff.ci[t] * nn];
+                const double *a = &s.Aff.v[(size_t)t * nn];
+                for (int e = 0; e < nn; ++e) o[e] += a[e];
+            }
+    }
     std::vector<double> t((size_t)nc * m);
     dss_inv.assign((size_t)nc * m * m, 0.0);
     std::atomic<int> singular{0};
     parallel_rows(nc, [&](int lo, int hi, int) {
         for (int i = lo; i < hi; ++i) {
-            const double *blk = &s.Aff.v[(size_t)dpos[i] * nn];   // original A_ff: A_ss, A_ps unmodified
+            // original A_ff (A_ss, A_ps unmodified by fixed stress)
+            const double *blk = reduction == PS_TRUE_IMPES ? &csum[(size_t)i * nn] : &s.Aff.v[(size_t)dpos[i] * nn];
             if (nf == 2) {
                 double dss = blk[0], dps = blk[nf * (nf - 1) + 0];
                 if (dss == 0.0) { singular = 1; continue; }
@@ -1054,10 +1075,10 @@ BiluSchedule color_schedule(const Bsr &S) {
     return sc;
 }
 
-void build_flow_operators(const System &s, FlowSetup &f) {
-    Tick t("fixed stress + qIMPES");
+void build_flow_operators(const System &s, const Options &o, FlowSetup &f) {
+    Tick t("fixed stress + IMPES reduction");
     fixed_stress(s, f.Sff);
-    quasi_impes(s, f.Sff, f.Spp, f.dss_inv);
+    quasi_impes(s, f.Sff, f.Spp, f.dss_inv, o.reduction);
 }
 
 void build_flow_local(const System &s, const Options &o, FlowSetup &f, bool pattern_only) {
@@ -1088,7 +1109,7 @@ void build_flow_local(const System &s, const Options &o, FlowSetup &f, bool patt
 }
 
 void build_flow(const System &s, const Options &o, FlowSetup &f) {
-    build_flow_operators(s, f);
+    build_flow_operators(s, o, f);
     {
         Tick t("pressure AMG");
         f.pres = amg_build(f.Spp, o);

@@ -50,6 +50,7 @@ struct Options {
     int ml_kind = PS_BILU0, ml_sweeps = 1, coarse_max = 256, max_levels = 25;
     int fp32_fallback = 0;
     double theta = 0.25;
+    int method = PS_FGMRES, reduction = PS_QUASI_IMPES, fixed_stress = PS_FS_GIVEN, fs_iters = 10;
 };
 
 Options options_from(const ps_options *o);
@@ -81,7 +82,9 @@ struct FlowSetup {                // recomputed at every ps_setup (Sec. 5.4)
 // --- setup steps ------------------------------------------------------------
 Bsr fixed_stress(const System &s);
 void fixed_stress(const System &s, Bsr &S);              // into S, reusing its storage
-void quasi_impes(const System &s, const Bsr &Sff, Csr &Spp, std::vector<double> &dss_inv);
+// reduction: PS_QUASI_IMPES (diagonal cell blocks) or PS_TRUE_IMPES (column sums)
+void quasi_impes(const System &s, const Bsr &Sff, Csr &Spp, std::vector<double> &dss_inv,
+                 int reduction = PS_QUASI_IMPES);
 Csr sdc_matrix(const System &s);                         // component-major
 Hierarchy amg_build(const Csr &A, const Options &o);
 // The steps of amg_build, for builders that form the Galerkin product elsewhere:
@@ -97,7 +100,7 @@ void block_jacobi_factor(const Bsr &S, Bsr &F);
 BiluSchedule bilu_schedule(const Bsr &S);
 BiluSchedule color_schedule(const Bsr &S);             // colour groups in fwd_ptr/fwd_rows
 void build_flow(const System &s, const Options &o, FlowSetup &f);
-void build_flow_operators(const System &s, FlowSetup &f);            // S_ff^(fs), S_pp, D_ss^{-1}
+void build_flow_operators(const System &s, const Options &o, FlowSetup &f);   // S_ff^(fs), S_pp, D_ss^{-1}
 // local-stage factors; pattern_only: a BILU(0) factor whose pattern and schedule exist
 // is left to the device (f.ml keeps its pattern, its values are not recomputed)
 void build_flow_local(const System &s, const Options &o, FlowSetup &f, bool pattern_only = false);

@@ -1215,6 +1215,13 @@ __global__ __launch_bounds__(WG) void convert(const TI *__restrict__ in, TO *__r
     if (i < n) out[i] = (TO)in[i];
 }
 
+// x += z (z in the preconditioner's type, widened exactly)
+template <typename TZ>
+__global__ __launch_bounds__(WG) void add_to(double *__restrict__ x, const TZ *__restrict__ z, size_t n) {
+    size_t i = (size_t)blockIdx.x * WG + threadIdx.x;
+    if (i < n) x[i] += (double)z[i];
+}
+
 template <typename T>
 __global__ __launch_bounds__(WG) void fill(T *__restrict__ p, T v, size_t n) {
     size_t i = (size_t)blockIdx.x * WG + threadIdx.x;

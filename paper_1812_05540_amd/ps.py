@@ -18,6 +18,9 @@ PS_EINVAL, PS_ENOMEM, PS_EDEVICE, PS_ENOTSETUP, PS_ESINGULAR = -1, -2, -3, -4, -
 PS_EMAXIT, PS_EPRECISION, PS_EBUSY, PS_EBREAKDOWN = -6, -7, -8, -9
 PS_FP64, PS_FP32_PREC = 0, 1
 PS_CHEB2, PS_L1JAC = 0, 1
+PS_FGMRES, PS_RICHARDSON = 0, 1
+PS_QUASI_IMPES, PS_TRUE_IMPES = 0, 1
+PS_FS_GIVEN, PS_FS_RSL = 0, 1
 PS_BILU0, PS_BJACOBI, PS_MCGS = 0, 1, 2
 PS_H_SDC, PS_H_PRES = 0, 1
 
@@ -40,7 +43,8 @@ class ps_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("restart", C.c_int32), ("maxit", C.c_int32),
                 ("smoother", C.c_int32), ("ml_kind", C.c_int32), ("ml_sweeps", C.c_int32),
                 ("coarse_max", C.c_int32), ("max_levels", C.c_int32), ("fp32_fallback", C.c_int32),
-                ("theta", C.c_double)]
+                ("theta", C.c_double), ("method", C.c_int32), ("reduction", C.c_int32),
+                ("fixed_stress", C.c_int32), ("fs_iters", C.c_int32)]
 
 
 class ps_result(C.Structure):
@@ -56,7 +60,7 @@ _SIGS = {
     "ps_ctx_create": (C.c_int, [C.c_int, C.c_size_t, C.POINTER(C.c_void_p)]),
     "ps_ctx_destroy": (None, [C.c_void_p]),
     "ps_create": (C.c_int, [C.c_void_p, C.POINTER(ps_system), C.POINTER(ps_options), C.POINTER(C.c_void_p)]),
-    "ps_update_flow": (C.c_int, [C.c_void_p, _f64p, _f64p, _f64p, _f64p]),
+    "ps_update_flow": (C.c_int, [C.c_void_p, _f64p, _f64p, _f64p, _f64p, _f64p]),
     "ps_setup": (C.c_int, [C.c_void_p]),
     "ps_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.POINTER(ps_result)]),
     "ps_apply_precond": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -204,8 +208,9 @@ def ps_create(ctx, sysobj, opts=None, mech_key=0):
     return out.value
 
 
-def ps_update_flow(h, afu_vals=None, aff_vals=None, d_sp=None, d_pp=None):
-    arrs = [None if a is None else np.ascontiguousarray(a, dtype=np.float64) for a in (afu_vals, aff_vals, d_sp, d_pp)]
+def ps_update_flow(h, afu_vals=None, aff_vals=None, d_sp=None, d_pp=None, auf_vals=None):
+    arrs = [None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+            for a in (afu_vals, aff_vals, d_sp, d_pp, auf_vals)]
     ptrs = [None if a is None else a.ctypes.data_as(_f64p) for a in arrs]
     _check(load().ps_update_flow(h, *ptrs), "ps_update_flow")
 

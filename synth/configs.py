@@ -24,9 +24,10 @@ from scipy.special import erfc, ndtr
 
 from .grf import gaussian_field, gaussian_field_2d
 from .jacobian import build_system, make_rhs, two_phase, three_phase, GRAV
+from .state import drive_pressure
 
 H = 10.0
-NOISE = 0.1e6
+DRIVE = 10e6            # pressure difference of the line drive across the grid (Pa)
 # Largest log10 permeability of the random-field workloads (about 20 D, the upper end of
 # reservoir rock such as the SPE10 data of the paper's second example).
 LOG10K_MAX = -10.7
@@ -36,19 +37,19 @@ def _rng(seed):
     return np.random.Generator(np.random.PCG64(seed))
 
 
-def _state(rng, nx, ny, nz, h=H, drive=1.0):
+def _state(nx, ny, nz, kperm, h=H, drive=1.0):
     """Synthetic pressure state and reference pressure (hydrostatic part).
 
-    drive = +1: pressure rises by 10 MPa along x; -1: falls along x (injection at x = 0).
+    p = p0 + p_drive: p0 = 20 MPa + rho_w0 g (z_top - z), and p_drive the steady
+    single-phase pressure of a 10 MPa line drive along x through the permeability field
+    (synth.state.drive_pressure), so that the Darcy fluxes are divergence free inside the
+    domain.  drive = +1: pressure rises along x; -1: falls along x (injection at x = 0).
     """
-    ci = np.tile(np.arange(nx), ny * nz)
     ck = np.repeat(np.arange(nz), nx * ny)
-    xc = (ci + 0.5) * h
     zc = (ck + 0.5) * h
     ztop = nz * h
     p0 = 20e6 + 1035.0 * GRAV * (ztop - zc)
-    ramp = xc / (nx * h) if drive > 0 else 1.0 - xc / (nx * h)
-    p = p0 + 10e6 * ramp + rng.normal(0.0, NOISE, nx * ny * nz)
+    p = p0 + drive_pressure(kperm, nx, ny, nz, h, DRIVE, drive)
     return p, p0
 
 
@@ -69,8 +70,9 @@ def fields_iid(nx, ny, nz, seed):
     logk = rng.normal(-13.0, 1.0, n)
     phi = rng.uniform(0.15, 0.3, n)
     S = rng.uniform(0.2, 0.8, (n, 1))
-    p, p0 = _state(rng, nx, ny, nz)
-    return dict(E=E, kperm=10.0 ** logk, phi=phi, S=S, p=p, p0=p0)
+    kperm = 10.0 ** logk
+    p, p0 = _state(nx, ny, nz, kperm)
+    return dict(E=E, kperm=kperm, phi=phi, S=S, p=p, p0=p0)
 
 
 def fields_grf(nx, ny, nz, seed, sigma=2.0, mean=-13.0, nph=2, e_seed=None, sat="iid"):
@@ -93,8 +95,9 @@ def fields_grf(nx, ny, nz, seed, sigma=2.0, mean=-13.0, nph=2, e_seed=None, sat=
         S = rng.uniform(0.2, 0.8, (n, 1))
     else:
         S = 0.05 + 0.85 * rng.dirichlet(np.ones(3), n)[:, :2]
-    p, p0 = _state(rng, nx, ny, nz, drive=drive)
-    return dict(E=E, kperm=10.0 ** logk, phi=phi, S=S, p=p, p0=p0)
+    kperm = 10.0 ** logk
+    p, p0 = _state(nx, ny, nz, kperm, drive=drive)
+    return dict(E=E, kperm=kperm, phi=phi, S=S, p=p, p0=p0)
 
 
 def fields_layered(nx, ny, nz, seed):
@@ -114,8 +117,9 @@ def fields_layered(nx, ny, nz, seed):
     phi = 0.15 + 0.15 * ndtr(g)
     E = np.exp(np.log(10e9) - 0.5 * g)
     S = rng.uniform(0.2, 0.8, (n, 1))
-    p, p0 = _state(rng, nx, ny, nz)
-    return dict(E=E, kperm=10.0 ** np.minimum(logk.ravel(), LOG10K_MAX), phi=phi, S=S, p=p, p0=p0)
+    kperm = 10.0 ** np.minimum(logk.ravel(), LOG10K_MAX)
+    p, p0 = _state(nx, ny, nz, kperm)
+    return dict(E=E, kperm=kperm, phi=phi, S=S, p=p, p0=p0)
 
 
 # name -> (grid, nf, recipe, matrix seed, rhs seed)

@@ -5,7 +5,8 @@ The oracle cannot run the whole solve at these sizes, so the checks are the ones
 hold at any size: the system SpMV on sampled rows computed one by one from the block
 matrices, the true FP64 residual of the returned x, the FP32- and FP64-preconditioned
 paths agreeing with each other, and the device-built pressure hierarchy equal to the
-host build on every level.
+host build on every level.  (The oracle comparison in the benchmarked configuration is
+in test_gpu_bench_config.py.)
 """
 import numpy as np
 import pytest
@@ -103,7 +104,7 @@ def test_grf64_spmv_rows_and_solves(ctx):
     sv.close()
     out = {}
     for prec in (ps.PS_FP32_PREC, ps.PS_FP64):
-        r, x, true_rel = solve(ctx, s, b, precision=prec)
+        r, x, true_rel = solve(ctx, s, b, precision=prec, ml_sweeps=2)
         assert r["status"] == ps.PS_OK, r
         assert true_rel <= 1.01e-8 and abs(true_rel - r["rel_residual"]) <= 1e-10, (true_rel, r)
         out[prec] = (r["iterations"], x)
@@ -133,30 +134,36 @@ def test_grf64_pressure_hierarchy_device_equals_host(ctx, monkeypatch):
     _cache.pop("grf64", None)
 
 
-def test_layered128_fp32_solve(ctx):
-    """128 x 128 x 96 cells, 7,988,259 unknowns, facies contrast ~1e6: the FP32-
-    preconditioned solve converges (it takes restarts) and its x has the reported residual."""
-    s, b = big("layered128")
+def both_paths(ctx, name, **kw):
+    """FP32- and FP64-preconditioned solves of one workload: both reach rtol 1e-8 with the
+    reported true residual, and their solutions agree to 1e-6 (the FP32 path's error
+    against the plain FP64 solve, the spec criterion)."""
+    s, b = big(name)
     sv = ps.Solver(ctx, s)
     check_spmv_rows(sv, s, 1000)
     sv.close()
-    r, _, true_rel = solve(ctx, s, b, precision=ps.PS_FP32_PREC)
-    assert r["status"] == ps.PS_OK, r
-    assert true_rel <= 1.01e-8 and abs(true_rel - r["rel_residual"]) <= 1e-10
-    _cache.pop("layered128", None)
+    out = {}
+    for prec in (ps.PS_FP32_PREC, ps.PS_FP64):
+        print(name, "precision", prec, kw, flush=True)
+        r, x, true_rel = solve(ctx, s, b, precision=prec, **kw)
+        assert r["status"] == ps.PS_OK, r
+        assert true_rel <= 1.01e-8 and abs(true_rel - r["rel_residual"]) <= 1e-10, (true_rel, r)
+        out[prec] = (r["iterations"], x)
+    (i32, x32), (i64, x64) = out[ps.PS_FP32_PREC], out[ps.PS_FP64]
+    diff = np.linalg.norm(x32 - x64) / np.linalg.norm(x64)
+    print(name, "iterations fp32 %d fp64 %d, solution difference %.2e" % (i32, i64, diff), flush=True)
+    assert abs(i32 - i64) <= 3
+    assert diff <= 1e-6, diff
+    _cache.pop(name, None)
 
 
-def test_three_phase_96_spmv_rows_and_residual_consistency(ctx):
-    """96 x 96 x 64 three-phase, 3,604,227 unknowns.  FGMRES(100) does not reach 1e-8
-    within 1000 iterations on this system (the residual plateaus after each restart; the
-    oracle shows the same plateau on smaller grids of the recipe before converging), so
-    the checks are the ones that hold regardless: SpMV rows, a status of OK or EMAXIT, and
-    a returned x whose true residual is the reported one and below the initial one."""
-    s, b = big("grf3ph96")
-    sv = ps.Solver(ctx, s)
-    check_spmv_rows(sv, s, 1500)
-    sv.close()
-    r, _, true_rel = solve(ctx, s, b, precision=ps.PS_FP32_PREC, maxit=300)
-    assert r["status"] in (ps.PS_OK, ps.PS_EMAXIT), r
-    assert abs(true_rel - r["rel_residual"]) <= 1e-10 and true_rel < 1.0
-    _cache.pop("grf3ph96", None)
+def test_layered128_both_paths(ctx):
+    """128 x 128 x 96 cells, 7,988,259 unknowns, facies contrast ~1e6 (the precision
+    variant): FP32-preconditioned against plain FP64, three local-stage sweeps."""
+    both_paths(ctx, "layered128", ml_sweeps=3)
+
+
+def test_three_phase_96_both_paths(ctx):
+    """96 x 96 x 64 three-phase (3 x 3 flow blocks), 3,604,227 unknowns: both paths reach
+    rtol 1e-8, three local-stage sweeps."""
+    both_paths(ctx, "grf3ph96", ml_sweeps=3)

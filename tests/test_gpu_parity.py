@@ -2,8 +2,9 @@
 
 Tolerances: FP64 kernels differ from the oracle only in summation order and fused
 multiply-adds, so single operators agree to ~1e-13 relative; a preconditioner
-application chains V-cycles and triangular sweeps (error amplified by their
-operator norms, measured ~1e2-1e3), bound 1e-10.  FP64 solves: iteration count
+application chains V-cycles and triangular sweeps and is compared field by field
+(displacement, saturation, pressure), each against its own oracle norm, with the
+bounds FP64_BLOCK_TOL / FP32_BLOCK_TOL below.  FP64 solves: iteration count
 equal to the oracle's +-1 and the solution within 1e-9 of the oracle's iterate at
 the same iteration.  FP32 preconditioner: true FP64 residual <= rtol and solution
 error vs a tightly converged oracle solution <= 1e-6 or, when the problem's
@@ -62,12 +63,40 @@ def make_solver(ctx, s, **opts):
     return sv
 
 
+# Per-field bounds on a preconditioner output, each relative to the oracle's field norm.
+# FP64: the kernels differ from the oracle only in summation order and fused multiply-
+# adds; measured at most 1.1e-12 (the saturation field, which step 6 forms by
+# cancellation: w_s = y_s - S_ss z_s - S_sp z_p with z_s ~ D_ss^-1 y_s), bound 1e-11.
+# FP32 preconditioner (unit roundoff 6e-8): measured at most 1.2e-7 (u), 2.6e-7 (p) and
+# 1.8e-4 (s, the same cancellation amplifying FP32 rounding by ~1e3); bounds 1e-6, 1e-3,
+# 1e-6.
+FP64_BLOCK_TOL = 1e-11
+FP32_BLOCK_TOL = (1e-6, 1e-3, 1e-6)
+
+
+def block_errors(z, ref, s):
+    """Relative error of each field of a preconditioner output, each against its own
+    oracle norm: (z_u, z_s, z_p).  One norm over the whole vector would be dominated
+    by the pressure block (|z_u|/|z| ~ 1e-6 on the random fields)."""
+    nu, nf = s.n_u, s.nf
+    out = []
+    for sl in (lambda a: a[:nu], lambda a: a[nu:].reshape(-1, nf)[:, : nf - 1],
+               lambda a: a[nu:].reshape(-1, nf)[:, nf - 1]):
+        out.append(np.linalg.norm(sl(z) - sl(ref)) / np.linalg.norm(sl(ref)))
+    return out
+
+
 def oracle_opts(**opts):
     return Options(smoother={ps.PS_CHEB2: "cheb2", ps.PS_L1JAC: "l1jac"}[opts.get("smoother", ps.PS_CHEB2)],
                    ml_kind={ps.PS_BILU0: "bilu0", ps.PS_BJACOBI: "bjacobi",
                             ps.PS_MCGS: "mcgs"}[opts.get("ml_kind", ps.PS_BILU0)],
                    ml_sweeps=opts.get("ml_sweeps", 1), restart=opts.get("restart", 100),
-                   maxit=opts.get("maxit", 1000))
+                   maxit=opts.get("maxit", 1000),
+                   method={ps.PS_FGMRES: "fgmres", ps.PS_RICHARDSON: "richardson"}[opts.get("method", ps.PS_FGMRES)],
+                   reduction={ps.PS_QUASI_IMPES: "quasi", ps.PS_TRUE_IMPES: "true"}[
+                       opts.get("reduction", ps.PS_QUASI_IMPES)],
+                   fixed_stress={ps.PS_FS_GIVEN: "given", ps.PS_FS_RSL: "rsl"}[opts.get("fixed_stress", ps.PS_FS_GIVEN)],
+                   fs_iters=opts.get("fs_iters", 10))
 
 
 @pytest.mark.parametrize("name", list(SMALL))
@@ -93,6 +122,11 @@ PRECOND_CASES = [
     ("iid3ph", dict(ml_kind=ps.PS_BJACOBI, ml_sweeps=2, smoother=ps.PS_L1JAC)),
     ("grf12", dict(ml_kind=ps.PS_MCGS, ml_sweeps=3)),
     ("iid3ph", dict(ml_kind=ps.PS_MCGS, ml_sweeps=2)),
+    # the alternative reductions of Sec. 5.1 / 5.3 (true-IMPES, row-sum-lumped fixed stress)
+    ("grf12", dict(reduction=ps.PS_TRUE_IMPES)),
+    ("iid3ph", dict(reduction=ps.PS_TRUE_IMPES, smoother=ps.PS_L1JAC)),
+    ("grf12", dict(fixed_stress=ps.PS_FS_RSL)),
+    ("iid3ph", dict(fixed_stress=ps.PS_FS_RSL, fs_iters=4, smoother=ps.PS_L1JAC)),
 ]
 
 
@@ -107,8 +141,8 @@ def test_precond_fp64_matches_oracle(ctx, name, opts):
         z = dev(np.zeros(s.N))
         sv.apply_precond(dev(v), z)
         ref = P.apply_precond(st, v)
-        err = np.linalg.norm(host(z) - ref) / np.linalg.norm(ref)
-        assert err <= 1e-10, err
+        errs = block_errors(host(z), ref, s)
+        assert max(errs) <= FP64_BLOCK_TOL, errs
     sv.close()
 
 
@@ -123,12 +157,12 @@ def test_level_layouts_match_oracle(ctx, name, opts, layout, monkeypatch):
     st = P.setup(s, oracle_opts(**opts))
     v = np.random.default_rng(4).standard_normal(s.N)
     ref = P.apply_precond(st, v)
-    for prec, tol in ((ps.PS_FP64, 1e-10), (ps.PS_FP32_PREC, 1e-3)):
+    for prec, tol in ((ps.PS_FP64, (FP64_BLOCK_TOL,) * 3), (ps.PS_FP32_PREC, FP32_BLOCK_TOL)):
         sv = make_solver(ctx, s, precision=prec, **opts)
         z = dev(np.zeros(s.N))
         sv.apply_precond(dev(v), z)
-        err = np.linalg.norm(host(z) - ref) / np.linalg.norm(ref)
-        assert err <= tol, (prec, err)
+        errs = block_errors(host(z), ref, s)
+        assert all(e <= t for e, t in zip(errs, tol)), (prec, errs)
         sv.close()
 
 
@@ -141,14 +175,21 @@ def test_precond_fp32_close_to_fp64(ctx, name):
     z = dev(np.zeros(s.N))
     sv.apply_precond(dev(v), z)
     ref = P.apply_precond(st, v)
-    err = np.linalg.norm(host(z) - ref) / np.linalg.norm(ref)
-    assert err <= 1e-3, err          # FP32 rounding amplified through the V-cycles and sweeps
+    errs = block_errors(host(z), ref, s)
+    assert all(e <= t for e, t in zip(errs, FP32_BLOCK_TOL)), errs
     sv.close()
 
 
-@pytest.mark.parametrize("name,opts", [("iid8", dict()), ("grf12s1", dict(ml_sweeps=2)),
+@pytest.mark.parametrize("name,opts", [("iid8", dict()), ("grf12", dict()), ("grf12", dict(smoother=ps.PS_L1JAC)),
+                                       ("grf12", dict(ml_sweeps=2)), ("grf12s1", dict(ml_sweeps=2)),
                                        ("iid3ph", dict(smoother=ps.PS_L1JAC)),
-                                       ("grf12s1", dict(ml_kind=ps.PS_MCGS, ml_sweeps=3))])
+                                       ("grf12", dict(ml_kind=ps.PS_MCGS, ml_sweeps=3)),
+                                       # (true-IMPES stalls on the sigma = 2 and three-phase fields,
+                                       # whose D_ss keeps only accumulation where transport dominates)
+                                       ("iid8", dict(reduction=ps.PS_TRUE_IMPES)),
+                                       ("iid3ph", dict(fixed_stress=ps.PS_FS_RSL)),
+                                       ("iid8", dict(method=ps.PS_RICHARDSON)),
+                                       ("iid3ph", dict(method=ps.PS_RICHARDSON, smoother=ps.PS_L1JAC))])
 def test_fp64_solve_matches_oracle(ctx, name, opts):
     s, b = small(name)
     out = oracle_solve(s, b, rtol=1e-8, opts=oracle_opts(**opts), record_iterates=True)
@@ -166,13 +207,15 @@ def test_fp64_solve_matches_oracle(ctx, name, opts):
 
 @pytest.mark.parametrize("opts", [dict(ml_sweeps=2), dict(ml_kind=ps.PS_MCGS, ml_sweeps=3)])
 def test_fp64_iterates_match_oracle_at_matched_k_on_ill_conditioned_field(ctx, opts):
-    """sigma = 2 field (cond ~1e10): rounding differences between the GPU and the oracle
-    are amplified along the iteration, so compare iterates at matched k rather than final
-    iteration counts: x_k (GPU stopped by maxit = k) against the oracle's x_k."""
+    """sigma = 2 field (cond ~1e10): x_k (GPU stopped by maxit = k) against the oracle's
+    x_k at k = 5, 15, 30, each within 1e-9.  Rounding differences (a few 1e-16 per
+    operation) grow along the iteration by at most ~1e5 on this field (oracle against
+    itself with 1e-13 relative noise on every preconditioner output: drift 4e-9 at k = 5,
+    falling to 1e-13 by k = 30), and the GPU's drift measured 2e-10 at most."""
     s, b = small("grf12")
     out = oracle_solve(s, b, rtol=1e-30, opts=oracle_opts(maxit=30, **opts), record_iterates=True)
     errs = []
-    for k, tol in ((5, 1e-9), (15, 1e-7), (30, 1e-5)):
+    for k, tol in ((5, 1e-9), (15, 1e-9), (30, 1e-9)):
         sv = make_solver(ctx, s, maxit=k, **opts)
         x = dev(np.zeros(s.N))
         r = sv.solve(dev(b), x, 1e-30)
@@ -216,7 +259,7 @@ def test_processor_local_bilu_matches_oracle(ctx):
     z = dev(np.zeros(s.N))
     sv.apply_precond(dev(v), z)
     ref = P.apply_precond(st, v)
-    assert np.linalg.norm(host(z) - ref) / np.linalg.norm(ref) <= 1e-10
+    assert max(block_errors(host(z), ref, s)) <= FP64_BLOCK_TOL
     out = oracle_solve(s, b, rtol=1e-8, setup_result=st)
     x = dev(np.zeros(s.N))
     r = sv.solve(dev(b), x, 1e-8)
@@ -263,7 +306,7 @@ def test_subdomain_bilu_kernel_matches_level_kernels(ctx, case, precision, monke
     if precision == ps.PS_FP64:
         st = P.setup(s, Options(ml_sweeps=sweeps))
         ref = P.apply_precond(st, host(v))
-        assert np.linalg.norm(za - ref) / np.linalg.norm(ref) <= 1e-10
+        assert max(block_errors(za, ref, s)) <= FP64_BLOCK_TOL
 
 
 @pytest.mark.parametrize("precision", [ps.PS_FP64, ps.PS_FP32_PREC])

@@ -132,3 +132,43 @@ def test_wait_and_busy_handle(reqs):
         sv.close()
     finally:
         ps.ps_ctx_destroy(ctx)
+
+
+def test_released_handle_is_reused_with_the_same_results():
+    """A set-up handle released by ps_destroy is taken by the next ps_create of a system
+    with the same mech_key, options and patterns (another field on the same grid): its
+    first setup runs the device path, and its solve equals, bit for bit, the solve of a
+    fresh handle (host-built first setup) on the same system."""
+    from synth.jacobian import box_partition
+    ps.load()
+    ctx = ps.ps_ctx_create(0, 0)
+    try:
+        systems = []
+        for i in range(2):
+            s, b = workload(grid=(10, 10, 10), kind="grf", seed=7100 + i, rhs_seed=9100 + i, sigma=1.5, e_seed=10)
+            s.ml_part = box_partition(10, 10, 10, 5, 5, 5)
+            systems.append((s, b))
+        opts = dict(precision=ps.PS_FP32_PREC, smoother=ps.PS_L1JAC)
+        sv = ps.Solver(ctx, systems[0][0], mech_key=10, **opts)
+        sv.setup()
+        x = dev(np.zeros(systems[0][0].N))
+        assert sv.solve(dev(systems[0][1]), x, 1e-8)["status"] == ps.PS_OK
+        first = sv.h
+        sv.close()                                       # kept by the context
+        s, b = systems[1]
+        out = []
+        for key in (10, 0):                             # reused handle, then a fresh one
+            sv = ps.Solver(ctx, s, mech_key=key, **opts)
+            if key == 10:
+                assert sv.h == first
+            sv.setup()
+            x = dev(np.zeros(s.N))
+            r = sv.solve(dev(b), x, 1e-8)
+            torch.cuda.synchronize()
+            out.append((r, x.cpu().numpy()))
+            sv.close()
+        (ra, xa), (rb, xb) = out
+        assert ra["status"] == rb["status"] == ps.PS_OK and ra["iterations"] == rb["iterations"]
+        assert np.array_equal(xa, xb)
+    finally:
+        ps.ps_ctx_destroy(ctx)

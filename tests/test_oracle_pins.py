@@ -657,3 +657,133 @@ def test_power_iteration_estimate_brute_force_and_bound():
     assert abs(lam - np.linalg.norm(B @ w9) / np.linalg.norm(w9)) <= 1e-13 * lam
     rho = 1.0 + np.cos(np.pi / (n + 1))
     assert lam <= rho * (1 + 1e-12) and lam > 0.5 * rho
+
+
+# ---------------------------------------------------------------------------- alternatives
+@pytest.mark.parametrize("kind", ["iid", "iid3"])
+def test_true_impes_column_sum_lumping_dense(kind):
+    """True-IMPES (eq. CPR_CSL): D_ss = diag(A_ss^T e), D_ps = diag(A_ps^T e) -- for
+    nf = 3 the s-s and p-s cell blocks summed down each block column -- and S_pp and
+    step 3 built from them, by dense brute force."""
+    s, _ = tiny(kind=kind, grid=(3, 3, 2))
+    st = P.setup(s, Options(reduction="true"))
+    nf, m = s.nf, s.nf - 1
+    sidx, pidx = perms(s)
+    Aff = dense(st.mats["Aff"])
+    Sff = dense(st.Sff)
+    Ass = Aff[np.ix_(sidx, sidx)]
+    Aps = Aff[np.ix_(pidx, sidx)]
+    Dss = np.zeros_like(Ass)
+    Dps = np.zeros_like(Aps)
+    for c in range(s.n_cells):
+        sl = slice(c * m, (c + 1) * m)
+        for k in range(s.n_cells):               # block column c: rows of every cell k
+            Dss[sl, sl] += Ass[k * m:(k + 1) * m, sl]
+            Dps[c, sl] += Aps[k, sl]
+    if nf == 2:                                   # the scalar case is exactly e^T A_ss
+        assert np.allclose(np.diag(Dss), Ass.sum(axis=0), rtol=1e-13)
+        assert np.allclose(np.diag(Dps), Aps.sum(axis=0), rtol=1e-13)
+    Spp = Sff[np.ix_(pidx, pidx)] - Dps @ np.linalg.inv(Dss) @ Sff[np.ix_(sidx, pidx)]
+    assert np.allclose(dense(st.Spp), Spp, rtol=1e-12, atol=1e-12 * np.abs(Spp).max())
+    dss_inv = np.zeros_like(Dss)
+    for c in range(s.n_cells):
+        sl = slice(c * m, (c + 1) * m)
+        dss_inv[sl, sl] = st.dss_inv[c]
+    assert np.allclose(dss_inv, np.linalg.inv(Dss), rtol=1e-12, atol=1e-12 * np.abs(dss_inv).max())
+    # and it differs from quasi-IMPES whenever fluxes couple the saturations
+    qi = P.setup(s, Options())
+    assert not np.allclose(dense(qi.Spp), dense(st.Spp))
+
+
+def test_true_impes_equals_quasi_impes_without_saturation_flux_terms():
+    """With no saturation derivatives off the diagonal (A_ss, A_ps block-diagonal), the
+    column sums are the diagonal blocks and the two reductions coincide."""
+    s, _ = tiny(kind="iid", grid=(3, 2, 2))
+    rows = np.repeat(np.arange(s.n_cells), np.diff(s.Aff.rowptr))
+    off = rows != s.Aff.colind
+    s.Aff.vals[off, :, : s.nf - 1] = 0.0
+    a = P.setup(s, Options(reduction="true"))
+    b = P.setup(s, Options())
+    assert np.array_equal(dense(a.Spp), dense(b.Spp))
+    assert np.array_equal(a.dss_inv, b.dss_inv)
+
+
+def test_rsl_diagonals_converge_to_the_exact_row_sums():
+    """eq. FS_RSL with A_uu^{-1} applied exactly: -diag(A_fu A_uu^{-1} A_up e) by a dense
+    solve; the oracle's V-cycle Richardson approximation approaches it as the number of
+    steps grows (and is the exact Schur complement's row sums over the pressure columns)."""
+    s, _ = tiny(kind="iid3", grid=(3, 3, 2))
+    mats = P.system_matrices(s)
+    nf, nc = s.nf, s.n_cells
+    Auu, Auf, Afu = dense(mats["Auu"]), dense(mats["Auf"]), dense(mats["Afu"])
+    sidx, pidx = perms(s)
+    Aup = Auf[:, pidx]
+    y = np.linalg.solve(Auu, Aup @ np.ones(nc))
+    w = Afu @ y
+    exact_sp = -w[sidx].reshape(nc, nf - 1)
+    exact_pp = -w[pidx]
+    # the same numbers are the row sums of the exact first-level Schur complement's
+    # coupling part  -A_fu A_uu^{-1} A_up  (Sec. 5.1)
+    C = -Afu @ np.linalg.solve(Auu, Aup)
+    assert np.allclose(C.sum(axis=1), np.concatenate([exact_sp, exact_pp[:, None]], 1).ravel(), rtol=1e-10)
+    sdc = amg.build(P.sdc_matrix(s), smoother="cheb2")
+    errs = []
+    for its in (1, 5, 40):
+        d_sp, d_pp = P.rsl_diagonals(s, mats, sdc, "cheb2", its)
+        errs.append(max(np.abs(d_sp - exact_sp).max() / np.abs(exact_sp).max(),
+                        np.abs(d_pp - exact_pp).max() / np.abs(exact_pp).max()))
+    assert errs[0] > errs[1] > errs[2] and errs[2] <= 1e-8, errs
+    # fixed stress with RSL diagonals: S_ff = A_ff + the lumped diagonals, nothing else
+    st = P.setup(s, Options(fixed_stress="rsl", fs_iters=40), mechanics=sdc)
+    D = dense(st.Sff) - dense(mats["Aff"])
+    expect = np.zeros_like(D)
+    for c in range(nc):
+        for l in range(nf - 1):
+            expect[c * nf + l, c * nf + nf - 1] = exact_sp[c, l]
+        expect[c * nf + nf - 1, c * nf + nf - 1] = exact_pp[c]
+    assert np.allclose(D, expect, rtol=1e-7, atol=1e-8 * np.abs(expect).max())
+
+
+def test_richardson_iterates_equal_the_stationary_closed_form():
+    """x_k of the preconditioned Richardson iteration from x_0 = 0 is
+    sum_{i<k} (I - M A)^i M b for a linear M (dense matrices, brute force), and with
+    M = A^{-1} it converges in one step."""
+    from oracle.fgmres import richardson
+    s, b = tiny(kind="iid", grid=(2, 2, 2))
+    st = P.setup(s)
+    A = dense(st.mats["A"])
+    n = A.shape[0]
+    M = np.column_stack([P.apply_precond(st, e) for e in np.eye(n)])
+    out = richardson(lambda v: A @ v, lambda v: M @ v, b, rtol=1e-300, maxit=6, record_iterates=True)
+    G = np.eye(n) - M @ A
+    acc = np.zeros(n)
+    term = M @ b
+    for k in range(6):
+        acc = acc + term
+        term = G @ term
+        assert np.allclose(out["iterates"][k], acc, rtol=1e-10, atol=1e-12 * np.abs(acc).max())
+    one = richardson(lambda v: A @ v, lambda v: np.linalg.solve(A, v), b, rtol=1e-6, maxit=5)
+    assert one["iterations"] == 1 and one["status"] == 0
+    assert np.allclose(one["x"], np.linalg.solve(A, b), rtol=1e-8)
+
+
+def test_eisenstat_walker_forcing_values():
+    """The forcing of the Sec. 4 remark with gamma = 0.9, omega = 2, eta_0 = 0.1, by hand."""
+    from oracle.newton import ew_eta
+    assert ew_eta(0, 5.0, None, None) == 0.1
+    assert np.isclose(ew_eta(1, 1.0, 2.0, 0.1), 0.9 * 0.25)               # 0.9 * 0.1^2 < 0.1
+    assert np.isclose(ew_eta(2, 1.0, 100.0, 0.5), 0.9 * 0.25)             # safeguard 0.225 > 0.1
+    assert np.isclose(ew_eta(2, 1.0, 100.0, 0.2), 0.9 * 1e-4)             # 0.036 <= 0.1: no safeguard
+    assert ew_eta(3, 10.0, 1.0, 0.5) == 0.9                               # capped
+
+
+def test_oracle_newton_converges_fast_near_the_solution():
+    """Newton on one backward-Euler day of a tiny i.i.d. grid: the scaled residual falls at
+    every step and reaches 1e-8 of the initial one, the last two steps by 100x or more."""
+    from synth.nonlinear import time_step
+    from oracle.newton import newton
+    out = newton(time_step((5, 4, 3), kind="iid", seed=3), tol=1e-8, max_steps=10,
+                 opts=Options(smoother="l1jac"))
+    res = [st["residual"] for st in out["steps"]]
+    assert out["converged"] and all(b < a for a, b in zip(res, res[1:]))
+    assert res[-1] < 0.01 * res[-2] and res[-2] < 0.01 * res[-3]

@@ -139,3 +139,30 @@ def test_three_phase_layout():
     assert s.nf == 3 and s.p_index == 2
     assert s.Aff.vals.shape[1:] == (3, 3) and s.Afu.vals.shape[1:] == (3, 3)
     assert s.d_sp.shape == (48, 2)
+
+
+@pytest.mark.parametrize("kind", ["iid", "iid3"])
+def test_time_step_jacobian_matches_finite_differences(kind):
+    """The Jacobian system of synth.nonlinear (unscaled: C^-1 J~ C^-1) against central
+    differences of its residual at a perturbed state (u != 0)."""
+    from synth.nonlinear import time_step
+    from oracle import precond as P
+    ts = time_step((4, 3, 3), kind=kind, seed=3)
+    rng = np.random.default_rng(0)
+    nf, nu = ts.nf, 3 * ts.nn
+    scale = np.concatenate([np.full(nu, 1e-9), np.tile([1e-6] * (nf - 1) + [0.1], ts.nc)])
+    x = ts.initial_state() + scale * rng.standard_normal(nu + nf * ts.nc)
+    system = ts.system(x)
+    c = ts.scale_vector(system)
+    J = P.system_matrices(system)["A"].toarray() / c[:, None] / c[None, :]
+    for _ in range(3):
+        v = rng.standard_normal(x.shape) * np.concatenate([np.full(nu, 1e-4), np.tile([1e-3] * (nf - 1) + [1e2], ts.nc)])
+        v[:nu][ts.mask] = 0.0
+        eps = 1e-4
+        fd = (ts.residual(x + eps * v) - ts.residual(x - eps * v)) / (2 * eps)
+        jv = J @ v
+        for sl in (slice(0, nu), slice(nu, None)):
+            assert np.linalg.norm(fd[sl] - jv[sl]) <= 1e-7 * np.linalg.norm(fd[sl])
+    # the step starts in mechanical equilibrium with no accumulation change
+    r0 = ts.residual(ts.initial_state())
+    assert np.all(r0[:nu] == 0.0)
