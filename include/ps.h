@@ -172,6 +172,26 @@ int  ps_setup(ps_handle *h);
 int  ps_solve(ps_handle *h, const double *rhs, double *x, double rtol, void *stream,
               ps_result *res);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): ps_solve with the FGMRES
+ * workspace -- the basis V ((restart+1) x N FP64), Z (restart x N, FP32 in the FP32
+ * path, else FP64), the Hessenberg matrix, rotations, reduction partials and the
+ * residual vector -- placed in a static device array of PS_NOALLOC_SCRATCH_BYTES that
+ * the library holds on each device it runs on until the process ends.  The call
+ * allocates nothing: the handle must be set up (ps_setup allocates the preconditioner),
+ * and the array's device address and a 64-byte pinned scalar mirror are set up once per
+ * device by ps_ctx_create.  Same arguments, results and statuses as ps_solve, except:
+ *  - PS_EINVAL when the workspace does not fit: about (restart+1) N 8 + restart N s
+ *    + N 8 bytes (s = 4 in the FP32 path, 8 otherwise), so N <= about 220,000 at
+ *    restart 100 with the FP32 preconditioner (the 16^3 to 32^3 grids);
+ *  - no FP64 retry after PS_EPRECISION (fp32_fallback is ignored).
+ * Every call on a device shares that device's array, which keeps the last call's
+ * contents: calls on one device are serialised by a lock inside the library (two
+ * processes on one device each have their own copy); the call is blocking. */
+#define PS_NOALLOC_SCRATCH_BYTES (256u << 20)
+int  ps_solve_noalloc(ps_handle *h, const double *rhs, double *x, double rtol, void *stream,
+                      ps_result *res);
+
 /* One application of the preconditioner, z = M^{-1} v (Algorithm 1), in the
  * handle's precision (v, z device FP64 arrays of length N).  Stream-ordered: the
  * work is enqueued on `stream` and the call returns without waiting for it. */

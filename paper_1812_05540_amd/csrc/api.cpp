@@ -255,6 +255,37 @@ void ensure_mech_device(ps_handle *h, bool need64, bool need32) {
     }
 }
 
+// ---------------------------------------------------------------- no-allocation solves
+// Static device memory for ps_solve_noalloc: the Krylov workspace of one solve at a time
+// per device.  Host code never uses the array's name as an address (it is a host-side
+// stand-in); the device address comes from hipGetSymbolAddress, looked up once per device
+// with that device current, at ps_ctx_create.
+__device__ __align__(256) unsigned char scratch[PS_NOALLOC_SCRATCH_BYTES];
+
+struct NoAllocDev {
+    std::once_flag once;
+    void *ptr = nullptr;                // this device's copy of `scratch`
+    double *hostscal = nullptr;         // pinned scalar mirror used by the solve's driver
+    std::mutex mu;                      // one ps_solve_noalloc at a time on this device
+};
+constexpr int kMaxDevices = 64;
+NoAllocDev g_noalloc[kMaxDevices];
+
+// Called with `dev` current (ps_ctx_create).
+void noalloc_init(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) throw Error(PS_EINVAL, "device index beyond the no-allocation table");
+    NoAllocDev &d = g_noalloc[dev];
+    std::call_once(d.once, [&] {
+        void *p = nullptr;
+        PS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        double *hs = nullptr;
+        PS_HIP(hipHostMalloc((void **)&hs, 8 * sizeof(double), hipHostMallocDefault));
+        d.ptr = p;
+        d.hostscal = hs;
+    });
+    if (!d.ptr || !d.hostscal) throw Error(PS_EDEVICE, "no-allocation scratch not set up for this device");
+}
+
 }  // namespace
 
 // ====================================================================== C ABI
@@ -305,6 +336,7 @@ int ps_ctx_create(int device, size_t budget, ps_ctx **out) {
         PS_HIP(hipGetDeviceCount(&n));
         if (device < 0 || device >= n) throw Error(PS_EINVAL, "no such device");
         set_device(device);
+        noalloc_init(device);
         auto c = std::make_unique<ps_ctx>();
         c->device = device;
         if (budget == 0) {
@@ -579,6 +611,48 @@ int ps_solve(ps_handle *h, const double *rhs, double *x, double rtol, void *stre
             alloc_krylov(K64, h->sys.N(), m, false);
             o = run_solve(h, K64, false, rhs, x, rtol, st);
         }
+        if (res) {
+            res->status = o.status;
+            res->iterations = o.iterations;
+            res->restarts = o.restarts;
+            res->rel_residual = o.rel_residual;
+            res->setup_s = h->setup_s;
+            res->solve_s = now_s() - t0;
+        }
+        return o.status;
+    });
+    if (code != PS_OK && res && code != PS_EMAXIT && code != PS_EPRECISION && code != PS_EBREAKDOWN)
+        res->status = code;
+    return code;
+}
+
+int ps_solve_noalloc(ps_handle *h, const double *rhs, double *x, double rtol, void *stream, ps_result *res) {
+    int code = guard([&] {
+        check_solve_args(h, rhs, x, rtol);
+        const int dev = h->ctx->device;
+        NoAllocDev &d = g_noalloc[dev];
+        if (!d.ptr) throw Error(PS_EDEVICE, "no-allocation scratch not set up for this device");
+        const bool f32 = use_fp32(h);
+        const int m = workspace_m(h);
+        const size_t need = krylov_bytes(h->sys.N(), m, f32);
+        if (need > (size_t)PS_NOALLOC_SCRATCH_BYTES)
+            throw Error(PS_EINVAL, "ps_solve_noalloc: N = " + std::to_string(h->sys.N()) + " with restart " +
+                                       std::to_string(h->opt.restart) + " needs " + std::to_string(need) +
+                                       " bytes of scratch; the maximum is " +
+                                       std::to_string((size_t)PS_NOALLOC_SCRATCH_BYTES));
+        bool expected = false;
+        if (!h->busy.compare_exchange_strong(expected, true)) throw Error(PS_EBUSY, "handle has a request in flight");
+        struct Unbusy {
+            ps_handle *h;
+            ~Unbusy() { h->busy = false; }
+        } ub{h};
+        std::lock_guard<std::mutex> lk(d.mu);
+        set_device(dev);
+        hipStream_t st = (hipStream_t)stream;
+        double t0 = now_s();
+        Krylov K;
+        carve_krylov(K, d.ptr, (size_t)PS_NOALLOC_SCRATCH_BYTES, h->sys.N(), m, f32, d.hostscal);
+        SolveOut o = run_solve(h, K, f32, rhs, x, rtol, st);
         if (res) {
             res->status = o.status;
             res->iterations = o.iterations;

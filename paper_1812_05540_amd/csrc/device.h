@@ -367,6 +367,10 @@ void alloc_prec_work(PrecWork<T> &w, const DHierarchy<T> &sdc, const DFlow<T> &f
 void alloc_krylov(Krylov &k, size_t N, int m, bool z_fp32);
 // bytes of device memory a Krylov workspace takes (arrays 256-byte aligned)
 size_t krylov_bytes(size_t N, int m, bool z_fp32);
+// The same workspace laid out inside caller-provided device memory [base, base + cap),
+// with a caller-owned pinned scalar mirror: allocates nothing.  Throws Error(PS_EINVAL)
+// when the workspace does not fit.
+void carve_krylov(Krylov &k, void *base, size_t cap, size_t N, int m, bool z_fp32, double *hostscal);
 
 // y = A x (FP64), or y = b - A x when b != nullptr; x of type TX.
 template <typename TX>

@@ -1441,6 +1441,21 @@ size_t krylov_bytes(size_t N, int m, bool z_fp32) {
     return used;
 }
 
+void carve_krylov(Krylov &K, void *base, size_t cap, size_t N, int m, bool z_fp32, double *hostscal) {
+    const size_t need = krylov_bytes(N, m, z_fp32);
+    if (need > cap)
+        throw Error(PS_EINVAL, "the Krylov workspace needs " + std::to_string(need) + " bytes; the static scratch holds " +
+                                   std::to_string(cap));
+    char *p = static_cast<char *>(base);
+    layout_krylov(K, N, m, z_fp32, [&](size_t bytes) {
+        void *q = p;
+        p += round256(bytes);
+        return q;
+    });
+    K.hostscal = hostscal;
+    K.own_hostscal = false;
+}
+
 // partial[...] <- chunk sums; rows = nv (+1 for |w|^2)
 static void launch_mdot(const Krylov &K, const double *V, int nv, const double *w, bool norm, hipStream_t st) {
     bool lds = K.chunk <= 7680;          // <= 60 KB of LDS per workgroup

@@ -63,6 +63,8 @@ _SIGS = {
     "ps_update_flow": (C.c_int, [C.c_void_p, _f64p, _f64p, _f64p, _f64p, _f64p]),
     "ps_setup": (C.c_int, [C.c_void_p]),
     "ps_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.POINTER(ps_result)]),
+    "ps_solve_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p,
+                                   C.POINTER(ps_result)]),
     "ps_apply_precond": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "ps_spmv": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "ps_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.POINTER(C.c_uint64)]),
@@ -225,6 +227,16 @@ def ps_solve(h, rhs, x, rtol, stream=None, raise_on_error=False):
     code = load().ps_solve(h, _ptr(rhs), _ptr(x), float(rtol), _stream(stream), C.byref(r))
     if raise_on_error and code != PS_OK:
         raise PsError(code, "ps_solve")
+    d = r.as_dict()
+    d["status"] = code
+    return d
+
+
+def ps_solve_noalloc(h, rhs, x, rtol, stream=None):
+    """ps_solve with the FGMRES workspace in the library's static device scratch (no
+    allocation); returns the ps_result as a dict (status included)."""
+    r = ps_result()
+    code = load().ps_solve_noalloc(h, _ptr(rhs), _ptr(x), float(rtol), _stream(stream), C.byref(r))
     d = r.as_dict()
     d["status"] = code
     return d
