@@ -222,56 +222,81 @@ def cpu_baseline(s, b, its_gpu, budget_s, args):
 SERVING_SIZES = (16, 24, 32, 48, 64)
 
 
-def _serving_field(job):
-    """One pooled field of the serving mix: grid n^3, its own seeded random field with
-    sigma ~ U(1, 3); E fixed per grid size so requests of one size share A_uu."""
-    n, k = job
+def _serving_request(job):
+    """Request i of the serving mix (synth.configs.serving_request: grid n^3 drawn from
+    16..64, its own seeded random field with sigma ~ U(1, 3), its own rhs; E fixed per grid
+    size so that requests of one size share A_uu).  Runs in a worker process; A_uu is
+    returned only for the first request of each size (the others take that copy), to keep
+    the stream in host memory."""
+    i, keep_auu = job
     import numpy as np
-    from synth import workload
+    from synth.configs import serving_request
     from synth.jacobian import box_partition
-    rng = np.random.Generator(np.random.PCG64(77_000 + 1000 * n + k))
-    s, _ = workload(grid=(n, n, n), kind="grf", seed=5000 + 1000 * n + k, rhs_seed=0,
-                    sigma=float(rng.uniform(1.0, 3.0)), e_seed=n)
+    s, b = serving_request(i)
+    n = s.meta["grid"][0]
     s.ml_part = box_partition(n, n, n, min(n, 32), min(n, 32), min(n, 16))
-    return s
+    if not keep_auu:
+        s.Auu = None
+    return i, n, s, np.asarray(b)
 
 
-def make_serving_pool(per_size, workers):
-    """Fields of the serving mix, generated in fresh processes before the GPU is used."""
+def make_serving_stream(nreq, workers):
+    """The request stream's systems, generated in fresh processes before the GPU is used."""
     import multiprocessing as mp
-    jobs = [(n, k) for n in SERVING_SIZES for k in range(per_size)]
-    with mp.get_context("spawn").Pool(min(workers, len(jobs))) as pool:
-        return dict(zip(jobs, pool.map(_serving_field, jobs)))
+    from synth.configs import serving_request_spec
+    first = {}
+    for i in range(nreq):
+        first.setdefault(serving_request_spec(i)[0], i)
+    jobs = [(i, first[serving_request_spec(i)[0]] == i) for i in range(nreq)]
+    # one BLAS thread per worker process (the workers already fill the cores)
+    saved = {v: os.environ.get(v) for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for v in saved:
+        os.environ[v] = "1"
+    try:
+        with mp.get_context("spawn").Pool(max(1, min(workers, nreq))) as pool:
+            out = pool.map(_serving_request, jobs, chunksize=1)
+    finally:
+        for v, old in saved.items():
+            if old is None:
+                os.environ.pop(v, None)
+            else:
+                os.environ[v] = old
+    auu = {n: s.Auu for i, n, s, _ in out if first[n] == i}
+    for _, n, s, _ in out:
+        s.Auu = auu[n]
+    return out
 
 
-def run_serving(args, pool):
+def run_serving(args, stream):
     """Mixed-size request stream against one context (continuous batching): each
     request is created, set up (flow stage), submitted and awaited by one of W client
     threads; latency runs from the request's arrival to its completion and includes
-    queueing, ps_create, ps_setup and the solve.  Capacity is measured closed-loop
-    first; then Poisson arrivals at 0.25, 0.5 and 0.9 of it."""
+    queueing, ps_create, ps_setup and the solve.  The stream is replayed closed-loop
+    first (capacity) and then with Poisson arrivals at 0.25, 0.5 and 0.9 of it."""
     import threading
     import numpy as np
     import torch
-    from synth.jacobian import make_rhs
     from paper_1812_05540_amd import ps
 
     ps.load()
     dev = torch.device("cuda:0")
     ctx = ps.ps_ctx_create(0, int(args.serving_budget_gb * 1e9))
-    opts = dict(precision=ps.PS_FP32_PREC, smoother=args.smoother_code, ml_kind=args.ml_kind_code)
-    # one resident handle per grid size keeps its mechanics hierarchy in HBM
-    keep = []
+    opts = dict(precision=ps.PS_FP32_PREC, smoother=args.smoother_code, ml_kind=args.ml_kind_code,
+                ml_sweeps=args.ml_sweeps)
+    # resident state per grid size: the mechanics hierarchy and set-up handles that the
+    # context keeps for the requests (released handles are reused by ps_create)
+    first = {}
+    for i, n, s, b in stream:
+        first.setdefault(n, s)
     for n in SERVING_SIZES:
-        sv = ps.Solver(ctx, pool[(n, 0)], mech_key=n, **opts)
-        sv.setup()
-        keep.append(sv)
+        if n not in first:
+            continue
+        warm = [ps.Solver(ctx, first[n], mech_key=n, **opts) for _ in range(min(args.serving_clients, 4))]
+        for sv in warm:
+            sv.setup()
+        for sv in warm:
+            sv.close()
     rng = np.random.Generator(np.random.PCG64(77))
-    per = max(1, len({k for (_, k) in pool}))
-
-    def request(i):
-        n = SERVING_SIZES[int(rng.integers(len(SERVING_SIZES)))]
-        return i, n, pool[(n, int(rng.integers(per)))]
 
     def serve(reqs, arrivals):
         lat, status, iters = [None] * len(reqs), [None] * len(reqs), [0] * len(reqs)
@@ -280,7 +305,7 @@ def run_serving(args, pool):
         t0 = time.perf_counter()
 
         def worker():
-            stream = torch.cuda.Stream()
+            stream_ = torch.cuda.Stream()
             while True:
                 with lock:
                     q = nxt[0]
@@ -290,14 +315,14 @@ def run_serving(args, pool):
                 wait = t0 + arrivals[q] - time.perf_counter()
                 if wait > 0:
                     time.sleep(wait)
-                i, n, s = reqs[q]
+                i, n, s, b = reqs[q]
                 try:
                     sv = ps.Solver(ctx, s, mech_key=n, **opts)
                     sv.setup()
-                    with torch.cuda.stream(stream):
-                        b = torch.as_tensor(make_rhs(s, 9000 + i), device=dev)
+                    with torch.cuda.stream(stream_):
+                        bd = torch.as_tensor(b, device=dev)
                         x = torch.zeros(s.N, dtype=torch.float64, device=dev)
-                    r = ps.ps_wait(ctx, sv.submit(b, x, args.rtol, stream))
+                    r = ps.ps_wait(ctx, sv.submit(bd, x, args.rtol, stream_))
                     sv.close()
                     status[q], iters[q] = r["status"], r["iterations"]
                     if r["status"] != ps.PS_OK:
@@ -319,27 +344,24 @@ def run_serving(args, pool):
         wall = time.perf_counter() - t0
         return np.array(lat), status, iters, wall
 
-    nreq = args.serving_requests
-    reqs = [request(i) for i in range(max(8, nreq // 2))]
-    _, st, _, wall = serve(reqs, [0.0] * len(reqs))
-    mu = len(reqs) / wall
+    nreq = len(stream)
+    _, st, _, wall = serve(stream, [0.0] * nreq)
+    mu = nreq / wall
     out = dict(capacity_rps=round(mu, 3), clients=args.serving_clients, requests_per_rate=nreq,
-               pool="%d pooled fields per grid size in %s^3, each request its own rhs" %
-                    (per, "/".join(str(n) for n in SERVING_SIZES)),
+               stream="%d requests, each its own seeded field (sigma U(1,3)) and rhs, grids drawn from %s^3; "
+                      "the same stream replayed closed-loop and at each arrival rate"
+                      % (nreq, "/".join(str(n) for n in SERVING_SIZES)),
                rates=[])
     for frac in (0.25, 0.5, 0.9):
-        reqs = [request(i) for i in range(nreq)]
         gaps = rng.exponential(1.0 / (frac * mu), nreq)
         arrivals = np.cumsum(gaps) - gaps[0]
-        lat, st, its, wall = serve(reqs, list(arrivals))
+        lat, st, its, wall = serve(stream, list(arrivals))
         ok = [l for l, c in zip(lat, st) if c == ps.PS_OK]
         out["rates"].append(dict(load=frac, rate_rps=round(frac * mu, 3), p50_s=round(float(np.percentile(lat, 50)), 4),
                                  p99_s=round(float(np.percentile(lat, 99)), 4), max_s=round(float(lat.max()), 4),
                                  solves_per_s=round(len(ok) / wall, 3), failed=len(lat) - len(ok),
                                  mean_iterations=round(float(np.mean(its)), 1)))
         log("serving", json.dumps(out["rates"][-1]))
-    for sv in keep:
-        sv.close()
     ps.ps_ctx_destroy(ctx)
     return out
 
@@ -360,9 +382,10 @@ def main():
                     help="processor-local local stage: subdomain box size in cells ('global': one domain)")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serving-requests", type=int, default=48,
-                    help="requests per arrival rate of the serving mix (0: skip)")
-    ap.add_argument("--serving-pool", type=int, default=2, help="pooled fields per grid size")
+    ap.add_argument("--serving-requests", type=int, default=64,
+                    help="requests of the serving stream, each with its own field (0: skip; 512: the full "
+                         "stream of the serving configuration)")
+    ap.add_argument("--serving-workers", type=int, default=16, help="processes generating the stream")
     ap.add_argument("--serving-clients", type=int, default=6)
     ap.add_argument("--serving-budget-gb", type=float, default=200.0)
     ap.add_argument("--cpu-budget-s", type=float, default=30.0)
@@ -382,13 +405,13 @@ def main():
         bx, by, bz = (int(v) for v in args.ml_part.split(","))
         s.ml_part = box_partition(*s.meta["grid"], bx, by, bz)
     log("workload %s: N=%d generated in %.1fs" % (args.workload, s.N, time.perf_counter() - t0))
-    pool = None
+    stream = None
     if args.serving_requests > 0:
         t0 = time.perf_counter()
-        pool = make_serving_pool(args.serving_pool, 12)
-        log("serving pool: %d fields in %.1fs" % (len(pool), time.perf_counter() - t0))
+        stream = make_serving_stream(args.serving_requests, args.serving_workers)
+        log("serving stream: %d requests generated in %.1fs" % (len(stream), time.perf_counter() - t0))
     g = run_gpu(args, s, b)
-    serving = run_serving(args, pool) if pool else None
+    serving = run_serving(args, stream) if stream else None
     head = g.get("fp32") or g.get("fp64")
     line = {
         "metric": "solves/s to rtol 1e-8 (FP64 vs FP32 precond), SpMV HBM GB/s, p50/p99 latency",

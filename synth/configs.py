@@ -159,10 +159,18 @@ def workload(name=None, grid=None, kind="iid", seed=1, rhs_seed=101, sigma=2.0, 
     return system, make_rhs(system, rhs_seed)
 
 
-def serving_request(i):
-    """Request i of the mixed-size serving stream (grid drawn from 16..64 cubed)."""
+def serving_request_spec(i):
+    """(n, sigma) of request i of the mixed-size serving stream: grid n^3 drawn uniformly
+    from 16, 24, 32, 48, 64 and the log-permeability sigma from U(1, 3)."""
     rng = _rng(77_000 + i)
     n = int(rng.choice([16, 24, 32, 48, 64]))
     sigma = float(rng.uniform(1.0, 3.0))
+    return n, sigma
+
+
+def serving_request(i):
+    """Request i of the mixed-size serving stream: its own field (seed 5000 + i) and rhs
+    (seed 9000 + i); E fixed per grid size (seed n), so requests of one size share A_uu."""
+    n, sigma = serving_request_spec(i)
     return workload(grid=(n, n, n), kind="grf", seed=5000 + i, rhs_seed=9000 + i,
                     sigma=sigma, e_seed=n)
