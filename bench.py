@@ -362,6 +362,8 @@ def run_serving(args, stream):
                                  solves_per_s=round(len(ok) / wall, 3), failed=len(lat) - len(ok),
                                  mean_iterations=round(float(np.mean(its)), 1)))
         log("serving", json.dumps(out["rates"][-1]))
+    launches, covered = ps.ps_ctx_batches(ctx)
+    out["batched_step1"] = dict(launch_sequences=launches, requests=covered)
     ps.ps_ctx_destroy(ctx)
     return out
 

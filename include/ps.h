@@ -209,6 +209,14 @@ int  ps_spmv(ps_handle *h, const double *x, double *y, void *stream);
  * Work already enqueued on `stream` (e.g. the copy that fills rhs) completes
  * before the request starts; NULL = legacy default stream. */
 int  ps_submit(ps_handle *h, const double *rhs, double *x, double rtol, void *stream, uint64_t *ticket);
+/* Step 1 of the admitted requests that share a mechanics hierarchy (same mech_key grid
+ * and precision) and are ready together runs as one batch: each V-cycle kernel is launched
+ * once for up to 8 requests (gridDim.y), reading the shared level operators once per
+ * request slice, with every slice computing what the request computes alone (results are
+ * bitwise those of a solo solve).  PS_SERVING_BATCH=0 in the environment turns it off.
+ * ps_ctx_batches reports, since ps_ctx_create, the batched step-1 launch sequences and the
+ * requests they covered (NULL to skip). */
+int  ps_ctx_batches(ps_ctx *ctx, uint64_t *launches, uint64_t *requests);
 /* PS_PENDING while running; the request's final status once done (result copied). */
 int  ps_poll(ps_ctx *ctx, uint64_t ticket, ps_result *res);
 /* Block until the request finishes; returns its status. */

@@ -1,4 +1,5 @@
 // C ABI of the solver (include/ps.h, include/ps_host.h) and the serving scheduler.
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <cstdio>
@@ -106,6 +107,8 @@ struct ps_ctx {
     size_t used = 0;
     bool stop = false;
     std::thread worker;
+    // batched step 1 (requests on one mechanics hierarchy in one sequence of launches)
+    std::atomic<uint64_t> batch_launches{0}, batch_requests{0};
     void scheduler();
 };
 
@@ -152,6 +155,13 @@ struct Prec64 : PrecFn {
     void operator()(const double *v, void *z, hipStream_t st) override {
         apply_precond<double>(*h->mech->d64, *h->fl64, h->w64, h->sys.n_nodes, v, (double *)z, st);
     }
+    bool can_split() const override { return true; }
+    const void *pre(const double *v, hipStream_t st) override {
+        return precond_pre<double>(h->w64, h->sys.n_nodes, v, st);
+    }
+    void post(const double *v, void *z, hipStream_t st) override {
+        precond_post<double>(*h->fl64, h->w64, h->sys.n_nodes, v, (double *)z, st);
+    }
 };
 
 struct Prec32 : PrecFn {
@@ -159,6 +169,13 @@ struct Prec32 : PrecFn {
     explicit Prec32(ps_handle *hh) : h(hh) {}
     void operator()(const double *v, void *z, hipStream_t st) override {
         apply_precond<float>(*h->mech->d32, *h->fl32, h->w32, h->sys.n_nodes, v, (float *)z, st);
+    }
+    bool can_split() const override { return true; }
+    const void *pre(const double *v, hipStream_t st) override {
+        return precond_pre<float>(h->w32, h->sys.n_nodes, v, st);
+    }
+    void post(const double *v, void *z, hipStream_t st) override {
+        precond_post<float>(*h->fl32, h->w32, h->sys.n_nodes, v, (float *)z, st);
     }
 };
 
@@ -174,6 +191,7 @@ struct Request {
     double t_submit = 0.0, t_start = 0.0;
     hipStream_t st = nullptr;
     hipEvent_t ready = nullptr;       // recorded on the caller's stream at submit
+    hipEvent_t mark = nullptr;        // orders the request's stream against a batched step 1
     std::unique_ptr<Krylov> K;
     std::unique_ptr<PrecFn> M;
     std::unique_ptr<Fgmres> run;
@@ -835,6 +853,15 @@ int ps_pressure_level(ps_handle *h, int lvl, int32_t *nlevels, int32_t *n, int32
     });
 }
 
+int ps_ctx_batches(ps_ctx *c, uint64_t *launches, uint64_t *requests) {
+    return guard([&] {
+        if (!c) throw Error(PS_EINVAL, "ctx is NULL");
+        if (launches) *launches = c->batch_launches.load();
+        if (requests) *requests = c->batch_requests.load();
+        return PS_OK;
+    });
+}
+
 int ps_wait(ps_ctx *c, uint64_t ticket, ps_result *res) {
     return guard([&] {
         if (!c) throw Error(PS_EINVAL, "ctx is NULL");
@@ -850,6 +877,21 @@ int ps_wait(ps_ctx *c, uint64_t ticket, ps_result *res) {
 // whenever their device footprint fits the budget, and finished ones leave at once.
 void ps_ctx::scheduler() {
     (void)hipSetDevice(device);
+    // step 1 of requests that share a mechanics hierarchy runs as one batch (gridDim.y = the
+    // requests) on this stream, ordered by events against each request's own stream
+    const bool batching = [] {
+        const char *e = std::getenv("PS_SERVING_BATCH");
+        return !(e && std::string(e) == "0");
+    }();
+    hipStream_t bst = nullptr;
+    hipEvent_t bev = nullptr;
+    if (batching) {
+        if (hipStreamCreateWithFlags(&bst, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&bev, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            bst = nullptr;
+        }
+    }
     auto finish = [this](Request *r, int status, const SolveOut *o) {
         r->res.status = status;
         if (o) {
@@ -866,6 +908,8 @@ void ps_ctx::scheduler() {
         r->st = nullptr;
         if (r->ready) (void)hipEventDestroy(r->ready);
         r->ready = nullptr;
+        if (r->mark) (void)hipEventDestroy(r->mark);
+        r->mark = nullptr;
         r->run.reset();
         r->M.reset();
         r->K.reset();
@@ -881,6 +925,10 @@ void ps_ctx::scheduler() {
             std::unique_lock<std::mutex> lk(mu);
             cv.wait(lk, [&] { return stop || !queue.empty() || !active.empty(); });
             if (stop && active.empty()) {
+                if (bev) (void)hipEventDestroy(bev);
+                if (bst) (void)hipStreamDestroy(bst);
+                bev = nullptr;
+                bst = nullptr;
                 for (Request *r : queue) {
                     r->status = PS_EBUSY;
                     r->res.status = PS_EBUSY;
@@ -905,6 +953,7 @@ void ps_ctx::scheduler() {
                 bool f32 = use_fp32(r->h);
                 PS_HIP(hipStreamCreateWithFlags(&r->st, hipStreamNonBlocking));
                 PS_HIP(hipStreamWaitEvent(r->st, r->ready, 0));
+                PS_HIP(hipEventCreateWithFlags(&r->mark, hipEventDisableTiming));
                 r->K = std::make_unique<Krylov>();
                 alloc_krylov(*r->K, r->h->sys.N(), r->h->opt.restart, f32);
                 if (f32) r->M = std::make_unique<Prec32>(r->h);
@@ -923,6 +972,7 @@ void ps_ctx::scheduler() {
         // is not held to the pace of a large one.  When nothing was ready the loop waits a
         // few microseconds (or for a new submission) instead of spinning.
         std::vector<Request *> still;
+        std::vector<Request *> step1;          // ready requests whose next iteration waits for step 1
         bool progressed = false;
         for (Request *r : active) {
             const hipError_t q = hipStreamQuery(r->st);
@@ -934,7 +984,9 @@ void ps_ctx::scheduler() {
             bool more = false;
             int code = guard([&] {
                 if (q != hipSuccess) PS_HIP(q);
+                r->run->set_defer(bst != nullptr);
                 more = r->run->advance();
+                if (more && r->run->step1_pending()) step1.push_back(r);
                 return PS_OK;
             });
             if (code != PS_OK) {
@@ -945,6 +997,70 @@ void ps_ctx::scheduler() {
                 finish(r, o.status, &o);
             } else {
                 still.push_back(r);
+            }
+        }
+        // step 1 of the deferred iterations: requests on one mechanics hierarchy (same grid and
+        // precision) in batches of up to kBatchMax, each slice computing what it would alone
+        std::vector<bool> done(step1.size(), false);
+        for (size_t a = 0; a < step1.size(); ++a) {
+            if (done[a]) continue;
+            const bool f32 = use_fp32(step1[a]->h);
+            const void *hier = f32 ? (const void *)step1[a]->h->mech->d32.get()
+                                   : (const void *)step1[a]->h->mech->d64.get();
+            std::vector<Request *> grp;
+            for (size_t c = a; c < step1.size() && (int)grp.size() < kBatchMax; ++c) {
+                if (done[c] || use_fp32(step1[c]->h) != f32) continue;
+                const void *hc = f32 ? (const void *)step1[c]->h->mech->d32.get()
+                                     : (const void *)step1[c]->h->mech->d64.get();
+                if (hc != hier) continue;
+                grp.push_back(step1[c]);
+                done[c] = true;
+            }
+            int code = guard([&] {
+                const int nb = (int)grp.size();
+                if (nb > 1) {
+                    for (Request *r : grp) {
+                        PS_HIP(hipEventRecord(r->mark, r->st));
+                        PS_HIP(hipStreamWaitEvent(bst, r->mark, 0));
+                    }
+                }
+                hipStream_t s1 = nb > 1 ? bst : grp[0]->st;
+                if (f32) {
+                    PrecWork<float> *w[kBatchMax];
+                    const float *vu[kBatchMax];
+                    float *zu[kBatchMax];
+                    for (int i = 0; i < nb; ++i) {
+                        w[i] = &grp[i]->h->w32;
+                        vu[i] = (const float *)grp[i]->run->step1_rhs();
+                        zu[i] = (float *)grp[i]->run->step1_out();
+                    }
+                    step1_batch<float>(*grp[0]->h->mech->d32, w, vu, zu, nb, s1);
+                } else {
+                    PrecWork<double> *w[kBatchMax];
+                    const double *vu[kBatchMax];
+                    double *zu[kBatchMax];
+                    for (int i = 0; i < nb; ++i) {
+                        w[i] = &grp[i]->h->w64;
+                        vu[i] = (const double *)grp[i]->run->step1_rhs();
+                        zu[i] = (double *)grp[i]->run->step1_out();
+                    }
+                    step1_batch<double>(*grp[0]->h->mech->d64, w, vu, zu, nb, s1);
+                }
+                if (nb > 1) {
+                    PS_HIP(hipEventRecord(bev, bst));
+                    for (Request *r : grp) PS_HIP(hipStreamWaitEvent(r->st, bev, 0));
+                    batch_launches += 1;
+                    batch_requests += nb;
+                }
+                for (Request *r : grp) r->run->finish_iteration();
+                return PS_OK;
+            });
+            if (code != PS_OK) {
+                // the group's requests end with the error; they leave the active set
+                for (Request *r : grp) {
+                    still.erase(std::remove(still.begin(), still.end(), r), still.end());
+                    finish(r, code, nullptr);
+                }
             }
         }
         active.swap(still);

@@ -380,6 +380,19 @@ void spmv_full(const DSystem &S, const TX *x, const double *b, double *y, hipStr
 template <typename T>
 void apply_precond(const DHierarchy<T> &sdc, const DFlow<T> &fl, PrecWork<T> &w, int n_nodes,
                    const double *v, T *z, hipStream_t st);
+// The same in three parts, so that step 1 of several solves sharing one mechanics hierarchy
+// can run as one batch: precond_pre returns step 1's right-hand side (v_u in T), step 1 writes
+// z_u = z[0 .. 3 n_nodes), precond_post runs steps 2-8.
+template <typename T>
+const T *precond_pre(PrecWork<T> &w, int n_nodes, const double *v, hipStream_t st);
+template <typename T>
+void precond_post(const DFlow<T> &fl, PrecWork<T> &w, int n_nodes, const double *v, T *z, hipStream_t st);
+constexpr int kBatchMax = 8;       // solves in one batched step 1
+// Step 1 (one V-cycle of the shared hierarchy) for nb <= kBatchMax solves in one sequence of launches:
+// w[i], vu[i], zu[i] of solve i.  Each solve's z_u is bitwise what apply_precond computes.
+template <typename T>
+void step1_batch(const DHierarchy<T> &sdc, PrecWork<T> *const *w, const T *const *vu, T *const *zu, int nb,
+                 hipStream_t st);
 
 struct SolveOut {
     int status = PS_OK, iterations = 0, restarts = 0;
@@ -389,6 +402,11 @@ struct SolveOut {
 // Preconditioner callback: z (double or float, per Krylov::z_fp32) = M^{-1} v.
 struct PrecFn {
     virtual void operator()(const double *v, void *z, hipStream_t st) = 0;
+    // The application in parts around step 1 (precond_pre / precond_post), for callers that
+    // run step 1 of several solves together; can_split() = false: whole applications only.
+    virtual bool can_split() const { return false; }
+    virtual const void *pre(const double *v, hipStream_t st) { return nullptr; }
+    virtual void post(const double *v, void *z, hipStream_t st) {}
     virtual ~PrecFn() = default;
 };
 
@@ -405,13 +423,27 @@ class Fgmres {
     void start();
     bool advance();
     SolveOut out;
+    // With defer set (and a splittable preconditioner), an iteration that advance() starts
+    // stops before step 1: step1_pending() is then true, step1_rhs() / step1_out() are step
+    // 1's operands (in the preconditioner's type), and after the caller has enqueued step 1
+    // -- ordered after this solve's stream and before its next work -- finish_iteration()
+    // enqueues the rest of the iteration on the solve's stream.
+    void set_defer(bool d) { defer_ = d; }
+    bool step1_pending() const { return pending_; }
+    const void *step1_rhs() const { return s1_rhs_; }
+    void *step1_out() const { return s1_z_; }
+    void finish_iteration();
 
   private:
     enum Phase { START, ITER, CYCLE_END, DONE };
     void copy_scal();
     void begin_cycle(const double *r);
     void enqueue_iteration();
+    void rest_of_iteration();
     void end_cycle(int k);
+    bool defer_ = false, pending_ = false;
+    const void *s1_rhs_ = nullptr;
+    void *s1_z_ = nullptr;
     const DSystem &S_;
     Krylov &K_;
     PrecFn &M_;

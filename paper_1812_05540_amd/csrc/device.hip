@@ -1115,11 +1115,46 @@ static void with_G(int G, F &&f) {
     }
 }
 
+#define LAUNCHB(kernel, grid, nb, shm, st, ...)                                          \
+    do {                                                                                 \
+        if ((grid) > 0) hipLaunchKernelGGL(kernel, dim3(grid, nb), dim3(WG), shm, st, __VA_ARGS__); \
+    } while (0)
+
+// The solves whose V-cycles run in one sequence of launches on a shared hierarchy: their
+// per-level work vectors.  A single solve is a batch of one.
+template <typename T>
+struct VBatch {
+    int k = 1;
+    HierWork<T> *W[k::MAXB] = {};
+};
+
+template <typename T>
+static k::VP<T> one(T *p) {
+    k::VP<T> v{};
+    v.p[0] = p;
+    return v;
+}
+
+// level l's vector `field` of every solve of the batch
+template <typename T>
+static k::VP<T> level_vec(const VBatch<T> &B, std::vector<T *> HierWork<T>::*field, int l) {
+    k::VP<T> v{};
+    for (int i = 0; i < B.k; ++i) v.p[i] = (B.W[i]->*field)[l];
+    return v;
+}
+
+template <typename T>
+static k::VP<const T> cvp(const k::VP<T> &v) {
+    k::VP<const T> c{};
+    for (int i = 0; i < k::MAXB; ++i) c.p[i] = v.p[i];
+    return c;
+}
+
 template <int MODE, typename T>
-static void csr_spmv(const DCsr<T> &A, const T *x, const T *b, T *y, hipStream_t st) {
+static void csr_spmv(const DCsr<T> &A, k::VP<const T> x, k::VP<const T> b, k::VP<T> y, int nb, hipStream_t st) {
     with_G(A.G, [&](auto Gc) {
         constexpr int G = decltype(Gc)::value;
-        LAUNCH((k::csr_spmv<G, MODE, T>), grid_for((size_t)A.n * k::lanes_of<G>()), 0, st, A, x, b, y);
+        LAUNCHB((k::csr_spmv<G, MODE, T>), grid_for((size_t)A.n * k::lanes_of<G>()), nb, 0, st, A, x, b, y);
     });
 }
 
@@ -1133,18 +1168,25 @@ static double op_bytes(const DCsr<T> &A, double vecs_rows, double vecs_cols = 0.
            vecs_cols * ncols * sizeof(T);
 }
 
+// One V(1,1)-cycle from level l for every solve of the batch B (right-hand sides b, results
+// out): each launch covers the batch (gridDim.y = B.k), reading the level's operator once
+// per slice and computing every slice with the single-solve arithmetic.
 template <typename T>
-static void vcycle(const DHierarchy<T> &H, HierWork<T> &W, int l, const T *b, T *out, hipStream_t st) {
+static void vcycle(const DHierarchy<T> &H, const VBatch<T> &B, int l, k::VP<const T> b, k::VP<T> out,
+                   hipStream_t st) {
+    const int nb = B.k;
     const int last = (int)H.lev.size() - 1;
     if (l == last) {
         unsigned g = (unsigned)((H.cn + (WG / 64) - 1) / (WG / 64));
-        LAUNCH(k::coarse_solve<T>, g, 0, st, H.cinv, H.cn, b, out);
+        LAUNCHB(k::coarse_solve<T>, g, nb, 0, st, H.cinv, H.cn, b, out);
         return;
     }
     const DLevel<T> &L = H.lev[l];
     const bool cheb = H.smoother == PS_CHEB2;
-    // level 0 is timed when kernel timing is on (ktag: the hierarchy's first phase id)
-    const int tag = l == 0 ? H.ktag : -1;
+    const k::VP<T> x = level_vec(B, &HierWork<T>::x, l), r = level_vec(B, &HierWork<T>::r, l);
+    // level 0 of a single solve is timed when kernel timing is on (ktag: the hierarchy's
+    // first phase id)
+    const int tag = l == 0 && nb == 1 ? H.ktag : -1;
     auto scope = [&](std::optional<ktime::Scope> &o, int phase, double bytes) {
         if (tag >= 0 && ktime::enabled()) o.emplace(tag + phase, st, bytes);
     };
@@ -1154,38 +1196,40 @@ static void vcycle(const DHierarchy<T> &H, HierWork<T> &W, int l, const T *b, T 
         // gathered, c1, cm in, x out) and the residual (x, b in, r out)
         std::optional<ktime::Scope> ts;
         scope(ts, 0, cheb ? op_bytes(L.A, 5) + op_bytes(L.A, 3) : op_bytes(L.A, l > 0 ? 3 : 4));
-    with_G(L.A.G, [&](auto Gc) {
-        constexpr int G = decltype(Gc)::value;
-        unsigned g = grid_for((size_t)L.n * k::lanes_of<G>());
-        if (cheb) {
-            LAUNCH((k::csr_cheb_pre<G, T>), g, 0, st, L.A, b, L.c0, L.c1, L.cm, W.x[l]);
-            LAUNCH((k::csr_spmv<G, 1, T>), g, 0, st, L.A, (const T *)W.x[l], b, W.r[l]);
-        } else if (l > 0) {                 // x = D^-1 b was written with b by the restriction
-            LAUNCH((k::csr_spmv<G, 1, T>), g, 0, st, L.A, (const T *)W.x[l], b, W.r[l]);
-        } else {
-            LAUNCH((k::csr_l1_pre<G, T>), g, 0, st, L.A, b, L.dinv, W.x[l], W.r[l]);
-        }
-    });
+        with_G(L.A.G, [&](auto Gc) {
+            constexpr int G = decltype(Gc)::value;
+            unsigned g = grid_for((size_t)L.n * k::lanes_of<G>());
+            if (cheb) {
+                LAUNCHB((k::csr_cheb_pre<G, T>), g, nb, 0, st, L.A, b, L.c0, L.c1, L.cm, x);
+                LAUNCHB((k::csr_spmv<G, 1, T>), g, nb, 0, st, L.A, cvp(x), b, r);
+            } else if (l > 0) {                 // x = D^-1 b was written with b by the restriction
+                LAUNCHB((k::csr_spmv<G, 1, T>), g, nb, 0, st, L.A, cvp(x), b, r);
+            } else {
+                LAUNCHB((k::csr_l1_pre<G, T>), g, nb, 0, st, L.A, b, L.dinv, x, r);
+            }
+        });
     }
+    const k::VP<T> bc = level_vec(B, &HierWork<T>::b, l + 1), ec = level_vec(B, &HierWork<T>::e, l + 1);
     if (!cheb && l + 1 < last) {
         // R r (r gathered) with the coarse level's D^-1 in, b and x = D^-1 b out
         std::optional<ktime::Scope> ts;
         scope(ts, 1, op_bytes(L.R, 3, 1, L.n));
+        const k::VP<T> xc = level_vec(B, &HierWork<T>::x, l + 1);
         with_G(L.R.G, [&](auto Gc) {
             constexpr int G = decltype(Gc)::value;
-            LAUNCH((k::csr_restrict_l1<G, T>), grid_for((size_t)L.R.n * k::lanes_of<G>()), 0, st, L.R,
-                   (const T *)W.r[l], H.lev[l + 1].dinv, W.b[l + 1], W.x[l + 1]);
+            LAUNCHB((k::csr_restrict_l1<G, T>), grid_for((size_t)L.R.n * k::lanes_of<G>()), nb, 0, st, L.R, cvp(r),
+                    H.lev[l + 1].dinv, bc, xc);
         });
     } else {
         std::optional<ktime::Scope> ts;
         scope(ts, 1, op_bytes(L.R, 1, 1, L.n));
-        csr_spmv<0, T>(L.R, (const T *)W.r[l], (const T *)nullptr, W.b[l + 1], st);
+        csr_spmv<0, T>(L.R, cvp(r), k::VP<const T>{}, bc, nb, st);
     }
-    vcycle(H, W, l + 1, W.b[l + 1], W.e[l + 1], st);
+    vcycle(H, B, l + 1, cvp(bc), ec, st);
     {
         std::optional<ktime::Scope> ts;
         scope(ts, 2, op_bytes(L.P, 2, 1, nc));             // e (gathered) in, x read and written
-        csr_spmv<2, T>(L.P, (const T *)W.e[l + 1], (const T *)nullptr, W.x[l], st);
+        csr_spmv<2, T>(L.P, cvp(ec), k::VP<const T>{}, x, nb, st);
     }
     // l1-Jacobi: b, x (gathered), D^-1 in, out written; Chebyshev: two sweeps (x, b, c0 in,
     // x1, d0 out; x1, b, d0, c1, cm in, out written)
@@ -1195,13 +1239,20 @@ static void vcycle(const DHierarchy<T> &H, HierWork<T> &W, int l, const T *b, T 
         constexpr int G = decltype(Gc)::value;
         unsigned g = grid_for((size_t)L.n * k::lanes_of<G>());
         if (cheb) {
-            LAUNCH((k::csr_cheb_post1<G, T>), g, 0, st, L.A, b, (const T *)W.x[l], L.c0, W.x1[l], W.d[l]);
-            LAUNCH((k::csr_cheb_post2<G, T>), g, 0, st, L.A, b, (const T *)W.x1[l], (const T *)W.d[l], L.c1,
-                   L.cm, out);
+            const k::VP<T> x1 = level_vec(B, &HierWork<T>::x1, l), d = level_vec(B, &HierWork<T>::d, l);
+            LAUNCHB((k::csr_cheb_post1<G, T>), g, nb, 0, st, L.A, b, cvp(x), L.c0, x1, d);
+            LAUNCHB((k::csr_cheb_post2<G, T>), g, nb, 0, st, L.A, b, cvp(x1), cvp(d), L.c1, L.cm, out);
         } else {
-            LAUNCH((k::csr_l1_post<G, T>), g, 0, st, L.A, b, (const T *)W.x[l], L.dinv, out);
+            LAUNCHB((k::csr_l1_post<G, T>), g, nb, 0, st, L.A, b, cvp(x), L.dinv, out);
         }
     });
+}
+
+template <typename T>
+static void vcycle(const DHierarchy<T> &H, HierWork<T> &W, int l, const T *b, T *out, hipStream_t st) {
+    VBatch<T> B;
+    B.W[0] = &W;
+    vcycle(H, B, l, one(b), one(out), st);
 }
 
 // ------------------------------------------------------------------ Algorithm 1
@@ -1351,20 +1402,47 @@ static void flow_stage(const DFlow<T> &fl, PrecWork<T> &w, const double *vf, con
 }
 
 template <typename T>
-void apply_precond(const DHierarchy<T> &sdc, const DFlow<T> &fl, PrecWork<T> &w, int n_nodes,
-                   const double *v, T *z, hipStream_t st) {
+const T *precond_pre(PrecWork<T> &w, int n_nodes, const double *v, hipStream_t st) {
     size_t nu = (size_t)3 * n_nodes;
-    const T *vu;
     if constexpr (sizeof(T) == 4) {
         LAUNCH((k::convert<double, T>), grid_for(nu), 0, st, v, w.vconv, nu);
-        vu = w.vconv;
+        return w.vconv;
     } else {
-        vu = reinterpret_cast<const T *>(v);
+        return reinterpret_cast<const T *>(v);
     }
-    T *zu = z, *zf = z + nu;
-    vcycle(sdc, w.sdc, 0, vu, zu, st);                                                 // step 1
-    if (fl.nf == 2) flow_stage<2, T>(fl, w, v + nu, zu, zf, st);
-    else flow_stage<3, T>(fl, w, v + nu, zu, zf, st);
+}
+
+template <typename T>
+void precond_post(const DFlow<T> &fl, PrecWork<T> &w, int n_nodes, const double *v, T *z, hipStream_t st) {
+    size_t nu = (size_t)3 * n_nodes;
+    if (fl.nf == 2) flow_stage<2, T>(fl, w, v + nu, z, z + nu, st);
+    else flow_stage<3, T>(fl, w, v + nu, z, z + nu, st);
+}
+
+template <typename T>
+void apply_precond(const DHierarchy<T> &sdc, const DFlow<T> &fl, PrecWork<T> &w, int n_nodes,
+                   const double *v, T *z, hipStream_t st) {
+    const T *vu = precond_pre(w, n_nodes, v, st);
+    vcycle(sdc, w.sdc, 0, vu, z, st);                                                  // step 1
+    precond_post(fl, w, n_nodes, v, z, st);                                            // steps 2-8
+}
+
+static_assert(kBatchMax == k::MAXB, "batch bound of the V-cycle kernels");
+
+template <typename T>
+void step1_batch(const DHierarchy<T> &sdc, PrecWork<T> *const *w, const T *const *vu, T *const *zu, int nb,
+                 hipStream_t st) {
+    if (nb < 1 || nb > k::MAXB) throw Error(PS_EINVAL, "batch size");
+    VBatch<T> B;
+    B.k = nb;
+    k::VP<const T> b{};
+    k::VP<T> out{};
+    for (int i = 0; i < nb; ++i) {
+        B.W[i] = &w[i]->sdc;
+        b.p[i] = vu[i];
+        out.p[i] = zu[i];
+    }
+    vcycle(sdc, B, 0, b, out, st);
 }
 
 // ------------------------------------------------------------------ system SpMV
@@ -1511,13 +1589,34 @@ void Fgmres::begin_cycle(const double *r) {
 }
 
 void Fgmres::enqueue_iteration() {
+    const size_t N = K_.N;
+    double *Vj = K_.V + (size_t)j_ * N;
+    size_t esz = K_.z_fp32 ? sizeof(float) : sizeof(double);
+    void *zj = (char *)K_.Z + (size_t)j_ * N * esz;
+    if (defer_ && M_.can_split()) {                                     // step 1 by the caller
+        s1_rhs_ = M_.pre(Vj, st_);
+        s1_z_ = zj;
+        pending_ = true;
+        return;
+    }
+    M_(Vj, zj, st_);                                                    // z_j = M^{-1} v_j
+    rest_of_iteration();
+}
+
+void Fgmres::finish_iteration() {
+    if (!pending_) return;
+    const size_t N = K_.N;
+    M_.post(K_.V + (size_t)j_ * N, s1_z_, st_);                         // steps 2-8
+    pending_ = false;
+    rest_of_iteration();
+}
+
+void Fgmres::rest_of_iteration() {
     const int j = j_, m = K_.m, nv = j + 1;
     const size_t N = K_.N;
-    double *Vj = K_.V + (size_t)j * N;
     double *w = K_.V + (size_t)(j + 1) * N;
     size_t esz = K_.z_fp32 ? sizeof(float) : sizeof(double);
     void *zj = (char *)K_.Z + (size_t)j * N * esz;
-    M_(Vj, zj, st_);                                                    // z_j = M^{-1} v_j
     if (K_.z_fp32) spmv_full<float>(S_, (const float *)zj, nullptr, w, st_);   // w = A z_j
     else spmv_full<double>(S_, (const double *)zj, nullptr, w, st_);
     // CGS2: h1 = V^T w (+ |w|^2), w -= V h1, h2 = V^T w, w -= V h2, h = h1 + h2, |w|^2
@@ -1768,6 +1867,16 @@ template void apply_precond<double>(const DHierarchy<double> &, const DFlow<doub
                                     const double *, double *, hipStream_t);
 template void apply_precond<float>(const DHierarchy<float> &, const DFlow<float> &, PrecWork<float> &, int,
                                    const double *, float *, hipStream_t);
+template const double *precond_pre<double>(PrecWork<double> &, int, const double *, hipStream_t);
+template const float *precond_pre<float>(PrecWork<float> &, int, const double *, hipStream_t);
+template void precond_post<double>(const DFlow<double> &, PrecWork<double> &, int, const double *, double *,
+                                   hipStream_t);
+template void precond_post<float>(const DFlow<float> &, PrecWork<float> &, int, const double *, float *,
+                                  hipStream_t);
+template void step1_batch<double>(const DHierarchy<double> &, PrecWork<double> *const *, const double *const *,
+                                  double *const *, int, hipStream_t);
+template void step1_batch<float>(const DHierarchy<float> &, PrecWork<float> *const *, const float *const *,
+                                 float *const *, int, hipStream_t);
 template void spmv_full<double>(const DSystem &, const double *, const double *, double *, hipStream_t);
 template void spmv_full<float>(const DSystem &, const float *, const double *, double *, hipStream_t);
 

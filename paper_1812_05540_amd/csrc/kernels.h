@@ -218,10 +218,22 @@ __global__ __launch_bounds__(WG) void l1_post(Sell<T> A, const T *__restrict__ b
     out[i] = x[i] + r * dinv[i];
 }
 
+// The vectors of up to MAXB solves that share one hierarchy's operators: a V-cycle kernel
+// launched with gridDim.y = k applies the same operator to the vectors p[0..k-1], slice
+// blockIdx.y taking p[blockIdx.y] (serving batches several requests of one grid this way;
+// a single solve is a batch of one).  Every slice runs the single-vector arithmetic.
+constexpr int MAXB = 8;
+template <typename T>
+struct VP {
+    T *p[MAXB];
+};
+
 // Coarsest level: x = A_c^{-1} b with the FP64 dense inverse; one wavefront per row.
 template <typename T>
-__global__ __launch_bounds__(WG) void coarse_solve(const double *__restrict__ Ainv, int n,
-                                                  const T *__restrict__ b, T *__restrict__ x) {
+__global__ __launch_bounds__(WG) void coarse_solve(const double *__restrict__ Ainv, int n, VP<const T> bv,
+                                                  VP<T> xv) {
+    const T *__restrict__ b = bv.p[blockIdx.y];
+    T *__restrict__ x = xv.p[blockIdx.y];
     int row = blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
     int lane = threadIdx.x & 63;
     if (row >= n) return;                      // whole wavefront leaves together
@@ -351,8 +363,10 @@ __device__ __forceinline__ T csr_dot(const DCsr<T> &A, int i, int g, const T *__
 
 // y = A x (0), b - A x (1), y + A x (2)
 template <int G, int MODE, typename T>
-__global__ __launch_bounds__(WG) void csr_spmv(DCsr<T> A, const T *__restrict__ x, const T *__restrict__ b,
-                                              T *__restrict__ y) {
+__global__ __launch_bounds__(WG) void csr_spmv(DCsr<T> A, VP<const T> xv, VP<const T> bv, VP<T> yv) {
+    const T *__restrict__ x = xv.p[blockIdx.y];
+    const T *__restrict__ b = bv.p[blockIdx.y];
+    T *__restrict__ y = yv.p[blockIdx.y];
     PS_CSR_ROW(G)
     T a = csr_dot<G, false>(A, i, g, x, x);
     if (g == 0) y[i] = MODE == 0 ? a : MODE == 1 ? b[i] - a : y[i] + a;
@@ -361,9 +375,11 @@ __global__ __launch_bounds__(WG) void csr_spmv(DCsr<T> A, const T *__restrict__ 
 // Restriction to a level below which the V-cycle goes on (l1-Jacobi): b = R r, and that
 // level's first smoothing step x = D^-1 b, so its pre-smoother gathers one vector.
 template <int G, typename T>
-__global__ __launch_bounds__(WG) void csr_restrict_l1(DCsr<T> A, const T *__restrict__ r,
-                                                     const T *__restrict__ dinv, T *__restrict__ b,
-                                                     T *__restrict__ x) {
+__global__ __launch_bounds__(WG) void csr_restrict_l1(DCsr<T> A, VP<const T> rv, const T *__restrict__ dinv,
+                                                     VP<T> bv, VP<T> xv) {
+    const T *__restrict__ r = rv.p[blockIdx.y];
+    T *__restrict__ b = bv.p[blockIdx.y];
+    T *__restrict__ x = xv.p[blockIdx.y];
     PS_CSR_ROW(G)
     T a = csr_dot<G, false>(A, i, g, r, r);
     if (g == 0) {
@@ -373,8 +389,11 @@ __global__ __launch_bounds__(WG) void csr_restrict_l1(DCsr<T> A, const T *__rest
 }
 
 template <int G, typename T>
-__global__ __launch_bounds__(WG) void csr_l1_pre(DCsr<T> A, const T *__restrict__ b, const T *__restrict__ dinv,
-                                                T *__restrict__ x, T *__restrict__ r) {
+__global__ __launch_bounds__(WG) void csr_l1_pre(DCsr<T> A, VP<const T> bv, const T *__restrict__ dinv,
+                                                VP<T> xv, VP<T> rv) {
+    const T *__restrict__ b = bv.p[blockIdx.y];
+    T *__restrict__ x = xv.p[blockIdx.y];
+    T *__restrict__ r = rv.p[blockIdx.y];
     PS_CSR_ROW(G)
     T a = csr_dot<G, true>(A, i, g, b, dinv);
     if (g == 0) {
@@ -385,9 +404,10 @@ __global__ __launch_bounds__(WG) void csr_l1_pre(DCsr<T> A, const T *__restrict_
 }
 
 template <int G, typename T>
-__global__ __launch_bounds__(WG) void csr_cheb_pre(DCsr<T> A, const T *__restrict__ b, const T *__restrict__ c0,
-                                                  const T *__restrict__ c1, const T *__restrict__ cm,
-                                                  T *__restrict__ x) {
+__global__ __launch_bounds__(WG) void csr_cheb_pre(DCsr<T> A, VP<const T> bv, const T *__restrict__ c0,
+                                                  const T *__restrict__ c1, const T *__restrict__ cm, VP<T> xv) {
+    const T *__restrict__ b = bv.p[blockIdx.y];
+    T *__restrict__ x = xv.p[blockIdx.y];
     PS_CSR_ROW(G)
     T a = csr_dot<G, true>(A, i, g, b, c0);
     if (g == 0) {
@@ -398,9 +418,12 @@ __global__ __launch_bounds__(WG) void csr_cheb_pre(DCsr<T> A, const T *__restric
 }
 
 template <int G, typename T>
-__global__ __launch_bounds__(WG) void csr_cheb_post1(DCsr<T> A, const T *__restrict__ b, const T *__restrict__ x,
-                                                    const T *__restrict__ c0, T *__restrict__ x1,
-                                                    T *__restrict__ d0) {
+__global__ __launch_bounds__(WG) void csr_cheb_post1(DCsr<T> A, VP<const T> bv, VP<const T> xv,
+                                                    const T *__restrict__ c0, VP<T> x1v, VP<T> d0v) {
+    const T *__restrict__ b = bv.p[blockIdx.y];
+    const T *__restrict__ x = xv.p[blockIdx.y];
+    T *__restrict__ x1 = x1v.p[blockIdx.y];
+    T *__restrict__ d0 = d0v.p[blockIdx.y];
     PS_CSR_ROW(G)
     T a = csr_dot<G, false>(A, i, g, x, x);
     if (g == 0) {
@@ -411,17 +434,24 @@ __global__ __launch_bounds__(WG) void csr_cheb_post1(DCsr<T> A, const T *__restr
 }
 
 template <int G, typename T>
-__global__ __launch_bounds__(WG) void csr_cheb_post2(DCsr<T> A, const T *__restrict__ b, const T *__restrict__ x1,
-                                                    const T *__restrict__ d0, const T *__restrict__ c1,
-                                                    const T *__restrict__ cm, T *__restrict__ out) {
+__global__ __launch_bounds__(WG) void csr_cheb_post2(DCsr<T> A, VP<const T> bv, VP<const T> x1v, VP<const T> d0v,
+                                                    const T *__restrict__ c1, const T *__restrict__ cm,
+                                                    VP<T> outv) {
+    const T *__restrict__ b = bv.p[blockIdx.y];
+    const T *__restrict__ x1 = x1v.p[blockIdx.y];
+    const T *__restrict__ d0 = d0v.p[blockIdx.y];
+    T *__restrict__ out = outv.p[blockIdx.y];
     PS_CSR_ROW(G)
     T a = csr_dot<G, false>(A, i, g, x1, x1);
     if (g == 0) out[i] = x1[i] + (cm[i] * d0[i] + c1[i] * (b[i] - a));
 }
 
 template <int G, typename T>
-__global__ __launch_bounds__(WG) void csr_l1_post(DCsr<T> A, const T *__restrict__ b, const T *__restrict__ x,
-                                                 const T *__restrict__ dinv, T *__restrict__ out) {
+__global__ __launch_bounds__(WG) void csr_l1_post(DCsr<T> A, VP<const T> bv, VP<const T> xv,
+                                                 const T *__restrict__ dinv, VP<T> outv) {
+    const T *__restrict__ b = bv.p[blockIdx.y];
+    const T *__restrict__ x = xv.p[blockIdx.y];
+    T *__restrict__ out = outv.p[blockIdx.y];
     PS_CSR_ROW(G)
     T a = csr_dot<G, false, T, true>(A, i, g, x, x);
     if (g == 0) out[i] = x[i] + (b[i] - a) * dinv[i];

@@ -70,6 +70,7 @@ _SIGS = {
     "ps_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.POINTER(C.c_uint64)]),
     "ps_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(ps_result)]),
     "ps_wait": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(ps_result)]),
+    "ps_ctx_batches": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
     "ps_footprint": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
     "ps_kernel_timing": (C.c_int, [C.c_int]),
     "ps_kernel_stats": (C.c_int, [C.c_int, C.c_char_p, C.c_size_t, C.POINTER(C.c_int64), C.POINTER(C.c_double),
@@ -270,6 +271,13 @@ def ps_wait(ctx, ticket):
     d = r.as_dict()
     d["status"] = code
     return d
+
+
+def ps_ctx_batches(ctx):
+    """(batched step-1 launch sequences, requests they covered) since ps_ctx_create."""
+    a, b = C.c_uint64(), C.c_uint64()
+    _check(load().ps_ctx_batches(ctx, C.byref(a), C.byref(b)), "ps_ctx_batches")
+    return a.value, b.value
 
 
 def ps_kernel_timing(enable):

@@ -85,11 +85,15 @@ def run_mix(ctx, reqs, **opts):
 
 @pytest.mark.parametrize("precision", [ps.PS_FP64, ps.PS_FP32_PREC])
 def test_results_identical_alone_and_in_mix(reqs, precision):
+    """Every request bitwise equal alone and in the mix, where requests of one grid size
+    share step-1 launches (batched V-cycles over the shared mechanics hierarchy)."""
     ps.load()
     ctx = ps.ps_ctx_create(0, 0)
     try:
         alone = run_alone(ctx, reqs, precision=precision)
+        launches0, _ = ps.ps_ctx_batches(ctx)
         mix = run_mix(ctx, reqs, precision=precision)
+        launches, covered = ps.ps_ctx_batches(ctx)
     finally:
         ps.ps_ctx_destroy(ctx)
     for (ra, xa), (rm, xm) in zip(alone, mix):
@@ -97,6 +101,9 @@ def test_results_identical_alone_and_in_mix(reqs, precision):
         assert ra["iterations"] == rm["iterations"]
         assert np.array_equal(xa, xm)
         assert rm["rel_residual"] <= 1e-8
+    # the mix has two requests on each of the 8^3 and 12^3 grids: they shared launches
+    print("batched step-1 launch sequences %d covering %d requests" % (launches, covered), flush=True)
+    assert launches0 == 0 and launches > 0 and covered >= 2 * launches
 
 
 def test_admission_under_small_budget_serialises(reqs):
