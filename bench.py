@@ -380,7 +380,7 @@ def main():
                     help="local-stage sweeps (2: measured fastest to rtol 1e-8 on grf64)")
     ap.add_argument("--smoother", default="l1jac", choices=["cheb2", "l1jac"])
     ap.add_argument("--ml-kind", default="bilu0", choices=["bilu0", "bjacobi", "mcgs"])
-    ap.add_argument("--ml-part", default="32,16,16",
+    ap.add_argument("--ml-part", default="16,16,16",
                     help="processor-local local stage: subdomain box size in cells ('global': one domain)")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")

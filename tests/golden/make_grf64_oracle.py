@@ -1,6 +1,6 @@
 """Writes grf64_bench_oracle.json: the FP64 oracle's FGMRES iteration count and final
 residual on grf64 (64^3 cells, 1,348,163 unknowns) in the benchmarked configuration
-(l1-Jacobi smoothing, BILU(0) on 32 x 16 x 16-cell subdomains with two sweeps, FGMRES(100),
+(l1-Jacobi smoothing, BILU(0) on 16 x 16 x 16-cell subdomains with two sweeps, FGMRES(100),
 rtol 1e-8).  Calls only the oracle and the input generator; takes several minutes on one
 core.  Run from the repository root:  python tests/golden/make_grf64_oracle.py
 """
@@ -18,7 +18,7 @@ from synth import workload                       # noqa: E402
 from synth.jacobian import box_partition         # noqa: E402
 from oracle import Options, solve                # noqa: E402
 
-CONFIG = dict(workload="grf64", smoother="l1jac", ml_kind="bilu0", ml_sweeps=2, ml_part=(32, 16, 16),
+CONFIG = dict(workload="grf64", smoother="l1jac", ml_kind="bilu0", ml_sweeps=2, ml_part=(16, 16, 16),
               restart=100, rtol=1e-8)
 
 

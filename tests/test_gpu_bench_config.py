@@ -1,7 +1,7 @@
 """The HIP path against the FP64 oracle at the benchmarked size and configuration.
 
 grf64 (64^3 cells, 1,348,163 unknowns) with the benchmark's options -- l1-Jacobi
-smoothing, BILU(0) on 32 x 16 x 16-cell subdomains with two sweeps -- and ps_setup run
+smoothing, BILU(0) on 16 x 16 x 16-cell subdomains with two sweeps -- and ps_setup run
 twice, so that the operators the timed steps use (fixed stress, quasi-IMPES, pressure AMG
 and subdomain factors built on the device) are the ones compared:
   * one preconditioner application, field by field, in FP64 and FP32;
@@ -30,7 +30,7 @@ from paper_1812_05540_amd import ps  # noqa: E402
 HERE = os.path.dirname(os.path.abspath(__file__))
 GOLDEN_PATH = os.path.join(HERE, "golden", "grf64_bench_oracle.json")
 # the configuration the golden file was written for (tests/golden/make_grf64_oracle.py)
-CFG = dict(workload="grf64", smoother="l1jac", ml_kind="bilu0", ml_sweeps=2, ml_part=(32, 16, 16),
+CFG = dict(workload="grf64", smoother="l1jac", ml_kind="bilu0", ml_sweeps=2, ml_part=(16, 16, 16),
            restart=100, rtol=1e-8)
 OPTS = dict(smoother=ps.PS_L1JAC, ml_kind=ps.PS_BILU0, ml_sweeps=CFG["ml_sweeps"])
 # field-by-field bounds, as in test_gpu_parity (FP64: summation order only; FP32: the
