@@ -225,11 +225,16 @@ int  ps_wait(ps_ctx *ctx, uint64_t ticket, ps_result *res);
 /* Device bytes held by the handle (system matrix, hierarchy, Krylov space). */
 int  ps_footprint(ps_handle *h, size_t *bytes);
 
-/* Instrumentation.  ps_kernel_timing(1) clears the totals and starts bracketing the
- * hot kernels -- the system SpMV (both block-row kernels), the three CGS2 passes over the
- * Krylov basis, the subdomain BILU(0) sweeps -- with HIP events recorded on the stream
- * each runs on, adding each launch's algorithmic bytes (values, indices and vectors the
- * kernel must move, not what the caches do); 0 stops.  Process-wide. */
+/* Instrumentation.  ps_kernel_timing(mask) clears the totals and starts bracketing the
+ * instrumented kernels whose bit is set -- bit i for kernel idx i of ps_kernel_stats: the
+ * system SpMV (both block-row kernels, idx 0), the three CGS2 passes over the Krylov basis,
+ * the subdomain BILU(0) sweeps, and the level-0 pre-smoothing, restriction, prolongation
+ * and post-smoothing of the SDC and the pressure V-cycles -- with HIP events recorded on
+ * the stream each runs on, adding each launch's algorithmic bytes (values, indices and
+ * vectors the kernel must move, not what the caches do).  PS_KT_ALL brackets every one;
+ * 0 stops.  Each bracket adds two event records (a few microseconds) to the stream, so a
+ * timed run brackets only the kernels it reports.  Process-wide. */
+#define PS_KT_ALL (-1)
 int  ps_kernel_timing(int enable);
 /* Totals of instrumented kernel idx = 0, 1, ... (PS_EINVAL past the last): its name
  * (NUL-terminated, truncated to len bytes), launches, event seconds and algorithmic

@@ -807,7 +807,7 @@ int ps_poll(ps_ctx *c, uint64_t ticket, ps_result *res) {
 
 int ps_kernel_timing(int enable) {
     return guard([&] {
-        ktime::set_enabled(enable != 0);
+        ktime::set_mask(enable == PS_KT_ALL ? ~0u : (unsigned)enable);
         return PS_OK;
     });
 }

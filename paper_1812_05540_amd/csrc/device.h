@@ -309,8 +309,9 @@ enum Id {
 };
 // first id of the four level-0 V-cycle phases of a hierarchy: SDC_PRE or PRES_PRE
 const char *name(int id);
-bool enabled();
-void set_enabled(bool on);          // clears the totals
+bool enabled();                     // any kernel bracketed
+bool enabled(int id);
+void set_mask(unsigned mask);       // bit i brackets kernel id i; clears the totals
 struct Scope {
     Scope(int id, hipStream_t st, double bytes);
     ~Scope();

@@ -34,7 +34,7 @@ static inline unsigned grid_for(size_t n) { return (unsigned)((n + WG - 1) / WG)
 // ------------------------------------------------------------------ kernel timing
 namespace ktime {
 namespace {
-std::atomic<bool> g_on{false};
+std::atomic<unsigned> g_mask{0u};          // bit i: kernel id i is bracketed
 std::mutex g_mu;
 struct Rec {
     int id;
@@ -81,20 +81,22 @@ const char *name(int id) {
     return id >= 0 && id < NUM ? n[id] : "";
 }
 
-bool enabled() { return g_on.load(std::memory_order_relaxed); }
+bool enabled() { return g_mask.load(std::memory_order_relaxed) != 0u; }
 
-void set_enabled(bool on) {
+bool enabled(int id) { return id >= 0 && id < NUM && ((g_mask.load(std::memory_order_relaxed) >> id) & 1u); }
+
+void set_mask(unsigned mask) {
     std::lock_guard<std::mutex> lk(g_mu);
     drain_locked();
     for (int i = 0; i < NUM; ++i) {
         g_launches[i] = 0;
         g_seconds[i] = g_bytes[i] = 0.0;
     }
-    g_on.store(on);
+    g_mask.store(mask & ((1u << NUM) - 1u));
 }
 
 Scope::Scope(int i, hipStream_t s, double b) : id(i), st(s), bytes(b) {
-    if (!enabled() || id < 0) return;
+    if (!enabled(id)) return;
     e0 = get_event();
     PS_HIP(hipEventRecord(e0, st));
 }

@@ -23,6 +23,7 @@ PS_QUASI_IMPES, PS_TRUE_IMPES = 0, 1
 PS_FS_GIVEN, PS_FS_RSL = 0, 1
 PS_BILU0, PS_BJACOBI, PS_MCGS = 0, 1, 2
 PS_H_SDC, PS_H_PRES = 0, 1
+PS_KT_ALL = -1
 
 _i32p = C.POINTER(C.c_int32)
 _f64p = C.POINTER(C.c_double)
@@ -281,7 +282,14 @@ def ps_ctx_batches(ctx):
 
 
 def ps_kernel_timing(enable):
-    _check(load().ps_kernel_timing(1 if enable else 0), "ps_kernel_timing")
+    """True: bracket every instrumented kernel; False: stop; an int: ps.h's bit mask."""
+    mask = PS_KT_ALL if enable is True else 0 if enable is False else int(enable)
+    _check(load().ps_kernel_timing(mask), "ps_kernel_timing")
+
+
+def kernel_index(name):
+    """Index of an instrumented kernel by name (its bit in ps_kernel_timing's mask)."""
+    return list(ps_kernel_stats()).index(name)
 
 
 def ps_kernel_stats():

@@ -42,6 +42,17 @@ def test_library_exports_every_declared_symbol():
     assert set(names) == set(ps.exported_symbols())
 
 
+def test_header_constants_match_binding():
+    """Every integer #define of the two headers has the same value in the Python binding."""
+    n = 0
+    for h in ("ps.h", "ps_host.h"):
+        text = open(os.path.join(ROOT, "include", h)).read()
+        for name, val in re.findall(r"^#define\s+(PS_[A-Z0-9_]+)\s+\(?(-?\d+)\)?(?:\s|/\*|$)", text, flags=re.M):
+            assert getattr(ps, name) == int(val), name
+            n += 1
+    assert n >= 20
+
+
 def test_strerror_and_defaults():
     _lib()
     assert ps.ps_strerror(ps.PS_EINVAL) == "invalid argument"
