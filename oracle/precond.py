@@ -50,6 +50,7 @@ class Options:
     reduction: str = "quasi"       # "quasi" | "true" (IMPES reduction, Sec. 5.3)
     fixed_stress: str = "given"    # "given" (the system's d_sp, d_pp) | "rsl" (eq. FS_RSL)
     fs_iters: int = 10             # RSL: Richardson steps with the mechanics V-cycle for A_uu^-1
+    orth: str = "cgs2"             # FGMRES Arnoldi step: "cgs2" | "dcgs2" (delayed re-orthogonalisation)
 
 
 def bsr_to_csr(rowptr, colind, vals, ncols_blocks):

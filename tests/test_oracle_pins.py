@@ -43,9 +43,13 @@ def perms(s):
 
 
 # ---------------------------------------------------------------------------- solve
-def test_fgmres_matches_dense_direct_solve(iid8):
+ORTHS = ("cgs2", "dcgs2")
+
+
+@pytest.mark.parametrize("orth", ORTHS)
+def test_fgmres_matches_dense_direct_solve(iid8, orth):
     s, b = iid8
-    out = solve(s, b, rtol=1e-10)
+    out = solve(s, b, rtol=1e-10, opts=Options(orth=orth))
     A = dense(out["setup"].mats["A"])
     x = np.linalg.solve(A, b)
     assert out["status"] == 0 and out["rel_residual"] <= 1e-10
@@ -531,15 +535,19 @@ def test_block_ilu0_equals_pointwise_ilu0_on_block_pattern():
 
 
 # ---------------------------------------------------------------------------- FGMRES
-def test_fgmres_arnoldi_relation_and_orthogonality():
+@pytest.mark.parametrize("orth", ORTHS)
+def test_fgmres_arnoldi_relation_and_orthogonality(orth):
     s, b = tiny(grid=(4, 4, 3))
     st = P.setup(s)
     A = st.mats["A"]
     out = fgmres(lambda v: A @ v, lambda v: P.apply_precond(st, v), b, rtol=1e-30,
-                 restart=12, maxit=12, debug=True)
+                 restart=12, maxit=12, debug=True, orth=orth)
     d = out["debug"]
     V, Z, H = d["V"], d["Z"], d["H"]
-    k = Z.shape[0] - 1       # columns whose next basis vector was stored
+    # columns whose next basis vector was formed (CGS2 stores none after the last column;
+    # DCGS2 forms it when it finishes that column)
+    k = Z.shape[0] - (0 if orth == "dcgs2" else 1)
+    assert k >= 11
     AZ = np.stack([A @ z for z in Z[:k]], axis=1)
     rel = np.abs(AZ - V[: k + 1].T @ H[: k + 1, :k]).max() / sp.linalg.norm(A, np.inf)
     assert rel <= 1e-12
@@ -547,14 +555,16 @@ def test_fgmres_arnoldi_relation_and_orthogonality():
     assert np.abs(G - np.eye(k + 1)).max() <= 1e-12
 
 
-def test_fgmres_residual_estimates_monotone(iid8):
+@pytest.mark.parametrize("orth", ORTHS)
+def test_fgmres_residual_estimates_monotone(iid8, orth):
     s, b = iid8
-    out = solve(s, b, rtol=1e-9)
+    out = solve(s, b, rtol=1e-9, opts=Options(orth=orth))
     h = np.array(out["history"])
     assert np.all(np.diff(h) <= 1e-15)
 
 
-def test_fgmres_equals_minimal_residual_with_fixed_preconditioner():
+@pytest.mark.parametrize("orth", ORTHS)
+def test_fgmres_equals_minimal_residual_with_fixed_preconditioner(orth):
     """With a fixed linear M, iterate k minimises |b - A x| over x in M^{-1} K_k(A M^{-1}, b)."""
     rng = np.random.default_rng(9)
     n = 40
@@ -562,7 +572,7 @@ def test_fgmres_equals_minimal_residual_with_fixed_preconditioner():
     Minv = np.linalg.inv(np.diag(np.diag(A)) + np.tril(A, -1))
     b = rng.standard_normal(n)
     out = fgmres(lambda v: A @ v, lambda v: Minv @ v, b, rtol=1e-30, restart=30, maxit=8,
-                 record_iterates=True)
+                 record_iterates=True, orth=orth)
     B = A @ Minv
     K = [b]
     for k in range(1, 9):
@@ -574,20 +584,80 @@ def test_fgmres_equals_minimal_residual_with_fixed_preconditioner():
         K.append(B @ K[-1])
 
 
-def test_unpreconditioned_gmres_converges_in_n_steps():
+@pytest.mark.parametrize("orth", ORTHS)
+def test_unpreconditioned_gmres_converges_in_n_steps(orth):
     rng = np.random.default_rng(2)
     Q = rng.standard_normal((12, 12))
     A = Q @ Q.T + 12 * np.eye(12)
     b = rng.standard_normal(12)
-    out = fgmres(lambda v: A @ v, lambda v: v, b, rtol=1e-12, restart=50, maxit=50)
+    out = fgmres(lambda v: A @ v, lambda v: v, b, rtol=1e-12, restart=50, maxit=50, orth=orth)
     assert out["status"] == 0 and out["iterations"] <= 12
     assert np.allclose(out["x"], np.linalg.solve(A, b), rtol=1e-9)
 
 
-def test_zero_rhs_returns_zero():
+@pytest.mark.parametrize("orth", ORTHS)
+def test_zero_rhs_returns_zero(orth):
     s, _ = tiny()
-    out = solve(s, np.zeros(s.N))
+    out = solve(s, np.zeros(s.N), opts=Options(orth=orth))
     assert out["iterations"] == 0 and not out["x"].any() and out["status"] == 0
+
+
+@pytest.mark.parametrize("restart", [100, 7])
+def test_dcgs2_iterates_equal_cgs2_iterates(restart):
+    """Delayed re-orthogonalisation changes only when the second Gram-Schmidt pass and the
+    normalisation happen: in exact arithmetic both variants build the same basis and the
+    same iterates, so on a well-conditioned system (two-stage preconditioner, restarts
+    included) they agree to rounding and stop at the same iteration."""
+    s, b = tiny(grid=(4, 4, 3))
+    st = P.setup(s)
+    A = st.mats["A"]
+    runs = [fgmres(lambda v: A @ v, lambda v: P.apply_precond(st, v), b, rtol=1e-9, restart=restart,
+                   maxit=60, record_iterates=True, orth=o) for o in ORTHS]
+    a, c = runs
+    assert a["status"] == c["status"] == 0 and a["iterations"] == c["iterations"]
+    assert a["restarts"] == c["restarts"]
+    for xa, xc in zip(a["iterates"], c["iterates"]):
+        assert np.linalg.norm(xa - xc) <= 1e-11 * np.linalg.norm(xa)
+    # residual estimates (above the rounding floor of this cond ~ 1e10 system)
+    ha, hc = np.array(a["history"]), np.array(c["history"])
+    big = ha >= 1e-7
+    assert big.sum() >= 10 and np.allclose(ha[big], hc[big], rtol=1e-6)
+
+
+@pytest.mark.parametrize("orth", ORTHS)
+def test_fgmres_orthogonality_under_cancellation(orth):
+    """A flexible preconditioner that returns z_j = z_{j-1} + 1e-9 v_j makes every A z_j lie
+    within 1e-9 of span(V): one classical Gram-Schmidt pass then loses orthogonality
+    completely (checked here), while both two-pass variants keep V orthonormal and
+    A Z = V H to rounding.  (Drops the second pass, the normalisation by alpha or the
+    s.p term of t in the delayed variant, and this fails.)"""
+    rng = np.random.default_rng(5)
+    n, k = 120, 25
+    A = np.eye(n) * 3 + rng.standard_normal((n, n)) / np.sqrt(n)
+    b = rng.standard_normal(n)
+    state = {}
+
+    def prec(v):
+        z = v.copy() if "z" not in state else state["z"] + 1e-9 * v
+        state["z"] = z
+        return z
+
+    V1 = np.zeros((k + 1, n))               # one classical Gram-Schmidt pass
+    V1[0] = b / np.linalg.norm(b)
+    for j in range(k):
+        w = A @ prec(V1[j])
+        w = w - V1[: j + 1].T @ (V1[: j + 1] @ w)
+        V1[j + 1] = w / np.linalg.norm(w)
+    assert np.abs(V1 @ V1.T - np.eye(k + 1)).max() > 1e-3
+    state.clear()
+    out = fgmres(lambda v: A @ v, prec, b, rtol=1e-30, restart=k, maxit=k, debug=True, orth=orth)
+    d = out["debug"]
+    V, Z, H = d["V"], d["Z"], d["H"]
+    kk = Z.shape[0] - (0 if orth == "dcgs2" else 1)
+    assert kk >= k - 1
+    assert np.abs(V[: kk + 1] @ V[: kk + 1].T - np.eye(kk + 1)).max() <= 1e-13
+    AZ = np.stack([A @ z for z in Z[:kk]], axis=1)
+    assert np.abs(AZ - V[: kk + 1].T @ H[: kk + 1, :kk]).max() <= 1e-13 * np.abs(AZ).max()
 
 
 def test_multicolour_gs_is_block_gs_in_colour_order():
