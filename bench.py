@@ -79,6 +79,8 @@ KERNEL_SOURCES = {
     "cgs2_subtract_project": ("gemv_sub_mdot", "cgs2_fused_grf64_traffic.md"),
     "cgs2_subtract_norm": ("gemv_sub", "cgs2_subtract_grf64_traffic.md"),
     "bilu_subdomain": ("bilu_sub", "bilu_subdomain_grf64_traffic.md"),
+    "dcgs2_project": ("mdot2", "dcgs2_project_grf64_traffic.md"),
+    "dcgs2_subtract": ("gemv_sub2", "dcgs2_subtract_grf64_traffic.md"),
 }
 
 
@@ -119,7 +121,7 @@ def run_gpu(args, s, b):
     xs = {}
     for name, prec in precs:
         opts = dict(precision=prec, ml_sweeps=args.ml_sweeps, smoother=args.smoother_code,
-                    ml_kind=args.ml_kind_code)
+                    ml_kind=args.ml_kind_code, orth=args.orth_code)
         sv = ps.Solver(ctx, s, mech_key=1, **opts)
         t0 = time.perf_counter()
         sv.setup()                                # mechanics AMG (once) + flow stage
@@ -214,7 +216,7 @@ def cpu_baseline(s, b, its_gpu, budget_s, args):
     os.environ.setdefault("OMP_NUM_THREADS", "1")
     from oracle import precond as P, amg, Options
     from oracle.fgmres import fgmres
-    o = Options(smoother=args.smoother, ml_kind=args.ml_kind, ml_sweeps=args.ml_sweeps)
+    o = Options(smoother=args.smoother, ml_kind=args.ml_kind, ml_sweeps=args.ml_sweeps, orth=args.orth)
     t0 = time.perf_counter()
     sdc = amg.build(P.sdc_matrix(s), smoother=args.smoother)
     t_mech = time.perf_counter() - t0
@@ -224,7 +226,7 @@ def cpu_baseline(s, b, its_gpu, budget_s, args):
     A = st.mats["A"]
     n_it = 2 if t_setup < budget_s else 1
     t0 = time.perf_counter()
-    fgmres(lambda v: A @ v, lambda v: P.apply_precond(st, v), b, 1e-30, 100, n_it)
+    fgmres(lambda v: A @ v, lambda v: P.apply_precond(st, v), b, 1e-30, 100, n_it, orth=args.orth)
     t_it = (time.perf_counter() - t0) / n_it
     per_solve = t_setup + its_gpu * t_it
     return dict(value=round(1.0 / per_solve, 6), unit="solves/s", cores=1, kind="oracle",
@@ -297,7 +299,7 @@ def run_serving(args, stream):
     dev = torch.device("cuda:0")
     ctx = ps.ps_ctx_create(0, int(args.serving_budget_gb * 1e9))
     opts = dict(precision=ps.PS_FP32_PREC, smoother=args.smoother_code, ml_kind=args.ml_kind_code,
-                ml_sweeps=args.ml_sweeps)
+                ml_sweeps=args.ml_sweeps, orth=args.orth_code)
     # resident state per grid size: the mechanics hierarchy and set-up handles that the
     # context keeps for the requests (released handles are reused by ps_create)
     first = {}
@@ -397,6 +399,8 @@ def main():
     ap.add_argument("--ml-kind", default="bilu0", choices=["bilu0", "bjacobi", "mcgs"])
     ap.add_argument("--ml-part", default="16,16,16",
                     help="processor-local local stage: subdomain box size in cells ('global': one domain)")
+    ap.add_argument("--orth", default="dcgs2", choices=["cgs2", "dcgs2"],
+                    help="FGMRES Arnoldi step: classical Gram-Schmidt twice, or with delayed re-orthogonalisation")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=64,
@@ -412,6 +416,7 @@ def main():
         sys.exit(2)
     args.smoother_code = 0 if args.smoother == "cheb2" else 1
     args.ml_kind_code = {"bilu0": 0, "bjacobi": 1, "mcgs": 2}[args.ml_kind]
+    args.orth_code = {"cgs2": 0, "dcgs2": 1}[args.orth]
 
     from synth import workload
     from synth.configs import LOG10K_MAX
@@ -443,14 +448,16 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 preconditioner, f64 Krylov" if "fp32" in g else "f64",
         "data": "synthetic",
-        "config": {"workload": "%s: %dx%dx%d-cell %s-phase poromechanics Jacobian, N=%d, FGMRES(100) + "
+        "config": {"workload": "%s: %dx%dx%d-cell %s-phase poromechanics Jacobian, N=%d, FGMRES(100) (%s) + "
                                "two-stage preconditioner, rtol %g; step = flow-stage setup + solve; "
                                "log10 permeability clipped above at %.1f (about 20 D); state: line-drive "
                                "pressure solved through the permeability field"
                                % (args.workload, *s.meta["grid"], "two" if s.nf == 2 else "three", s.N,
+                                  "CGS2" if args.orth == "cgs2" else "delayed re-orthogonalisation",
                                   args.rtol, LOG10K_MAX),
                    "precision": "fp32-preconditioner" if "fp32" in g else "fp64",
                    "ml_sweeps": args.ml_sweeps, "smoother": args.smoother, "ml_kind": args.ml_kind,
+                   "orth": args.orth,
                    "ml_part": args.ml_part if args.ml_part else "global"},
         "paths": {k: v for k, v in g.items() if k in ("fp32", "fp64")},
         "roofline": g["roofline"],

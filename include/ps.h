@@ -67,6 +67,13 @@ extern "C" {
 #define PS_FS_RSL      1   /* fixed-stress diagonals by row-sum lumping, eq. FS_RSL: -diag(A_fu
                               A_uu^-1 A_up e), with A_uu^-1 approximated by fs_iters Richardson
                               steps preconditioned by the mechanics V-cycle */
+#define PS_CGS2        0   /* classical Gram-Schmidt applied twice: three passes over the basis
+                              per iteration */
+#define PS_DCGS2       1   /* classical Gram-Schmidt with delayed re-orthogonalisation (Bielich
+                              et al., Parallel Computing 112, 2022): the vector entering the
+                              preconditioner has had one pass; its second pass and its
+                              normalisation share the next iteration's pass over the basis,
+                              so two passes per iteration.  Same iterates in exact arithmetic */
 
 /* Block CSR matrix (host arrays).  Row-major br x bc blocks; rowptr has nbrows+1
  * entries starting at 0; colind sorted and unique within each block row. */
@@ -122,6 +129,7 @@ typedef struct {
     int32_t reduction;    /* PS_QUASI_IMPES | PS_TRUE_IMPES               (quasi)     */
     int32_t fixed_stress; /* PS_FS_GIVEN | PS_FS_RSL                      (given)     */
     int32_t fs_iters;     /* PS_FS_RSL: V-cycle iterations for A_uu^-1    (10)        */
+    int32_t orth;         /* FGMRES Arnoldi step: PS_CGS2 | PS_DCGS2      (PS_CGS2)   */
 } ps_options;
 
 typedef struct {

@@ -240,10 +240,10 @@ std::string park_key(const System &s, const Options &o) {
     }
     char buf[512];
     std::snprintf(buf, sizeof buf,
-                  "%llu|%d,%d,%d,%d,%d,%d,%d,%d,%d,%.17g,%d,%d,%d,%d|%d,%d,%d|%llx,%llx,%llx,%llx,%llx",
+                  "%llu|%d,%d,%d,%d,%d,%d,%d,%d,%d,%.17g,%d,%d,%d,%d,%d|%d,%d,%d|%llx,%llx,%llx,%llx,%llx",
                   (unsigned long long)s.mech_key, o.precision, o.restart, o.maxit, o.smoother, o.ml_kind,
                   o.ml_sweeps, o.coarse_max, o.max_levels, o.fp32_fallback, o.theta, o.method, o.reduction,
-                  o.fixed_stress, o.fs_iters, s.n_nodes, s.n_cells, s.nf, (unsigned long long)pattern_hash(s.Auu),
+                  o.fixed_stress, o.fs_iters, o.orth, s.n_nodes, s.n_cells, s.nf, (unsigned long long)pattern_hash(s.Auu),
                   (unsigned long long)pattern_hash(s.Auf), (unsigned long long)pattern_hash(s.Afu),
                   (unsigned long long)pattern_hash(s.Aff), (unsigned long long)part);
     return buf;
@@ -344,6 +344,7 @@ void ps_default_options(ps_options *o) {
     o->reduction = PS_QUASI_IMPES;
     o->fixed_stress = PS_FS_GIVEN;
     o->fs_iters = 10;
+    o->orth = PS_CGS2;
 }
 
 int ps_ctx_create(int device, size_t budget, ps_ctx **out) {
@@ -594,7 +595,7 @@ static SolveOut run_solve(ps_handle *h, Krylov &K, bool fp32, const double *rhs,
     Prec64 m64(h);
     PrecFn &M = fp32 ? static_cast<PrecFn &>(m32) : static_cast<PrecFn &>(m64);
     if (h->opt.method == PS_RICHARDSON) return richardson_blocking(h->dsys, K, M, rhs, x, rtol, h->opt.maxit, st);
-    Fgmres run(h->dsys, K, M, rhs, x, rtol, h->opt.maxit, st);
+    Fgmres run(h->dsys, K, M, rhs, x, rtol, h->opt.maxit, st, h->opt.orth);
     return fgmres_blocking(run, st);
 }
 
@@ -959,7 +960,7 @@ void ps_ctx::scheduler() {
                 if (f32) r->M = std::make_unique<Prec32>(r->h);
                 else r->M = std::make_unique<Prec64>(r->h);
                 r->run = std::make_unique<Fgmres>(r->h->dsys, *r->K, *r->M, r->rhs, r->x, r->rtol,
-                                                  r->h->opt.maxit, r->st);
+                                                  r->h->opt.maxit, r->st, r->h->opt.orth);
                 r->t_start = now_s();
                 r->run->start();
                 return PS_OK;

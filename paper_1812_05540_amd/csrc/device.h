@@ -305,6 +305,8 @@ enum Id {
     // prolongation (x += P e), post-smoothing sweep
     SDC_PRE, SDC_RESTRICT, SDC_PROLONG, SDC_POST,
     PRES_PRE, PRES_RESTRICT, PRES_PROLONG, PRES_POST,
+    // the two passes of delayed re-orthogonalisation
+    DCGS2_PROJECT, DCGS2_SUBTRACT,
     NUM
 };
 // first id of the four level-0 V-cycle phases of a hierarchy: SDC_PRE or PRES_PRE
@@ -334,7 +336,9 @@ struct Krylov {                   // FGMRES workspace (FP64 basis, Z in the prec
     double *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr;
     double *h1 = nullptr, *h2 = nullptr, *hsum = nullptr, *nw2 = nullptr;
     double *scal = nullptr;       // [|g_j+1|, h_j+1,j, |A z_j|, breakdown, beta, |r|^2, -, -]
-    double *partial = nullptr;    // (m+2) x nblk reduction partials
+    double *partial = nullptr;    // (2m+4) x nblk reduction partials
+    double *raw = nullptr;        // DCGS2: first-pass entries of the unfinished column (m+2)
+    double *coef = nullptr;       // DCGS2: [alpha, t, beta of the unfinished column, -]
     double *r = nullptr;          // true residual
     double *hostscal = nullptr;   // pinned host mirror of scal
     bool own_hostscal = true;     // false: hostscal belongs to the caller
@@ -419,8 +423,9 @@ struct PrecFn {
 // many of these, one per request and stream.
 class Fgmres {
   public:
+    // orth: PS_CGS2 or PS_DCGS2 (Arnoldi step)
     Fgmres(const DSystem &S, Krylov &K, PrecFn &M, const double *b, double *x, double rtol, int maxit,
-           hipStream_t st);
+           hipStream_t st, int orth = PS_CGS2);
     void start();
     bool advance();
     SolveOut out;
@@ -441,6 +446,8 @@ class Fgmres {
     void begin_cycle(const double *r);
     void enqueue_iteration();
     void rest_of_iteration();
+    void rest_dcgs2();
+    void finish_last_column(int k);
     void end_cycle(int k);
     bool defer_ = false, pending_ = false;
     const void *s1_rhs_ = nullptr;
@@ -453,6 +460,8 @@ class Fgmres {
     double rtol_;
     int maxit_;
     hipStream_t st_;
+    int orth_;
+    bool open_col_ = false;       // DCGS2: the newest column still lacks its second pass
     Phase phase_ = START;
     int j_ = 0, its_ = 0, cycles_ = 0;
     double beta_b_ = 0.0;

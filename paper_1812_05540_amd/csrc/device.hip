@@ -77,7 +77,7 @@ const char *name(int id) {
     static const char *n[NUM] = {"system_spmv", "cgs2_project", "cgs2_subtract_project", "cgs2_subtract_norm",
                                  "bilu_subdomain", "sdc_l0_presmooth", "sdc_l0_restrict", "sdc_l0_prolong",
                                  "sdc_l0_postsmooth", "pres_l0_presmooth", "pres_l0_restrict",
-                                 "pres_l0_prolong", "pres_l0_postsmooth"};
+                                 "pres_l0_prolong", "pres_l0_postsmooth", "dcgs2_project", "dcgs2_subtract"};
     return id >= 0 && id < NUM ? n[id] : "";
 }
 
@@ -1491,12 +1491,14 @@ static void layout_krylov(Krylov &K, size_t N, int m, bool z_fp32, Take take) {
     K.sn = d(m);
     K.g = d(m + 1);
     K.y = d(m);
-    K.h1 = d(m + 2);
+    K.h1 = d(2 * (size_t)m + 4);         // CGS2: m + 2 rows; DCGS2: 2 (m + 1) + 1
     K.h2 = d(m + 2);
     K.hsum = d(m + 2);
     K.nw2 = d(2);
     K.scal = d(8);
-    K.partial = d((size_t)(m + 2) * K.nblk);
+    K.partial = d((2 * (size_t)m + 4) * K.nblk);
+    K.raw = d(m + 2);
+    K.coef = d(4);
     K.r = d(N);
 }
 
@@ -1567,8 +1569,8 @@ void widen_f32(const float *in, double *out, size_t n, hipStream_t st) {
 
 // ------------------------------------------------------------------ FGMRES
 Fgmres::Fgmres(const DSystem &S, Krylov &K, PrecFn &M, const double *b, double *x, double rtol, int maxit,
-               hipStream_t st)
-    : S_(S), K_(K), M_(M), b_(b), x_(x), rtol_(rtol), maxit_(maxit), st_(st) {}
+               hipStream_t st, int orth)
+    : S_(S), K_(K), M_(M), b_(b), x_(x), rtol_(rtol), maxit_(maxit), st_(st), orth_(orth) {}
 
 void Fgmres::copy_scal() {
     PS_HIP(hipMemcpyAsync(K_.hostscal, K_.scal, 8 * sizeof(double), hipMemcpyDeviceToHost, st_));
@@ -1587,6 +1589,7 @@ void Fgmres::begin_cycle(const double *r) {
     LAUNCH(k::scale_div, grid_for(K_.N), 0, st_, r, (const double *)K_.scal, 4, K_.V, K_.N);
     j_ = 0;
     breakdown_ = false;
+    open_col_ = false;
     enqueue_iteration();
 }
 
@@ -1621,6 +1624,10 @@ void Fgmres::rest_of_iteration() {
     void *zj = (char *)K_.Z + (size_t)j * N * esz;
     if (K_.z_fp32) spmv_full<float>(S_, (const float *)zj, nullptr, w, st_);   // w = A z_j
     else spmv_full<double>(S_, (const double *)zj, nullptr, w, st_);
+    if (orth_ == PS_DCGS2) {
+        rest_dcgs2();
+        return;
+    }
     // CGS2: h1 = V^T w (+ |w|^2), w -= V h1, h2 = V^T w, w -= V h2, h = h1 + h2, |w|^2
     const double vb = (double)N * 8;                  // bytes of one basis vector
     {
@@ -1671,7 +1678,55 @@ void Fgmres::rest_of_iteration() {
     phase_ = ITER;
 }
 
+// DCGS2 (j = j_): one pass over V_0..V_j = u for every product (mdot2), their sums, the
+// second pass (u finished as v_j, w projected; gemv_sub2), then column j - 1 finished and
+// the estimate from the unfinished column j (givens2).
+void Fgmres::rest_dcgs2() {
+    const int j = j_, m = K_.m, nv = j + 1;
+    const size_t N = K_.N;
+    double *u = K_.V + (size_t)j * N, *w = u + N;
+    const double vb = (double)N * 8;
+    {
+        ktime::Scope ts(ktime::DCGS2_PROJECT, st_, (nv + 1) * vb);
+        const bool lds = K_.chunk <= 3840;           // w and u: <= 60 KB of LDS
+        const size_t shm = lds ? 2 * (size_t)K_.chunk * sizeof(double) : 0;
+        if (lds)
+            LAUNCH((k::mdot2<true>), K_.nblk, shm, st_, (const double *)K_.V, N, nv, (const double *)w, N, K_.chunk,
+                   K_.partial, K_.nblk);
+        else
+            LAUNCH((k::mdot2<false>), K_.nblk, shm, st_, (const double *)K_.V, N, nv, (const double *)w, N,
+                   K_.chunk, K_.partial, K_.nblk);
+    }
+    LAUNCH(k::reduce_rows, 2 * nv + 1, 0, st_, (const double *)K_.partial, K_.nblk, K_.h1,
+           (const double *)nullptr, (double *)nullptr);
+    {
+        ktime::Scope ts(ktime::DCGS2_SUBTRACT, st_, (nv + 3) * vb);
+        LAUNCH(k::gemv_sub2, K_.nblk, 0, st_, (const double *)K_.V, N, j, (const double *)K_.h1, u, w, N, K_.chunk,
+               K_.partial, K_.coef);
+    }
+    LAUNCH(k::givens2, 1, 0, st_, j, m, (const double *)K_.h1, K_.coef, K_.raw, (const double *)K_.partial,
+           K_.nblk, K_.H, K_.cs, K_.sn, K_.g, K_.scal, K_.hostscal);
+    open_col_ = true;
+    phase_ = ITER;
+}
+
+// DCGS2 at the end of a cycle of k columns: u_k = w / beta (into V_k), its products with
+// V_0..V_{k-1} and its norm, then column k - 1 finished and its rotation kept.
+void Fgmres::finish_last_column(int k) {
+    const size_t N = K_.N;
+    double *w = K_.V + (size_t)k * N;
+    LAUNCH(k::scale_div, grid_for(N), 0, st_, (const double *)w, (const double *)K_.scal, 1, w, N);
+    launch_mdot(K_, K_.V, k, w, true, st_);
+    LAUNCH(k::reduce_rows, k + 1, 0, st_, (const double *)K_.partial, K_.nblk, K_.h2, (const double *)nullptr,
+           (double *)nullptr);
+    LAUNCH(k::givens_finish, 1, 0, st_, k - 1, K_.m, (const double *)K_.h2, (const double *)K_.coef,
+           (const double *)K_.raw, K_.H, K_.cs, K_.sn, K_.g);
+    open_col_ = false;
+}
+
 void Fgmres::end_cycle(int k) {
+    if (k > 0 && open_col_) finish_last_column(k);
+    open_col_ = false;
     if (k > 0) {
         LAUNCH(k::backsolve, 1, 0, st_, k, K_.m, (const double *)K_.H, (const double *)K_.g, K_.y);
         if (K_.z_fp32)
@@ -1718,6 +1773,7 @@ bool Fgmres::advance() {
         }
         if (brk) {
             breakdown_ = true;
+            open_col_ = false;                // column k - 1 is dropped; k - 2 is finished
             end_cycle(k - 1);
             return true;
         }

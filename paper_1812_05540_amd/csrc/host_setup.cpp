@@ -253,11 +253,13 @@ Options options_from(const ps_options *o) {
     r.reduction = o->reduction;
     r.fixed_stress = o->fixed_stress;
     r.fs_iters = o->fs_iters;
+    r.orth = o->orth;
     if (r.precision != PS_FP64 && r.precision != PS_FP32_PREC) throw Error(PS_EINVAL, "precision");
     if (r.method != PS_FGMRES && r.method != PS_RICHARDSON) throw Error(PS_EINVAL, "method");
     if (r.reduction != PS_QUASI_IMPES && r.reduction != PS_TRUE_IMPES) throw Error(PS_EINVAL, "reduction");
     if (r.fixed_stress != PS_FS_GIVEN && r.fixed_stress != PS_FS_RSL) throw Error(PS_EINVAL, "fixed_stress");
     if (r.fs_iters < 1 || r.fs_iters > 100) throw Error(PS_EINVAL, "fs_iters must be in 1..100");
+    if (r.orth != PS_CGS2 && r.orth != PS_DCGS2) throw Error(PS_EINVAL, "orth must be PS_CGS2 or PS_DCGS2");
     if (r.restart < 1 || r.restart > 200) throw Error(PS_EINVAL, "restart must be in 1..200");
     if (r.maxit < 1) throw Error(PS_EINVAL, "maxit must be positive");
     if (r.smoother != PS_CHEB2 && r.smoother != PS_L1JAC) throw Error(PS_EINVAL, "smoother");

@@ -51,6 +51,7 @@ struct Options {
     int fp32_fallback = 0;
     double theta = 0.25;
     int method = PS_FGMRES, reduction = PS_QUASI_IMPES, fixed_stress = PS_FS_GIVEN, fs_iters = 10;
+    int orth = PS_CGS2;
 };
 
 Options options_from(const ps_options *o);

@@ -1537,6 +1537,284 @@ __global__ __launch_bounds__(WG) void givens(int j, int m, const double *__restr
     }
 }
 
+// ------------------------------------------------------------------ DCGS2
+// Classical Gram-Schmidt with delayed re-orthogonalisation (Bielich et al., Parallel
+// Computing 112, 2022).  While iteration j runs, V_0..V_{j-1} are finished and V_j holds u,
+// the vector that entered the preconditioner after one Gram-Schmidt pass (scaled to unit
+// norm); w = A z_j sits in V_{j+1}.  One pass over the basis gives every product, a second
+// finishes u and projects w.  Rows of the reduced products h (mdot2's partial rows):
+//   h[k] = V_k . w (k <= j; h[j] = u . w),  h[j+1] = w . w,  h[j+2+k] = V_k . u (k <= j;
+//   h[2j+2] = u . u).
+
+// partial rows (nv = j + 1): k < nv: V_k . w; nv: w . w; nv + 1 + k: V_k . u, over this
+// block's chunk.  Same structure as mdot (eight vectors per pass, three elements per thread
+// per step, fixed-order combination of the four waves); w and u are staged in LDS.
+template <bool LDSW>
+__global__ __launch_bounds__(WG) void mdot2(const double *__restrict__ V, size_t ldv, int nv,
+                                           const double *__restrict__ w, size_t n, int chunk,
+                                           double *__restrict__ partial, int nblk) {
+    constexpr int U = 3;
+    extern __shared__ double sw[];
+    __shared__ double red[4][2 * MAXV + 2];
+    size_t i0 = (size_t)blockIdx.x * chunk;
+    int len = i0 < n ? (int)((n - i0) < (size_t)chunk ? (n - i0) : (size_t)chunk) : 0;
+    const double *wb = w + i0;
+    const double *ub = V + (size_t)(nv - 1) * ldv + i0;
+    if (LDSW) {
+        for (int t = threadIdx.x; t < len; t += WG) {
+            sw[t] = wb[t];
+            sw[chunk + t] = ub[t];
+        }
+        __syncthreads();
+    }
+    const double *ws = LDSW ? sw : wb;
+    const double *us = LDSW ? sw + chunk : ub;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int npass = (nv + 7) / 8;
+    for (int p = 0; p < npass; ++p) {
+        const int k0 = 8 * p, kk = nv - k0 < 8 ? nv - k0 : 8;
+        const bool wnorm = p == 0;
+        // rows past nv re-read row k0 (in bounds, unused): every load is unconditional
+        const double *v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = V + (size_t)(q < kk ? k0 + q : k0) * ldv + i0;
+        double a[8], c[8], an = 0.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) a[q] = c[q] = 0.0;
+        for (int t0 = threadIdx.x; t0 < len; t0 += U * WG) {
+            double x[U][8], wt[U], ut[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int t = t0 + u * WG, tc = t < len ? t : len - 1;
+                wt[u] = ws[tc];
+                ut[u] = us[tc];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) x[u][q] = v[q][tc];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (t0 + u * WG < len) {
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        if (q < kk) {
+                            a[q] += x[u][q] * wt[u];
+                            c[q] += x[u][q] * ut[u];
+                        }
+                    }
+                    if (wnorm) an += wt[u] * wt[u];
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            if (q < kk) {
+                const double ra = wave_sum(a[q]);
+                const double rc = wave_sum(c[q]);
+                if (lane == 0) {
+                    red[wid][k0 + q] = ra;
+                    red[wid][nv + 1 + k0 + q] = rc;
+                }
+            }
+        }
+        if (wnorm) {
+            const double r = wave_sum(an);
+            if (lane == 0) red[wid][nv] = r;
+        }
+    }
+    __syncthreads();
+    const int ntot = 2 * nv + 1;
+    for (int k = threadIdx.x; k < ntot; k += WG)
+        partial[(size_t)k * nblk + blockIdx.x] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+}
+
+// alpha = sqrt(u.u - s.s) and t = (u.w - s.p) / alpha from the reduced rows h (j finished
+// vectors); one thread, increasing k: every caller gets the same bits.
+__device__ __forceinline__ void dcgs2_coef(const double *__restrict__ h, int j, double &alpha, double &t) {
+    double ss = 0.0, sp = 0.0;
+    for (int k = 0; k < j; ++k) {
+        const double sk = h[j + 2 + k];
+        ss += sk * sk;
+        sp += sk * h[k];
+    }
+    const double a2 = h[2 * j + 2] - ss;
+    alpha = a2 > 0.0 ? sqrt(a2) : 0.0;
+    t = (h[j] - sp) / alpha;
+}
+
+// The second pass: u <- (u - V_j s) / alpha (the finished v_j), w <- w - V_j p - t v_j, and
+// partial[blk] = |w|^2 over this block's chunk.  Block 0 stores alpha, t in coef[0], coef[1].
+// V is read with non-temporal loads, as in gemv_sub (the last pass over it this iteration).
+__global__ __launch_bounds__(WG) void gemv_sub2(const double *__restrict__ V, size_t ldv, int j,
+                                               const double *__restrict__ h, double *__restrict__ u,
+                                               double *__restrict__ w, size_t n, int chunk,
+                                               double *__restrict__ partial, double *__restrict__ coef) {
+    __shared__ double hs[MAXV], hp[MAXV];
+    __shared__ double red[4];
+    __shared__ double at[2];
+    for (int k = threadIdx.x; k < j; k += WG) {
+        hs[k] = h[j + 2 + k];
+        hp[k] = h[k];
+    }
+    if (threadIdx.x == 0) {
+        double alpha, t;
+        dcgs2_coef(h, j, alpha, t);
+        at[0] = alpha;
+        at[1] = t;
+        if (blockIdx.x == 0) {
+            coef[0] = alpha;
+            coef[1] = t;
+        }
+    }
+    __syncthreads();
+    const double alpha = at[0], t = at[1];
+    size_t i0 = (size_t)blockIdx.x * chunk;
+    int len = i0 < n ? (int)((n - i0) < (size_t)chunk ? (n - i0) : (size_t)chunk) : 0;
+    double acc = 0.0;
+    for (int e = threadIdx.x; e < len; e += WG) {
+        const size_t i = i0 + e;
+        double su = 0.0, sw = 0.0;
+        for (int k = 0; k < j; ++k) {
+            const double v = __builtin_nontemporal_load(&V[(size_t)k * ldv + i]);
+            su += v * hs[k];
+            sw += v * hp[k];
+        }
+        const double vn = (u[i] - su) / alpha;
+        const double wn = (w[i] - sw) - t * vn;
+        u[i] = vn;
+        w[i] = wn;
+        acc += wn * wn;
+    }
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+// Hessenberg columns under DCGS2 (column-major H, leading dimension m+1).  Column j - 1 is
+// finished now that u_j's products are known: its first-pass entries raw[0..j-1] gain
+// beta_{j-1} s and h_{j,j-1} = beta_{j-1} alpha (beta_{j-1} in coef[2]); its rotation is kept.
+// Column j's first-pass entries (p, t) replace raw, beta_j = |w| (sum of the chunk partials
+// wpart) goes to coef[2], and the Givens estimate with the unfinished column j -- rotation
+// not kept -- decides whether to stop.  scal out: [0] estimate, [1] beta_j, [2] |A z_j|,
+// [3] breakdown flag; hscal: pinned host copy.
+__global__ __launch_bounds__(WG) void givens2(int j, int m, const double *__restrict__ h,
+                                             double *__restrict__ coef, double *__restrict__ raw,
+                                             const double *__restrict__ wpart, int nblk,
+                                             double *__restrict__ H, double *__restrict__ cs,
+                                             double *__restrict__ sn, double *__restrict__ g,
+                                             double *__restrict__ scal, double *__restrict__ hscal) {
+    __shared__ double col[MAXV + 1], c[MAXV], s[MAXV], rw[MAXV + 1];
+    __shared__ double out[4], red[4];
+    __shared__ double nw2[1];
+    const int tid = threadIdx.x;
+    {
+        double a = 0.0;
+        for (int b = tid; b < nblk; b += WG) a += wpart[b];
+        a = block_sum(a, red);
+        if (tid == 0) nw2[0] = a;
+    }
+    for (int i = tid; i < j; i += WG) {
+        rw[i] = raw[i];
+        c[i] = cs[i];
+        s[i] = sn[i];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const double alpha = coef[0], t = coef[1];
+        if (j > 0) {
+            const double bp = coef[2];
+            for (int i = 0; i < j; ++i) col[i] = rw[i] + bp * h[j + 2 + i];
+            col[j] = bp * alpha;
+            for (int i = 0; i + 1 < j; ++i) {
+                double r = c[i] * col[i] + s[i] * col[i + 1];
+                col[i + 1] = -s[i] * col[i] + c[i] * col[i + 1];
+                col[i] = r;
+            }
+            const double rho = hypot(col[j - 1], col[j]);
+            const double cj = col[j - 1] / rho, sj = col[j] / rho;
+            c[j - 1] = cj;
+            s[j - 1] = sj;
+            cs[j - 1] = cj;
+            sn[j - 1] = sj;
+            col[j - 1] = rho;
+            col[j] = 0.0;
+            double *hc = H + (size_t)(j - 1) * (m + 1);
+            for (int i = 0; i <= j; ++i) hc[i] = col[i];
+            const double gj = g[j - 1];
+            g[j] = -sj * gj;
+            g[j - 1] = cj * gj;
+        }
+        // column j as the first pass left it
+        for (int i = 0; i < j; ++i) {
+            rw[i] = h[i];
+            raw[i] = h[i];
+        }
+        raw[j] = t;
+        const double hn = sqrt(nw2[0]);
+        coef[2] = hn;
+        for (int i = 0; i < j; ++i) col[i] = rw[i];
+        col[j] = t;
+        col[j + 1] = hn;
+        for (int i = 0; i < j; ++i) {
+            double r = c[i] * col[i] + s[i] * col[i + 1];
+            col[i + 1] = -s[i] * col[i] + c[i] * col[i + 1];
+            col[i] = r;
+        }
+        const double rho = hypot(col[j], col[j + 1]);
+        out[1] = hn;
+        out[2] = sqrt(h[j + 1]);
+        if (rho == 0.0) {
+            out[0] = fabs(g[j]);
+            out[3] = 1.0;
+        } else {
+            out[0] = fabs(col[j + 1] / rho * g[j]);
+            out[3] = 0.0;
+        }
+    }
+    __syncthreads();
+    if (tid < 4) {
+        scal[tid] = out[tid];
+        if (hscal) hscal[tid] = out[tid];
+    }
+}
+
+// End of a DCGS2 cycle: column j is finished with u_{j+1} = w / beta_j (beta_j in coef[2])
+// and its reduced products h2[k] = V_k . u_{j+1} (k <= j), h2[j+1] = |u_{j+1}|^2: the
+// first-pass entries raw[0..j] gain beta_j s', h_{j+1,j} = beta_j alpha' with alpha' =
+// sqrt(|u|^2 - s'.s'), and its rotation is kept (g updated).  beta_j = 0: nothing to add.
+__global__ void givens_finish(int j, int m, const double *__restrict__ h2, const double *__restrict__ coef,
+                              const double *__restrict__ raw, double *__restrict__ H, double *__restrict__ cs,
+                              double *__restrict__ sn, double *__restrict__ g) {
+    __shared__ double col[MAXV + 1];
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double bt = coef[2];
+    for (int i = 0; i <= j; ++i) col[i] = raw[i];
+    col[j + 1] = 0.0;
+    if (bt != 0.0) {
+        double ss = 0.0;
+        for (int i = 0; i <= j; ++i) {
+            ss += h2[i] * h2[i];
+            col[i] += bt * h2[i];
+        }
+        const double a2 = h2[j + 1] - ss;
+        col[j + 1] = a2 > 0.0 ? bt * sqrt(a2) : 0.0;
+    }
+    for (int i = 0; i < j; ++i) {
+        double r = cs[i] * col[i] + sn[i] * col[i + 1];
+        col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+        col[i] = r;
+    }
+    const double rho = hypot(col[j], col[j + 1]);
+    const double cj = col[j] / rho, sj = col[j + 1] / rho;
+    cs[j] = cj;
+    sn[j] = sj;
+    col[j] = rho;
+    col[j + 1] = 0.0;
+    double *hc = H + (size_t)j * (m + 1);
+    for (int i = 0; i <= j + 1; ++i) hc[i] = col[i];
+    const double gj = g[j];
+    g[j + 1] = -sj * gj;
+    g[j] = cj * gj;
+}
+
 // Start of a cycle: g = beta e_1 with beta = sqrt(nr2[0]).
 __global__ void cycle_start(int m, const double *__restrict__ nr2, double *__restrict__ g,
                             double *__restrict__ scal) {

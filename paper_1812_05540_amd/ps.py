@@ -21,6 +21,7 @@ PS_CHEB2, PS_L1JAC = 0, 1
 PS_FGMRES, PS_RICHARDSON = 0, 1
 PS_QUASI_IMPES, PS_TRUE_IMPES = 0, 1
 PS_FS_GIVEN, PS_FS_RSL = 0, 1
+PS_CGS2, PS_DCGS2 = 0, 1
 PS_BILU0, PS_BJACOBI, PS_MCGS = 0, 1, 2
 PS_H_SDC, PS_H_PRES = 0, 1
 PS_KT_ALL = -1
@@ -45,7 +46,7 @@ class ps_options(C.Structure):
                 ("smoother", C.c_int32), ("ml_kind", C.c_int32), ("ml_sweeps", C.c_int32),
                 ("coarse_max", C.c_int32), ("max_levels", C.c_int32), ("fp32_fallback", C.c_int32),
                 ("theta", C.c_double), ("method", C.c_int32), ("reduction", C.c_int32),
-                ("fixed_stress", C.c_int32), ("fs_iters", C.c_int32)]
+                ("fixed_stress", C.c_int32), ("fs_iters", C.c_int32), ("orth", C.c_int32)]
 
 
 class ps_result(C.Structure):

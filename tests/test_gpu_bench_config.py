@@ -1,7 +1,8 @@
 """The HIP path against the FP64 oracle at the benchmarked size and configuration.
 
 grf64 (64^3 cells, 1,348,163 unknowns) with the benchmark's options -- l1-Jacobi
-smoothing, BILU(0) on 16 x 16 x 16-cell subdomains with two sweeps -- and ps_setup run
+smoothing, BILU(0) on 16 x 16 x 16-cell subdomains with two sweeps, FGMRES with delayed
+re-orthogonalisation -- and ps_setup run
 twice, so that the operators the timed steps use (fixed stress, quasi-IMPES, pressure AMG
 and subdomain factors built on the device) are the ones compared:
   * one preconditioner application, field by field, in FP64 and FP32;
@@ -31,8 +32,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 GOLDEN_PATH = os.path.join(HERE, "golden", "grf64_bench_oracle.json")
 # the configuration the golden file was written for (tests/golden/make_grf64_oracle.py)
 CFG = dict(workload="grf64", smoother="l1jac", ml_kind="bilu0", ml_sweeps=2, ml_part=(16, 16, 16),
-           restart=100, rtol=1e-8)
-OPTS = dict(smoother=ps.PS_L1JAC, ml_kind=ps.PS_BILU0, ml_sweeps=CFG["ml_sweeps"])
+           restart=100, rtol=1e-8, orth="dcgs2")
+OPTS = dict(smoother=ps.PS_L1JAC, ml_kind=ps.PS_BILU0, ml_sweeps=CFG["ml_sweeps"], orth=ps.PS_DCGS2)
 # field-by-field bounds, as in test_gpu_parity (FP64: summation order only; FP32: the
 # FP32 rounding amplified by the cancellation that forms the saturation field)
 FP64_BLOCK_TOL = 1e-11
@@ -102,7 +103,7 @@ def test_bench_config_iterates_match_oracle(ctx, case):
     A = st.mats["A"]
     print("oracle FGMRES, 10 iterations", flush=True)
     out = fgmres(lambda v: A @ v, lambda v: P.apply_precond(st, v), b, rtol=1e-30, restart=100, maxit=10,
-                 record_iterates=True)
+                 record_iterates=True, orth=CFG["orth"])
     for k in (5, 10):
         sv = solver(ctx, s, precision=ps.PS_FP64, maxit=k)
         x = dev(np.zeros(s.N))

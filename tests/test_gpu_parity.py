@@ -96,7 +96,8 @@ def oracle_opts(**opts):
                    reduction={ps.PS_QUASI_IMPES: "quasi", ps.PS_TRUE_IMPES: "true"}[
                        opts.get("reduction", ps.PS_QUASI_IMPES)],
                    fixed_stress={ps.PS_FS_GIVEN: "given", ps.PS_FS_RSL: "rsl"}[opts.get("fixed_stress", ps.PS_FS_GIVEN)],
-                   fs_iters=opts.get("fs_iters", 10))
+                   fs_iters=opts.get("fs_iters", 10),
+                   orth={ps.PS_CGS2: "cgs2", ps.PS_DCGS2: "dcgs2"}[opts.get("orth", ps.PS_CGS2)])
 
 
 @pytest.mark.parametrize("name", list(SMALL))
@@ -189,7 +190,12 @@ def test_precond_fp32_close_to_fp64(ctx, name):
                                        ("iid8", dict(reduction=ps.PS_TRUE_IMPES)),
                                        ("iid3ph", dict(fixed_stress=ps.PS_FS_RSL)),
                                        ("iid8", dict(method=ps.PS_RICHARDSON)),
-                                       ("iid3ph", dict(method=ps.PS_RICHARDSON, smoother=ps.PS_L1JAC))])
+                                       ("iid3ph", dict(method=ps.PS_RICHARDSON, smoother=ps.PS_L1JAC)),
+                                       # delayed re-orthogonalisation against the oracle's DCGS2
+                                       ("iid8", dict(orth=ps.PS_DCGS2)),
+                                       ("grf12", dict(orth=ps.PS_DCGS2)),
+                                       ("grf12", dict(orth=ps.PS_DCGS2, smoother=ps.PS_L1JAC, ml_sweeps=2)),
+                                       ("iid3ph", dict(orth=ps.PS_DCGS2, smoother=ps.PS_L1JAC))])
 def test_fp64_solve_matches_oracle(ctx, name, opts):
     s, b = small(name)
     out = oracle_solve(s, b, rtol=1e-8, opts=oracle_opts(**opts), record_iterates=True)
@@ -205,7 +211,8 @@ def test_fp64_solve_matches_oracle(ctx, name, opts):
     sv.close()
 
 
-@pytest.mark.parametrize("opts", [dict(ml_sweeps=2), dict(ml_kind=ps.PS_MCGS, ml_sweeps=3)])
+@pytest.mark.parametrize("opts", [dict(ml_sweeps=2), dict(ml_kind=ps.PS_MCGS, ml_sweeps=3),
+                                  dict(ml_sweeps=2, orth=ps.PS_DCGS2)])
 def test_fp64_iterates_match_oracle_at_matched_k_on_ill_conditioned_field(ctx, opts):
     """sigma = 2 field (cond ~1e10): x_k (GPU stopped by maxit = k) against the oracle's
     x_k at k = 5, 15, 30, each within 1e-9.  Rounding differences (a few 1e-16 per
@@ -227,14 +234,15 @@ def test_fp64_iterates_match_oracle_at_matched_k_on_ill_conditioned_field(ctx, o
         assert err <= tol, (k, err)
 
 
-@pytest.mark.parametrize("name", ["iid8", "grf12", "iid3ph"])
-def test_fp32_solve_reaches_fp64_accuracy(ctx, name):
+@pytest.mark.parametrize("name,orth", [("iid8", ps.PS_CGS2), ("grf12", ps.PS_CGS2), ("iid3ph", ps.PS_CGS2),
+                                       ("grf12", ps.PS_DCGS2)])
+def test_fp32_solve_reaches_fp64_accuracy(ctx, name, orth):
     s, b = small(name)
     tight = oracle_solve(s, b, rtol=1e-12)["x"]
     A = P.system_matrices(s)["A"]
     res = {}
     for prec in (ps.PS_FP64, ps.PS_FP32_PREC):
-        sv = make_solver(ctx, s, precision=prec)
+        sv = make_solver(ctx, s, precision=prec, orth=orth)
         x = dev(np.zeros(s.N))
         r = sv.solve(dev(b), x, 1e-8)
         xh = host(x)
@@ -391,9 +399,10 @@ def test_device_operators_equal_host_operators(ctx, case, precision, monkeypatch
         assert np.array_equal(xa, xb)
 
 
-def test_solves_are_deterministic(ctx):
+@pytest.mark.parametrize("orth", [ps.PS_CGS2, ps.PS_DCGS2])
+def test_solves_are_deterministic(ctx, orth):
     s, b = small("grf12")
-    sv = make_solver(ctx, s)
+    sv = make_solver(ctx, s, orth=orth)
     xs = []
     for _ in range(2):
         x = dev(np.zeros(s.N))
@@ -431,10 +440,11 @@ def test_edge_cases(ctx):
     sv.close()
 
 
-def test_restarted_solve_matches_oracle(ctx):
+@pytest.mark.parametrize("orth", [ps.PS_CGS2, ps.PS_DCGS2])
+def test_restarted_solve_matches_oracle(ctx, orth):
     s, b = small("iid8")
-    out = oracle_solve(s, b, rtol=1e-8, opts=Options(restart=7))
-    sv = make_solver(ctx, s, restart=7)
+    out = oracle_solve(s, b, rtol=1e-8, opts=oracle_opts(restart=7, orth=orth))
+    sv = make_solver(ctx, s, restart=7, orth=orth)
     x = dev(np.zeros(s.N))
     r = sv.solve(dev(b), x, 1e-8)
     assert r["status"] == ps.PS_OK
