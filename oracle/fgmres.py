@@ -10,20 +10,23 @@ Hessenberg least-squares problem, x0 = 0, convergence when the true residual
 h_{j+1,j} <= 1e-14 |A z_j|, and at most `maxit` iterations in total.
 
 orth = "dcgs2": the same method with the Arnoldi step orthogonalised by classical
-Gram-Schmidt with delayed re-orthogonalisation (Bielich, Langou, Thomas, Swirydowicz,
-Yamazaki, Boman, Parallel Computing 112, 2022).  The vector u_j that enters the
-preconditioner has had one Gram-Schmidt pass against the finished basis v_0..v_{j-1} and
-was scaled by its norm; its second pass and exact normalisation happen in the next
-iteration, in the same pass over the basis that projects w = A z_j:
+Gram-Schmidt with delayed re-orthogonalisation and lagged normalisation (Bielich, Langou,
+Thomas, Swirydowicz, Yamazaki, Boman, Parallel Computing 112, 2022).  The vector u_j that
+enters the preconditioner has had one Gram-Schmidt pass against the finished basis
+v_0..v_{j-1}; its second pass and its normalisation happen in the next iteration, in the
+same pass over the basis that projects w = A z_j:
 
     s = V_j^T u_j,   p = V_j^T w,   alpha = sqrt(u_j.u_j - s.s),   t = (u_j.w - s.p) / alpha,
-    v_j = (u_j - V_j s) / alpha,   w <- w - V_j p - t v_j,   beta = |w|,   u_{j+1} = w / beta.
+    v_j = (u_j - V_j s) / alpha,   r_j = w - V_j p - t v_j,   u_{j+1} = r_j / |w|.
 
-Column j of the Hessenberg matrix is (p, t) until the next iteration adds beta s' and sets
-h_{j+1,j} = beta alpha' (s', alpha' of u_{j+1}); FGMRES keeps z_j = M^{-1} u_j, so
-A Z_k = V_{k+1} H_k holds with the finished columns (the flexible method allows any z_j).
-The stopping test after iteration j uses the Givens estimate of the unfinished column; when
-the cycle ends its last column is finished with one more product V^T u_{j+1}.  In exact
+Scaling by |w| = |A z_j| (known before the second pass) keeps |u_{j+1}| <= 1 without a pass
+of its own, and, unlike leaving u unscaled, does not compound over the iterations.  Column j
+of the Hessenberg matrix is (p, t) until the next iteration adds |w| s' and sets
+h_{j+1,j} = |w| alpha' (s', alpha' of u_{j+1}); FGMRES keeps z_j = M^{-1} u_j, so
+A Z_k = V_{k+1} H_k holds with the finished columns (the flexible method allows any z_j, and
+every formula above is invariant to the scale of u_j).  The stopping test after iteration j
+uses the Givens estimate of the unfinished column, with |r_j| as its subdiagonal; when the
+cycle ends its last column is finished with one more product V^T u_{j+1}.  In exact
 arithmetic the iterates equal those of CGS2.
 """
 import numpy as np
@@ -138,22 +141,24 @@ def _rotate(col, cs, sn, nrot):
         col[i] = t
 
 
-def _finished_column(raw, beta, V, u_next, want_v=False):
-    """Column j of H from its first-pass entries raw (length j+1), the norm beta of the
-    vector w left after that pass and the next vector u_next = w / beta: adds beta s' and
-    sets h_{j+1,j} = beta alpha', s' = V_{j+1}^T u_next, alpha' = sqrt(|u_next|^2 - s'.s').
-    want_v: also return v_{j+1} = (u_next - V_{j+1} s') / alpha' (None when beta = 0)."""
+def _finished_column(raw, naz, V, u_next, want_v=False):
+    """Column j of H from its first-pass entries raw (length j+1), the scale naz = |A z_j|
+    and the vector u_next = r_j / naz that pass left: adds naz s' and sets h_{j+1,j} =
+    naz alpha', s' = V_{j+1}^T u_next, alpha' = sqrt(|u_next|^2 - s'.s') (naz = 0: nothing
+    to add).  want_v: also return v_{j+1} = (u_next - V_{j+1} s') / alpha' (None when
+    alpha' = 0)."""
     j = raw.shape[0] - 1
     col = np.zeros(j + 2)
     col[: j + 1] = raw
-    if beta == 0.0:
+    if naz == 0.0:
         return (col, None) if want_v else col
     sp = V[: j + 1] @ u_next
     a2 = u_next @ u_next - sp @ sp
-    col[: j + 1] += beta * sp
-    col[j + 1] = beta * np.sqrt(a2) if a2 > 0.0 else 0.0
+    alpha = np.sqrt(a2) if a2 > 0.0 else 0.0
+    col[: j + 1] += naz * sp
+    col[j + 1] = naz * alpha
     if want_v:
-        return col, (u_next - V[: j + 1].T @ sp) / np.sqrt(a2)
+        return col, ((u_next - V[: j + 1].T @ sp) / alpha if alpha > 0.0 else None)
     return col
 
 
@@ -180,7 +185,7 @@ def _fgmres_dcgs2(matvec, precond, b, rtol, restart, maxit, record_iterates, deb
         g = np.zeros(m + 1)
         g[0] = beta
         V[0] = r / beta
-        raw_prev, beta_prev = None, 0.0
+        raw_prev, naz_prev = None, 0.0
         Hraw = np.zeros((m + 1, m))       # finished columns before rotation
         v_last = None
         k = 0
@@ -202,11 +207,12 @@ def _fgmres_dcgs2(matvec, precond, b, rtol, restart, maxit, record_iterates, deb
             V[j] = v
             w = w - V[:j].T @ p - t * v
             hn = np.linalg.norm(w)
+            u_next = w / norm_az if norm_az > 0.0 else np.zeros(n)
             if j > 0:
                 # column j-1 finished with s and alpha of u_j
                 col = np.zeros(j + 1)
-                col[:j] = raw_prev + beta_prev * s
-                col[j] = beta_prev * alpha
+                col[:j] = raw_prev + naz_prev * s
+                col[j] = naz_prev * alpha
                 Hraw[: j + 1, j - 1] = col
                 _rotate(col, cs, sn, j - 1)
                 rho = np.hypot(col[j - 1], col[j])
@@ -230,7 +236,7 @@ def _fgmres_dcgs2(matvec, precond, b, rtol, restart, maxit, record_iterates, deb
             est = abs(col[j + 1] / rho * g[j])
             res["history"].append(est / beta_b)
             if record_iterates:
-                colf = _finished_column(raw, hn, V, w / hn if hn > 0.0 else w)
+                colf = _finished_column(raw, norm_az, V, u_next)
                 _rotate(colf, cs, sn, j)
                 rf = np.hypot(colf[j], colf[j + 1])
                 Hk = H[:k, :k].copy()
@@ -242,7 +248,7 @@ def _fgmres_dcgs2(matvec, precond, b, rtol, restart, maxit, record_iterates, deb
                 res["iterates"].append(x + Z[:k].T @ y)
             if est <= rtol * beta_b or hn <= 1e-14 * norm_az or its >= maxit:
                 # finish the last column, keep its rotation
-                col, v_last = _finished_column(raw, hn, V, w / hn if hn > 0.0 else w, want_v=True)
+                col, v_last = _finished_column(raw, norm_az, V, u_next, want_v=True)
                 Hraw[: j + 2, j] = col
                 _rotate(col, cs, sn, j)
                 rho = np.hypot(col[j], col[j + 1])
@@ -254,13 +260,13 @@ def _fgmres_dcgs2(matvec, precond, b, rtol, restart, maxit, record_iterates, deb
                 g[j + 1] = -sn[j] * g[j]
                 g[j] = cs[j] * g[j]
                 break
-            V[j + 1] = w / hn
-            raw_prev, beta_prev = raw, hn
+            V[j + 1] = u_next
+            raw_prev, naz_prev = raw, norm_az
             last_open = True
         if last_open:
             # the cycle ran to the restart length: finish its last column
             j = m - 1
-            col, v_last = _finished_column(raw, hn, V, V[m], want_v=True)
+            col, v_last = _finished_column(raw, naz_prev, V, V[m], want_v=True)
             Hraw[: j + 2, j] = col
             _rotate(col, cs, sn, j)
             rho = np.hypot(col[j], col[j + 1])

@@ -215,10 +215,12 @@ Sell<T> upload_sell(Arena &ar, const HostSell &h) {
 }
 
 // An operator takes the SELL-64 form (one lane per row, coalesced loads) when its 64-row
-// slices pad it to at most 1.5 stored slots per entry, its rows average at most 32 entries
+// slices pad it to at most 1.5 stored slots per entry, its rows average at most 128 entries
 // and it has at least 2^17 rows (2048 wavefronts); otherwise one lane per row leaves too
 // few wavefronts with too long a chain of loads each, and CSR with G lanes per row is
-// faster on MI355X.  PS_SELL=all puts every operator in SELL-64, PS_SELL=off none.
+// faster on MI355X (measured on grf64: the SDC operator's second level, 227k rows of 67
+// entries on average, is 12 us per V-cycle faster in SELL-64; its third, 44k rows, slower).
+// PS_SELL=all puts every operator in SELL-64, PS_SELL=off none.
 static int sell_mode() {                 // 0 by the rule above, 1 all, -1 none
     const char *e = std::getenv("PS_SELL");
     if (!e) return 0;
@@ -238,7 +240,7 @@ static double sell_padding(const int *w, int n, size_t nnz) {
 static bool take_sell(double pad, int n, size_t nnz) {
     const int mode = sell_mode();
     if (mode < 0 || pad * nnz >= 2e9) return false;
-    return mode > 0 || (pad <= 1.5 && n >= (1 << 17) && nnz <= (size_t)32 * n);
+    return mode > 0 || (pad <= 1.5 && n >= (1 << 17) && nnz <= (size_t)128 * n);
 }
 
 static int lanes_per_row(int n, size_t nnz) {
@@ -1710,12 +1712,11 @@ void Fgmres::rest_dcgs2() {
     phase_ = ITER;
 }
 
-// DCGS2 at the end of a cycle of k columns: u_k = w / beta (into V_k), its products with
-// V_0..V_{k-1} and its norm, then column k - 1 finished and its rotation kept.
+// DCGS2 at the end of a cycle of k columns: the products of u_k (in V_k) with V_0..V_{k-1}
+// and its norm, then column k - 1 finished and its rotation kept.
 void Fgmres::finish_last_column(int k) {
     const size_t N = K_.N;
     double *w = K_.V + (size_t)k * N;
-    LAUNCH(k::scale_div, grid_for(N), 0, st_, (const double *)w, (const double *)K_.scal, 1, w, N);
     launch_mdot(K_, K_.V, k, w, true, st_);
     LAUNCH(k::reduce_rows, k + 1, 0, st_, (const double *)K_.partial, K_.nblk, K_.h2, (const double *)nullptr,
            (double *)nullptr);
@@ -1782,7 +1783,8 @@ bool Fgmres::advance() {
             return true;
         }
         double *w = K_.V + (size_t)k * K_.N;
-        LAUNCH(k::scale_div, grid_for(K_.N), 0, st_, (const double *)w, (const double *)K_.scal, 1, w, K_.N);
+        if (orth_ != PS_DCGS2)                       // DCGS2: gemv_sub2 wrote u_k already scaled
+            LAUNCH(k::scale_div, grid_for(K_.N), 0, st_, (const double *)w, (const double *)K_.scal, 1, w, K_.N);
         j_ = k;
         enqueue_iteration();
         return true;

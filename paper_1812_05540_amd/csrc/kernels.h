@@ -1641,9 +1641,11 @@ __device__ __forceinline__ void dcgs2_coef(const double *__restrict__ h, int j, 
     t = (h[j] - sp) / alpha;
 }
 
-// The second pass: u <- (u - V_j s) / alpha (the finished v_j), w <- w - V_j p - t v_j, and
-// partial[blk] = |w|^2 over this block's chunk.  Block 0 stores alpha, t in coef[0], coef[1].
-// V is read with non-temporal loads, as in gemv_sub (the last pass over it this iteration).
+// The second pass: u <- (u - V_j s) / alpha (the finished v_j), r = w - V_j p - t v_j, and w
+// <- r / |w| (the next u: scaled by |A z_j| = sqrt(h[j+1]), known before this pass, so that
+// it needs no normalising pass and its scale does not compound); partial[blk] = |r|^2 over
+// this block's chunk.  Block 0 stores alpha, t in coef[0], coef[1].  V is read with
+// non-temporal loads, as in gemv_sub (the last pass over it this iteration).
 __global__ __launch_bounds__(WG) void gemv_sub2(const double *__restrict__ V, size_t ldv, int j,
                                                const double *__restrict__ h, double *__restrict__ u,
                                                double *__restrict__ w, size_t n, int chunk,
@@ -1667,6 +1669,7 @@ __global__ __launch_bounds__(WG) void gemv_sub2(const double *__restrict__ V, si
     }
     __syncthreads();
     const double alpha = at[0], t = at[1];
+    const double naz = sqrt(h[j + 1]);
     size_t i0 = (size_t)blockIdx.x * chunk;
     int len = i0 < n ? (int)((n - i0) < (size_t)chunk ? (n - i0) : (size_t)chunk) : 0;
     double acc = 0.0;
@@ -1679,10 +1682,10 @@ __global__ __launch_bounds__(WG) void gemv_sub2(const double *__restrict__ V, si
             sw += v * hp[k];
         }
         const double vn = (u[i] - su) / alpha;
-        const double wn = (w[i] - sw) - t * vn;
+        const double rn = (w[i] - sw) - t * vn;
         u[i] = vn;
-        w[i] = wn;
-        acc += wn * wn;
+        w[i] = naz > 0.0 ? rn / naz : 0.0;
+        acc += rn * rn;
     }
     acc = block_sum(acc, red);
     if (threadIdx.x == 0) partial[blockIdx.x] = acc;
@@ -1690,11 +1693,11 @@ __global__ __launch_bounds__(WG) void gemv_sub2(const double *__restrict__ V, si
 
 // Hessenberg columns under DCGS2 (column-major H, leading dimension m+1).  Column j - 1 is
 // finished now that u_j's products are known: its first-pass entries raw[0..j-1] gain
-// beta_{j-1} s and h_{j,j-1} = beta_{j-1} alpha (beta_{j-1} in coef[2]); its rotation is kept.
-// Column j's first-pass entries (p, t) replace raw, beta_j = |w| (sum of the chunk partials
-// wpart) goes to coef[2], and the Givens estimate with the unfinished column j -- rotation
-// not kept -- decides whether to stop.  scal out: [0] estimate, [1] beta_j, [2] |A z_j|,
-// [3] breakdown flag; hscal: pinned host copy.
+// c s and h_{j,j-1} = c alpha, c = |A z_{j-1}| (the scale of u_j, in coef[2]); its rotation is
+// kept.  Column j's first-pass entries (p, t) replace raw, |A z_j| goes to coef[2], and the
+// Givens estimate with the unfinished column j (subdiagonal |r_j|, from the chunk partials
+// wpart; rotation not kept) decides whether to stop.  scal out: [0] estimate, [1] |r_j|,
+// [2] |A z_j|, [3] breakdown flag; hscal: pinned host copy.
 __global__ __launch_bounds__(WG) void givens2(int j, int m, const double *__restrict__ h,
                                              double *__restrict__ coef, double *__restrict__ raw,
                                              const double *__restrict__ wpart, int nblk,
@@ -1749,7 +1752,7 @@ __global__ __launch_bounds__(WG) void givens2(int j, int m, const double *__rest
         }
         raw[j] = t;
         const double hn = sqrt(nw2[0]);
-        coef[2] = hn;
+        coef[2] = sqrt(h[j + 1]);
         for (int i = 0; i < j; ++i) col[i] = rw[i];
         col[j] = t;
         col[j + 1] = hn;
@@ -1776,10 +1779,10 @@ __global__ __launch_bounds__(WG) void givens2(int j, int m, const double *__rest
     }
 }
 
-// End of a DCGS2 cycle: column j is finished with u_{j+1} = w / beta_j (beta_j in coef[2])
-// and its reduced products h2[k] = V_k . u_{j+1} (k <= j), h2[j+1] = |u_{j+1}|^2: the
-// first-pass entries raw[0..j] gain beta_j s', h_{j+1,j} = beta_j alpha' with alpha' =
-// sqrt(|u|^2 - s'.s'), and its rotation is kept (g updated).  beta_j = 0: nothing to add.
+// End of a DCGS2 cycle: column j is finished with u_{j+1} = r_j / c, c = |A z_j| (in
+// coef[2]), and its reduced products h2[k] = V_k . u_{j+1} (k <= j), h2[j+1] = |u_{j+1}|^2:
+// the first-pass entries raw[0..j] gain c s', h_{j+1,j} = c alpha' with alpha' =
+// sqrt(|u|^2 - s'.s'), and its rotation is kept (g updated).  c = 0: nothing to add.
 __global__ void givens_finish(int j, int m, const double *__restrict__ h2, const double *__restrict__ coef,
                               const double *__restrict__ raw, double *__restrict__ H, double *__restrict__ cs,
                               double *__restrict__ sn, double *__restrict__ g) {

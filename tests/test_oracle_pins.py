@@ -626,8 +626,8 @@ def test_dcgs2_iterates_equal_cgs2_iterates(restart):
 
 @pytest.mark.parametrize("orth", ORTHS)
 def test_fgmres_orthogonality_under_cancellation(orth):
-    """A flexible preconditioner that returns z_j = z_{j-1} + 1e-9 v_j makes every A z_j lie
-    within 1e-9 of span(V): one classical Gram-Schmidt pass then loses orthogonality
+    """A flexible preconditioner that returns z_j = |v_j| (z_{j-1} / |z_{j-1}| + 1e-9 v_j / |v_j|)
+    makes every A z_j lie within 1e-9 of span(V): one classical Gram-Schmidt pass then loses orthogonality
     completely (checked here), while both two-pass variants keep V orthonormal and
     A Z = V H to rounding.  (Drops the second pass, the normalisation by alpha or the
     s.p term of t in the delayed variant, and this fails.)"""
@@ -638,7 +638,8 @@ def test_fgmres_orthogonality_under_cancellation(orth):
     state = {}
 
     def prec(v):
-        z = v.copy() if "z" not in state else state["z"] + 1e-9 * v
+        nv = np.linalg.norm(v)
+        z = v.copy() if "z" not in state else nv * (state["z"] / np.linalg.norm(state["z"]) + 1e-9 * v / nv)
         state["z"] = z
         return z
 
