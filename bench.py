@@ -239,6 +239,82 @@ def cpu_baseline(s, b, its_gpu, budget_s, args):
 SERVING_SIZES = (16, 24, 32, 48, 64)
 
 
+def per_grid_cases():
+    """The small configuration (8^3, i.i.d. fields) and the first request of each smaller
+    grid size of the serving stream (its own field, its subdomain partition), for the
+    per-grid GPU and oracle timings."""
+    from synth import workload
+    from synth.configs import serving_request, serving_request_spec
+    from synth.jacobian import box_partition
+    s, b = workload(grid=(8, 8, 8), kind="iid", seed=1, rhs_seed=101)
+    cases = [("8^3 i.i.d. (two-phase)", s, b)]
+    for n in SERVING_SIZES[:-1]:
+        i = next(i for i in range(10000) if serving_request_spec(i)[0] == n)
+        s, b = serving_request(i)
+        s.ml_part = box_partition(n, n, n, min(n, 32), min(n, 32), min(n, 16))
+        cases.append(("%d^3 serving request %d" % (n, i), s, b))
+    return cases
+
+
+def run_per_grid(args, cases):
+    """FP32-path solves/s of each case alone (flow setup + solve, best of three, after a
+    device-path setup and one warm-up solve), with the benchmark's options."""
+    import torch
+    from paper_1812_05540_amd import ps
+    ctx = ps.ps_ctx_create(0, 0)
+    out = []
+    try:
+        for label, s, b in cases:
+            sv = ps.Solver(ctx, s, precision=ps.PS_FP32_PREC, ml_sweeps=args.ml_sweeps,
+                           smoother=args.smoother_code, ml_kind=args.ml_kind_code, orth=args.orth_code)
+            sv.setup()
+            bd = torch.as_tensor(b, dtype=torch.float64, device="cuda")
+            x = torch.zeros(s.N, dtype=torch.float64, device="cuda")
+            sv.setup()
+            sv.solve(bd, x, args.rtol)
+            best, res = 1e30, None
+            for _ in range(3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                sv.setup()
+                res = sv.solve(bd, x, args.rtol)
+                torch.cuda.synchronize()
+                best = min(best, time.perf_counter() - t0)
+            sv.close()
+            out.append(dict(grid=label, unknowns=int(s.N), iterations=res["iterations"], status=res["status"],
+                            gpu_solves_per_s=round(1.0 / best, 2)))
+    finally:
+        ps.ps_ctx_destroy(ctx)
+    return out
+
+
+def per_grid_oracle(cases, rows, budget_s, args):
+    """The oracle (one thread) on each case: flow setup + up to two FGMRES iterations,
+    extrapolated to the GPU's iteration count (mechanics AMG excluded); cases stop once
+    the budget is spent."""
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    from oracle import precond as P, amg, Options
+    from oracle.fgmres import fgmres
+    o = Options(smoother=args.smoother, ml_kind=args.ml_kind, ml_sweeps=args.ml_sweeps, orth=args.orth)
+    t_start = time.perf_counter()
+    for (label, s, b), row in zip(cases, rows):
+        if time.perf_counter() - t_start > budget_s:
+            row["oracle"] = "skipped (budget)"
+            continue
+        sdc = amg.build(P.sdc_matrix(s), smoother=args.smoother)
+        t0 = time.perf_counter()
+        st = P.setup(s, o, mechanics=sdc)
+        t_setup = time.perf_counter() - t0
+        A = st.mats["A"]
+        t0 = time.perf_counter()
+        fgmres(lambda v: A @ v, lambda v: P.apply_precond(st, v), b, 1e-30, 100, 2, orth=args.orth)
+        t_it = (time.perf_counter() - t0) / 2
+        v = 1.0 / (t_setup + row["iterations"] * t_it)
+        row["oracle_solves_per_s"] = round(v, 4)
+        row["gpu_over_oracle"] = round(row["gpu_solves_per_s"] / v, 1)
+    return rows
+
+
 def _serving_request(job):
     """Request i of the serving mix (synth.configs.serving_request: grid n^3 drawn from
     16..64, its own seeded random field with sigma ~ U(1, 3), its own rhs; E fixed per grid
@@ -410,6 +486,9 @@ def main():
     ap.add_argument("--serving-clients", type=int, default=6)
     ap.add_argument("--serving-budget-gb", type=float, default=200.0)
     ap.add_argument("--cpu-budget-s", type=float, default=30.0)
+    ap.add_argument("--per-grid", type=int, default=1,
+                    help="1: also time the 8^3 case and one request of each smaller serving grid alone, "
+                         "GPU and oracle")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
@@ -432,7 +511,9 @@ def main():
         t0 = time.perf_counter()
         stream = make_serving_stream(args.serving_requests, args.serving_workers)
         log("serving stream: %d requests generated in %.1fs" % (len(stream), time.perf_counter() - t0))
+    cases = per_grid_cases() if args.per_grid else None
     g = run_gpu(args, s, b)
+    per_grid = run_per_grid(args, cases) if cases else None
     serving = run_serving(args, stream) if stream else None
     head = g.get("fp32") or g.get("fp64")
     line = {
@@ -475,6 +556,10 @@ def main():
         line["serving"] = serving
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(s, b, head["iterations"], args.cpu_budget_s, args)
+        if per_grid:
+            per_grid = per_grid_oracle(cases, per_grid, args.cpu_budget_s, args)
+    if per_grid:
+        line["per_grid"] = per_grid
     print(json.dumps(line), flush=True)
 
 

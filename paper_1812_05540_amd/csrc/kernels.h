@@ -1472,6 +1472,20 @@ __global__ __launch_bounds__(WG) void gemv_sub_mdot(const double *__restrict__ V
     }
 }
 
+// Rotations 0..n-1 applied in order to col[0..n] (in LDS): the updated entry i + 1 is
+// carried in a register from one rotation to the next, so the dependent chain is two
+// multiply-adds per rotation rather than a round trip through LDS.
+__device__ __forceinline__ void rotate_col(double *col, const double *c, const double *s, int n) {
+    double x = col[0];
+    for (int i = 0; i < n; ++i) {
+        const double y = col[i + 1];
+        const double t = c[i] * x + s[i] * y;
+        x = -s[i] * x + c[i] * y;
+        col[i] = t;
+    }
+    col[n] = x;
+}
+
 // Givens update of Hessenberg column j (column-major, leading dimension m+1).
 // h: j+1 orthogonalisation coefficients; naz2[0] = |A z_j|^2; |w|^2 is the sum of the nblk
 // chunk partials wpart, added as reduce_rows adds them (the same bits).
@@ -1504,11 +1518,7 @@ __global__ __launch_bounds__(WG) void givens(int j, int m, const double *__restr
     if (tid == 0) {
         const double hn = sqrt(nw2[0]);
         col[j + 1] = hn;
-        for (int i = 0; i < j; ++i) {
-            double t = c[i] * col[i] + s[i] * col[i + 1];
-            col[i + 1] = -s[i] * col[i] + c[i] * col[i + 1];
-            col[i] = t;
-        }
+        rotate_col(col, c, s, j);
         const double rho = hypot(col[j], col[j + 1]);
         out[1] = hn;
         out[2] = sqrt(naz2[0]);
@@ -1704,7 +1714,7 @@ __global__ __launch_bounds__(WG) void givens2(int j, int m, const double *__rest
                                              double *__restrict__ H, double *__restrict__ cs,
                                              double *__restrict__ sn, double *__restrict__ g,
                                              double *__restrict__ scal, double *__restrict__ hscal) {
-    __shared__ double col[MAXV + 1], c[MAXV], s[MAXV], rw[MAXV + 1];
+    __shared__ double col[MAXV + 1], c[MAXV], s[MAXV], rw[MAXV], hs[MAXV], hp[MAXV], fin[MAXV + 1];
     __shared__ double out[4], red[4];
     __shared__ double nw2[1];
     const int tid = threadIdx.x;
@@ -1714,56 +1724,42 @@ __global__ __launch_bounds__(WG) void givens2(int j, int m, const double *__rest
         a = block_sum(a, red);
         if (tid == 0) nw2[0] = a;
     }
+    // every operand staged in LDS by the workgroup; one thread runs the dependent chains
     for (int i = tid; i < j; i += WG) {
         rw[i] = raw[i];
         c[i] = cs[i];
         s[i] = sn[i];
+        hs[i] = h[j + 2 + i];
+        hp[i] = h[i];
     }
     __syncthreads();
     if (tid == 0) {
-        const double alpha = coef[0], t = coef[1];
+        const double alpha = coef[0], t = coef[1], naz = sqrt(h[j + 1]);
         if (j > 0) {
             const double bp = coef[2];
-            for (int i = 0; i < j; ++i) col[i] = rw[i] + bp * h[j + 2 + i];
-            col[j] = bp * alpha;
-            for (int i = 0; i + 1 < j; ++i) {
-                double r = c[i] * col[i] + s[i] * col[i + 1];
-                col[i + 1] = -s[i] * col[i] + c[i] * col[i + 1];
-                col[i] = r;
-            }
-            const double rho = hypot(col[j - 1], col[j]);
-            const double cj = col[j - 1] / rho, sj = col[j] / rho;
+            for (int i = 0; i < j; ++i) fin[i] = rw[i] + bp * hs[i];
+            fin[j] = bp * alpha;
+            rotate_col(fin, c, s, j - 1);
+            const double rho = hypot(fin[j - 1], fin[j]);
+            const double cj = fin[j - 1] / rho, sj = fin[j] / rho;
             c[j - 1] = cj;
             s[j - 1] = sj;
-            cs[j - 1] = cj;
-            sn[j - 1] = sj;
-            col[j - 1] = rho;
-            col[j] = 0.0;
-            double *hc = H + (size_t)(j - 1) * (m + 1);
-            for (int i = 0; i <= j; ++i) hc[i] = col[i];
+            fin[j - 1] = rho;
+            fin[j] = 0.0;
             const double gj = g[j - 1];
             g[j] = -sj * gj;
             g[j - 1] = cj * gj;
         }
-        // column j as the first pass left it
-        for (int i = 0; i < j; ++i) {
-            rw[i] = h[i];
-            raw[i] = h[i];
-        }
-        raw[j] = t;
+        // column j as the first pass left it, with its estimate (rotation not kept)
         const double hn = sqrt(nw2[0]);
-        coef[2] = sqrt(h[j + 1]);
-        for (int i = 0; i < j; ++i) col[i] = rw[i];
+        coef[2] = naz;
+        for (int i = 0; i < j; ++i) col[i] = hp[i];
         col[j] = t;
         col[j + 1] = hn;
-        for (int i = 0; i < j; ++i) {
-            double r = c[i] * col[i] + s[i] * col[i + 1];
-            col[i + 1] = -s[i] * col[i] + c[i] * col[i + 1];
-            col[i] = r;
-        }
+        rotate_col(col, c, s, j);
         const double rho = hypot(col[j], col[j + 1]);
         out[1] = hn;
-        out[2] = sqrt(h[j + 1]);
+        out[2] = naz;
         if (rho == 0.0) {
             out[0] = fabs(g[j]);
             out[3] = 1.0;
@@ -1771,8 +1767,19 @@ __global__ __launch_bounds__(WG) void givens2(int j, int m, const double *__rest
             out[0] = fabs(col[j + 1] / rho * g[j]);
             out[3] = 0.0;
         }
+        col[j] = t;                 // raw[j]
     }
     __syncthreads();
+    if (j > 0) {
+        double *hc = H + (size_t)(j - 1) * (m + 1);
+        for (int i = tid; i <= j; i += WG) hc[i] = fin[i];
+        if (tid == 0) {
+            cs[j - 1] = c[j - 1];
+            sn[j - 1] = s[j - 1];
+        }
+    }
+    for (int i = tid; i < j; i += WG) raw[i] = hp[i];
+    if (tid == 0) raw[j] = col[j];
     if (tid < 4) {
         scal[tid] = out[tid];
         if (hscal) hscal[tid] = out[tid];
@@ -1800,11 +1807,7 @@ __global__ void givens_finish(int j, int m, const double *__restrict__ h2, const
         const double a2 = h2[j + 1] - ss;
         col[j + 1] = a2 > 0.0 ? bt * sqrt(a2) : 0.0;
     }
-    for (int i = 0; i < j; ++i) {
-        double r = cs[i] * col[i] + sn[i] * col[i + 1];
-        col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
-        col[i] = r;
-    }
+    rotate_col(col, cs, sn, j);
     const double rho = hypot(col[j], col[j + 1]);
     const double cj = col[j] / rho, sj = col[j + 1] / rho;
     cs[j] = cj;

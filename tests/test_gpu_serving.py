@@ -83,16 +83,17 @@ def run_mix(ctx, reqs, **opts):
     return out
 
 
-@pytest.mark.parametrize("precision", [ps.PS_FP64, ps.PS_FP32_PREC])
-def test_results_identical_alone_and_in_mix(reqs, precision):
+@pytest.mark.parametrize("precision,orth", [(ps.PS_FP64, ps.PS_CGS2), (ps.PS_FP32_PREC, ps.PS_CGS2),
+                                            (ps.PS_FP32_PREC, ps.PS_DCGS2)])
+def test_results_identical_alone_and_in_mix(reqs, precision, orth):
     """Every request bitwise equal alone and in the mix, where requests of one grid size
     share step-1 launches (batched V-cycles over the shared mechanics hierarchy)."""
     ps.load()
     ctx = ps.ps_ctx_create(0, 0)
     try:
-        alone = run_alone(ctx, reqs, precision=precision)
+        alone = run_alone(ctx, reqs, precision=precision, orth=orth)
         launches0, _ = ps.ps_ctx_batches(ctx)
-        mix = run_mix(ctx, reqs, precision=precision)
+        mix = run_mix(ctx, reqs, precision=precision, orth=orth)
         launches, covered = ps.ps_ctx_batches(ctx)
     finally:
         ps.ps_ctx_destroy(ctx)

@@ -37,10 +37,12 @@ CASES = [
     (dict(grid=(8, 8, 8), kind="iid", seed=1, rhs_seed=101), dict(precision=ps.PS_FP32_PREC)),
     (dict(grid=(9, 8, 7), kind="iid3", seed=3, rhs_seed=103), dict()),
     (dict(grid=(7, 6, 5), kind="iid3", seed=3, rhs_seed=103), dict(smoother=ps.PS_L1JAC)),
+    (dict(grid=(12, 11, 10), kind="grf", seed=2, rhs_seed=102), dict(precision=ps.PS_FP32_PREC, orth=ps.PS_DCGS2)),
+    (dict(grid=(8, 8, 8), kind="iid", seed=1, rhs_seed=101), dict(orth=ps.PS_DCGS2)),
 ]
 
 
-@pytest.mark.parametrize("first,second", [(0, 1), (2, 3)])
+@pytest.mark.parametrize("first,second", [(0, 1), (2, 3), (4, 5)])
 def test_noalloc_solve_equals_allocating_solve(ctx, first, second):
     for idx in (first, second):                # the second system is smaller than the first
         spec, opts = CASES[idx]
