@@ -43,18 +43,22 @@ def spmv_bytes(s):
     return b + 2 * 8 * s.N
 
 
-def kernel_fingerprint(name):
-    """SHA-256 of a kernel template's source text in kernels.h (from its template line
-    to the next one): recorded with HBM counters so that they are reported only while
-    the kernel is unchanged."""
+def kernel_fingerprint(names):
+    """SHA-256 of the source text in kernels.h of a kernel, or of several (a kernel and
+    the device functions it runs; each from its template line, if any, to its closing
+    brace): recorded with HBM counters so that they are reported only while the kernel
+    is unchanged."""
     import hashlib
     import re
     text = open(os.path.join(ROOT, "paper_1812_05540_amd", "csrc", "kernels.h")).read()
-    m = re.search(r"\ntemplate <[^\n]*>\n__global__[^\n]*\bvoid %s\(" % name, text)
-    if not m:
-        return None
-    end = text.find("\ntemplate <", m.end())
-    return hashlib.sha256(text[m.start():end].encode()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in ([names] if isinstance(names, str) else names):
+        m = re.search(r"\n(?:template <[^\n]*>\n)?__(?:global|device)__[^\n]*\bvoid %s\(" % name, text)
+        if not m:
+            return None
+        end = text.find("\n}\n", m.end())
+        h.update(text[m.start():end + 3].encode())
+    return h.hexdigest()[:16]
 
 
 def recorded_traffic(kernel, profile):
@@ -74,7 +78,7 @@ def recorded_traffic(kernel, profile):
 
 # instrumented kernel -> (kernel template in kernels.h, HBM-counter summary under profiles/)
 KERNEL_SOURCES = {
-    "system_spmv": ("spmv2", "system_spmv_grf64_traffic.md"),
+    "system_spmv": (("spmv2_row", "spmv_sys"), "system_spmv_grf64_traffic.md"),
     "cgs2_project": ("mdot", "cgs2_project_grf64_traffic.md"),
     "cgs2_subtract_project": ("gemv_sub_mdot", "cgs2_fused_grf64_traffic.md"),
     "cgs2_subtract_norm": ("gemv_sub", "cgs2_subtract_grf64_traffic.md"),

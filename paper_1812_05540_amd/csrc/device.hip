@@ -1455,13 +1455,13 @@ static void spmv_full_nf(const DSystem &S, const TX *x, const double *b, double 
     size_t nu = (size_t)3 * S.n_nodes;
     const double N = (double)nu + (double)NF * S.n_cells;
     ktime::Scope ts(ktime::SPMV, st, S.mat_bytes + N * sizeof(TX) + N * 8 * (b ? 2 : 1));
-    if (b) {
-        LAUNCH((k::spmv2<3, 3, NF, TX, true>), grid_for(S.n_nodes), 0, st, S.Auu, x, S.Auf, x + nu, b, y);
-        LAUNCH((k::spmv2<NF, 3, NF, TX, true>), grid_for(S.n_cells), 0, st, S.Afu, x, S.Aff, x + nu, b + nu, y + nu);
-    } else {
-        LAUNCH((k::spmv2<3, 3, NF, TX, false>), grid_for(S.n_nodes), 0, st, S.Auu, x, S.Auf, x + nu, b, y);
-        LAUNCH((k::spmv2<NF, 3, NF, TX, false>), grid_for(S.n_cells), 0, st, S.Afu, x, S.Aff, x + nu, b, y + nu);
-    }
+    const unsigned gn = grid_for(S.n_nodes), g = gn + grid_for(S.n_cells);
+    if (b)
+        LAUNCH((k::spmv_sys<NF, TX, true>), g, 0, st, S.Auu, S.Auf, S.Afu, S.Aff, x, x + nu, b, b + nu, y, y + nu,
+               (int)gn);
+    else
+        LAUNCH((k::spmv_sys<NF, TX, false>), g, 0, st, S.Auu, S.Auf, S.Afu, S.Aff, x, x + nu, b, b, y, y + nu,
+               (int)gn);
 }
 
 template <typename TX>

@@ -78,10 +78,9 @@ __global__ __launch_bounds__(WG) void spmv(Sell<T> A, const TX *__restrict__ x,
 // values are read once per product and bypass the caches (non-temporal loads), which leaves
 // them to the gathered x: 10% faster on MI355X (the plain copy's bandwidth).
 template <int R, int C1, int C2, typename TX, bool RESID>
-__global__ __launch_bounds__(WG) void spmv2(Sell<double> A1, const TX *__restrict__ x1,
-                                           Sell<double> A2, const TX *__restrict__ x2,
-                                           const double *__restrict__ b, double *__restrict__ y) {
-    int pos = blockIdx.x * WG + threadIdx.x;
+__device__ __forceinline__ void spmv2_row(const Sell<double> &A1, const TX *__restrict__ x1,
+                                          const Sell<double> &A2, const TX *__restrict__ x2,
+                                          const double *__restrict__ b, double *__restrict__ y, int pos) {
     if (pos >= A1.nrows) return;
     int lane = pos & 63;
     double acc[R];
@@ -128,6 +127,28 @@ __global__ __launch_bounds__(WG) void spmv2(Sell<double> A1, const TX *__restric
         size_t o = (size_t)pos * R + r;
         y[o] = RESID ? b[o] - acc[r] : acc[r];
     }
+}
+
+template <int R, int C1, int C2, typename TX, bool RESID>
+__global__ __launch_bounds__(WG) void spmv2(Sell<double> A1, const TX *__restrict__ x1,
+                                           Sell<double> A2, const TX *__restrict__ x2,
+                                           const double *__restrict__ b, double *__restrict__ y) {
+    spmv2_row<R, C1, C2, TX, RESID>(A1, x1, A2, x2, b, y, blockIdx.x * WG + threadIdx.x);
+}
+
+// The whole system product in one launch: the first gn workgroups take the node rows
+// ([A_uu A_uf] z), the rest the cell rows ([A_fu A_ff] z), so that the two halves' ramps
+// overlap instead of each launch draining before the next starts.
+template <int NF, typename TX, bool RESID>
+__global__ __launch_bounds__(WG) void spmv_sys(Sell<double> Auu, Sell<double> Auf, Sell<double> Afu,
+                                              Sell<double> Aff, const TX *__restrict__ xu,
+                                              const TX *__restrict__ xf, const double *__restrict__ bu,
+                                              const double *__restrict__ bf, double *__restrict__ yu,
+                                              double *__restrict__ yf, int gn) {
+    if ((int)blockIdx.x < gn)
+        spmv2_row<3, 3, NF, TX, RESID>(Auu, xu, Auf, xf, bu, yu, blockIdx.x * WG + threadIdx.x);
+    else
+        spmv2_row<NF, 3, NF, TX, RESID>(Afu, xu, Aff, xf, bf, yf, (blockIdx.x - gn) * WG + threadIdx.x);
 }
 
 // ------------------------------------------------------------------ AMG level kernels
