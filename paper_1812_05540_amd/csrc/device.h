@@ -154,6 +154,7 @@ struct PresStore {
                                        // in H carry sizes only; cf and dinv are here
     std::vector<signed char *> cf;     // C/F splitting per level (1 C, -1 F)
     std::vector<double *> dinv;        // l1-Jacobi 1 / (a_ii + sum |a_ij|) per level
+    double *cinv = nullptr;            // dense inverse of the coarsest operator, when formed here
     // S_pp formed on the device (quasi-IMPES from the system's A_ff and the fixed-stress
     // terms) once its pattern, A_ff's block pattern, is laid out here (npat rows)
     Arena pat;                         // kept across setups

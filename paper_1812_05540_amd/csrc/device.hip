@@ -874,7 +874,7 @@ static void adopt_hierarchy(DHierarchy<T> &d, const Hierarchy &H, const PresStor
     }
     d.lev[nl - 1].n = H.coarse_n;
     d.cn = H.coarse_n;
-    d.cinv = d.arena.upload(H.coarse_inv.data(), H.coarse_inv.size());
+    d.cinv = S.cinv ? S.cinv : d.arena.upload(H.coarse_inv.data(), H.coarse_inv.size());
     PS_HIP(hipStreamSynchronize(0));
 }
 

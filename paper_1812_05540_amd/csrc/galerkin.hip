@@ -9,6 +9,7 @@
 // increasing inner index, so the coarse operators equal the host build bit for bit.
 // Entries that sum to exactly zero are dropped; columns come out sorted.
 #include <cstring>
+#include <mutex>
 
 #include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/device/device_scan.hpp>
@@ -435,6 +436,140 @@ __global__ void l1_inv_k(const int *__restrict__ rp, const int *__restrict__ ci,
     dinv[i] = __ddiv_rn(1.0, __dadd_rn(diag, s));
 }
 
+
+// ---------------------------------------------------------------- coarsest level
+// Dense inverse of the coarsest operator on the device, operation for operation the host's
+// invert_dense (LU with partial pivoting, ties to the lowest row, rows swapped whole; then
+// the identity's columns solved forward and backward; products and differences rounded
+// separately, as the host compiles them), so that the inverse is bitwise the host's.  One
+// workgroup of DI_WG threads; n <= DI_WG.  With LDS_A the factor and the columns being
+// solved live in LDS (2 n^2 doubles), else in `ga` and inv; inv (row-major) receives the
+// inverse.  flag[0] = 1: singular or not finite, as on the host.
+constexpr int DI_WG = 1024;
+
+template <bool LDS_A>
+__global__ __launch_bounds__(DI_WG) void dense_inverse_k(const int *__restrict__ rp, const int *__restrict__ ci,
+                                                        const double *__restrict__ v, int n, double *ga,
+                                                        double *__restrict__ inv, int *__restrict__ piv,
+                                                        int *__restrict__ flag) {
+    extern __shared__ double lds_a[];
+    double *a = LDS_A ? lds_a : ga;
+    double *X = LDS_A ? lds_a + (size_t)n * n : inv;
+    __shared__ double rv[DI_WG / 64];
+    __shared__ int ri[DI_WG / 64];
+    __shared__ int bad, pc;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const size_t nn = (size_t)n * n;
+    for (size_t e = tid; e < nn; e += DI_WG) a[e] = 0.0;
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    for (int i = tid; i < n; i += DI_WG)
+        for (int t = rp[i]; t < rp[i + 1]; ++t) a[(size_t)i * n + ci[t]] = v[t];
+    __syncthreads();
+    for (int c = 0; c < n; ++c) {
+        // pivot: the first row r >= c with the largest |a_rc| (NaN entries below the
+        // diagonal never win; a NaN on the diagonal makes the matrix singular)
+        const int r = c + tid;
+        double val = -1.0;
+        if (r < n) {
+            const double x = fabs(a[(size_t)r * n + c]);
+            val = (r == c || x == x) ? x : -1.0;
+        }
+        int idx = r < n ? r : n;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ov = __shfl_xor(val, off, 64);
+            const int oi = __shfl_xor(idx, off, 64);
+            if (ov > val || (ov == val && oi < idx)) {
+                val = ov;
+                idx = oi;
+            }
+        }
+        if (lane == 0) {
+            rv[wid] = val;
+            ri[wid] = idx;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double best = rv[0];
+            int p = ri[0];
+            for (int w = 1; w < DI_WG / 64; ++w)
+                if (rv[w] > best || (rv[w] == best && ri[w] < p)) {
+                    best = rv[w];
+                    p = ri[w];
+                }
+            const double dgl = fabs(a[(size_t)c * n + c]);
+            if (dgl != dgl) best = dgl;
+            if (best == 0.0 || !isfinite(best)) bad = 1;
+            pc = p;
+            piv[c] = p;
+        }
+        __syncthreads();
+        if (bad) break;
+        const int p = pc;
+        if (p != c)
+            for (int j = tid; j < n; j += DI_WG) {
+                const double t = a[(size_t)c * n + j];
+                a[(size_t)c * n + j] = a[(size_t)p * n + j];
+                a[(size_t)p * n + j] = t;
+            }
+        __syncthreads();
+        const double d = a[(size_t)c * n + c];
+        for (int rr = c + 1 + tid; rr < n; rr += DI_WG) a[(size_t)rr * n + c] = __ddiv_rn(a[(size_t)rr * n + c], d);
+        __syncthreads();
+        const int m = n - c - 1;
+        for (long long e = tid; e < (long long)m * m; e += DI_WG) {
+            const int rr = c + 1 + (int)(e / m), j = c + 1 + (int)(e % m);
+            const double f = a[(size_t)rr * n + c];
+            if (f != 0.0) a[(size_t)rr * n + j] = __dsub_rn(a[(size_t)rr * n + j], __dmul_rn(f, a[(size_t)c * n + j]));
+        }
+        __syncthreads();
+    }
+    if (bad) {
+        if (tid == 0) flag[0] = 1;
+        return;
+    }
+    // column k of the inverse: P e_k, then L y = P e_k, then U x = y (thread k)
+    // the sums in the host's order (increasing c), their operands loaded eight at a time
+    const int k = tid;
+    if (k < n) {
+        for (int r = 0; r < n; ++r) X[(size_t)r * n + k] = r == k ? 1.0 : 0.0;
+        for (int c = 0; c < n; ++c) {
+            const int p = piv[c];
+            const double t = X[(size_t)c * n + k];
+            X[(size_t)c * n + k] = X[(size_t)p * n + k];
+            X[(size_t)p * n + k] = t;
+        }
+        auto dot_sub = [&](double s, const double *ar, int c0, int c1) {
+            int c = c0;
+            for (; c + 8 <= c1; c += 8) {
+                double av[8], xv[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    av[u] = ar[c + u];
+                    xv[u] = X[(size_t)(c + u) * n + k];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) s = __dsub_rn(s, __dmul_rn(av[u], xv[u]));
+            }
+            for (; c < c1; ++c) s = __dsub_rn(s, __dmul_rn(ar[c], X[(size_t)c * n + k]));
+            return s;
+        };
+        for (int r = 1; r < n; ++r)                                  // L y = P e_k
+            X[(size_t)r * n + k] = dot_sub(X[(size_t)r * n + k], a + (size_t)r * n, 0, r);
+        bool fin = true;
+        for (int r = n - 1; r >= 0; --r) {                           // U x = y
+            const double sr = dot_sub(X[(size_t)r * n + k], a + (size_t)r * n, r + 1, n);
+            const double x = __ddiv_rn(sr, a[(size_t)r * n + r]);
+            X[(size_t)r * n + k] = x;
+            fin = fin && isfinite(x);
+        }
+        if (LDS_A)
+            for (int r = 0; r < n; ++r) inv[(size_t)r * n + k] = X[(size_t)r * n + k];
+        if (!fin) atomicOr(flag, 1);
+    }
+}
+
 }  // namespace
 
 void spgemm_device(const DevCsr &A, const DevCsr &B, DevCsr &C, Arena &out, Arena &tmp, hipStream_t st) {
@@ -740,12 +875,49 @@ static void build_pressure_levels(DevCsr A, const Options &o, Hierarchy &H, Pres
         A = Ac;
     }
     S.A.push_back(A);
-    if (read_back(zdiag, st) != 0) throw Error(PS_ESINGULAR, "zero diagonal in an AMG level");
-    coarse_level(download(A), H);
+    if (A.n > DI_WG) {                    // dense inverse on the host (beyond one workgroup)
+        if (read_back(zdiag, st) != 0) throw Error(PS_ESINGULAR, "zero diagonal in an AMG level");
+        coarse_level(download(A), H);
+        return;
+    }
+    // the coarsest level's dense inverse on the device (bitwise the host's); one read-back
+    // brings the zero-diagonal flag and the inverse's singularity flag together
+    int *iflag = ctr + 2;
+    zero(iflag, 1);
+    const size_t an = (size_t)A.n * A.n;
+    S.cinv = S.arena.alloc<double>(an);
+    int *piv = S.work.alloc<int>((size_t)A.n + 1);
+    if (2 * an * sizeof(double) <= (size_t)150 * 1024) {
+        // the factor and the solved columns in LDS: allow up to 150 KB (once per process)
+        static std::once_flag raised;
+        std::call_once(raised, [] {
+            PS_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&dense_inverse_k<true>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024));
+        });
+        hipLaunchKernelGGL((dense_inverse_k<true>), dim3(1), dim3(DI_WG), 2 * an * sizeof(double), st, A.rp, A.ci,
+                           A.v, A.n, (double *)nullptr, S.cinv, piv, iflag);
+    } else {
+        double *ga = S.work.alloc<double>(an);
+        hipLaunchKernelGGL((dense_inverse_k<false>), dim3(1), dim3(DI_WG), 0, st, A.rp, A.ci, A.v, A.n, ga, S.cinv, piv,
+                           iflag);
+    }
+    PS_HIP(hipGetLastError());
+    struct Flags {
+        int zdiag, singular;
+    };
+    const Flags fl = read_back(reinterpret_cast<const Flags *>(zdiag), st);
+    if (fl.zdiag != 0) throw Error(PS_ESINGULAR, "zero diagonal in an AMG level");
+    if (fl.singular != 0) throw Error(PS_ESINGULAR, "singular coarsest AMG matrix");
+    Level C;
+    C.A.n = C.A.m = A.n;
+    C.cf.assign(A.n, 0);
+    H.coarse_n = A.n;
+    H.lev.push_back(std::move(C));
 }
 
 static void clear_store(Hierarchy &H, PresStore &S) {
     H = Hierarchy();
+    S.cinv = nullptr;
     S.arena.recycle();
     S.A.clear();
     S.P.clear();
