@@ -412,9 +412,10 @@ def test_solves_are_deterministic(ctx, orth):
     sv.close()
 
 
-def test_edge_cases(ctx):
+@pytest.mark.parametrize("orth", [ps.PS_CGS2, ps.PS_DCGS2])
+def test_edge_cases(ctx, orth):
     s, b = small("iid8")
-    sv = ps.Solver(ctx, s)
+    sv = ps.Solver(ctx, s, orth=orth)
     x = dev(np.zeros(s.N))
     r = sv.solve(dev(b), x, 1e-8)
     assert r["status"] == ps.PS_ENOTSETUP
@@ -433,11 +434,30 @@ def test_edge_cases(ctx):
     assert r["status"] == ps.PS_EINVAL
     sv.close()
     # iteration cap: status EMAXIT with the last iterate, which has reduced the residual
-    sv = make_solver(ctx, s, maxit=3)
+    sv = make_solver(ctx, s, maxit=3, orth=orth)
     x = dev(np.zeros(s.N))
     r = sv.solve(dev(b), x, 1e-12)
     assert r["status"] == ps.PS_EMAXIT and r["iterations"] == 3 and r["rel_residual"] < 1.0
     sv.close()
+
+
+@pytest.mark.parametrize("restart", [1, 2, 3])
+def test_dcgs2_shortest_restart_lengths_match_oracle(ctx, restart):
+    """Restart lengths 1-3 (twelve iterations, so four to twelve cycles): every cycle ends
+    right after its first columns, so the last column is finished at nearly every
+    iteration (the delayed pass's corner cases).  The iterate after twelve iterations
+    against the oracle's."""
+    s, b = small("iid8")
+    out = oracle_solve(s, b, rtol=1e-30, opts=oracle_opts(restart=restart, maxit=12, orth=ps.PS_DCGS2))
+    sv = make_solver(ctx, s, restart=restart, maxit=12, orth=ps.PS_DCGS2)
+    x = dev(np.zeros(s.N))
+    r = sv.solve(dev(b), x, 1e-30)
+    sv.close()
+    assert out["status"] == -6 and r["status"] == ps.PS_EMAXIT and r["iterations"] == 12
+    assert r["restarts"] == out["restarts"]
+    err = np.linalg.norm(host(x) - out["x"]) / np.linalg.norm(out["x"])
+    assert err <= 1e-9, err
+    assert abs(r["rel_residual"] - out["rel_residual"]) <= 1e-9 * out["rel_residual"]
 
 
 @pytest.mark.parametrize("orth", [ps.PS_CGS2, ps.PS_DCGS2])
