@@ -20,6 +20,36 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Wavefront sum without LDS traffic: pair, quad, half-row and row sums with DPP lane moves
+// (each lane adds its partner's value, so both partners hold the same bits), then the four
+// 16-lane row sums read from lanes 0, 16, 32, 48 and added as (r0 + r1) + (r2 + r3).  The
+// result is wave-uniform.  Needs every lane of the wavefront active.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xF, 0xF, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+template <int LANE>
+__device__ __forceinline__ double readlane_f64(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, LANE);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), LANE);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+    v += dpp_f64<0xB1>(v);     // quad_perm [1,0,3,2]: lane ^ 1
+    v += dpp_f64<0x4E>(v);     // quad_perm [2,3,0,1]: lane ^ 2
+    v += dpp_f64<0x141>(v);    // row_half_mirror: lane 7 - i within eight
+    v += dpp_f64<0x140>(v);    // row_mirror: lane 15 - i within sixteen
+    const double r0 = readlane_f64<0>(v), r1 = readlane_f64<16>(v);
+    const double r2 = readlane_f64<32>(v), r3 = readlane_f64<48>(v);
+    return (r0 + r1) + (r2 + r3);
+}
+
 // Deterministic block sum (WG threads): fixed shuffle tree per wave, then the four
 // wave sums added in wave order by thread 0.  Result valid in thread 0 only.
 __device__ __forceinline__ double block_sum(double v, double *red) {
@@ -1356,12 +1386,12 @@ __global__ __launch_bounds__(WG) void mdot(const double *__restrict__ V, size_t 
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             if (q < kk) {
-                const double r = wave_sum(a[q]);
+                const double r = wave_sum_dpp(a[q]);
                 if (lane == 0) red[wid][k0 + q] = r;
             }
         }
         if (wnorm) {
-            const double r = wave_sum(an);
+            const double r = wave_sum_dpp(an);
             if (lane == 0) red[wid][nv] = r;
         }
     }
@@ -1639,8 +1669,8 @@ __global__ __launch_bounds__(WG) void mdot2(const double *__restrict__ V, size_t
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             if (q < kk) {
-                const double ra = wave_sum(a[q]);
-                const double rc = wave_sum(c[q]);
+                const double ra = wave_sum_dpp(a[q]);
+                const double rc = wave_sum_dpp(c[q]);
                 if (lane == 0) {
                     red[wid][k0 + q] = ra;
                     red[wid][nv + 1 + k0 + q] = rc;
@@ -1648,7 +1678,7 @@ __global__ __launch_bounds__(WG) void mdot2(const double *__restrict__ V, size_t
             }
         }
         if (wnorm) {
-            const double r = wave_sum(an);
+            const double r = wave_sum_dpp(an);
             if (lane == 0) red[wid][nv] = r;
         }
     }
