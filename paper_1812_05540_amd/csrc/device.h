@@ -330,8 +330,9 @@ void totals(int id, long long &launches, double &seconds, double &bytes);
 struct Krylov {                   // FGMRES workspace (FP64 basis, Z in the precond type)
     int m = 0, nblk = 0, chunk = 0;
     size_t N = 0;
+    size_t ldv = 0;               // basis stride: N rounded up to 32 (256-byte aligned vectors)
     bool z_fp32 = false;
-    double *V = nullptr;          // (m+1) x N
+    double *V = nullptr;          // (m+1) x ldv
     void *Z = nullptr;            // m x N (double or float)
     double *H = nullptr;          // (m+1) x m, column-major, Givens-rotated
     double *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr;

@@ -1486,7 +1486,8 @@ static void layout_krylov(Krylov &K, size_t N, int m, bool z_fp32, Take take) {
     size_t chunk = (N + K.nblk - 1) / K.nblk;
     K.chunk = (int)((chunk + 63) / 64 * 64);
     auto d = [&](size_t n) { return static_cast<double *>(take(n * sizeof(double))); };
-    K.V = d((size_t)(m + 1) * N);
+    K.ldv = (N + 31) / 32 * 32;
+    K.V = d((size_t)(m + 1) * K.ldv);
     K.Z = take((size_t)m * N * (z_fp32 ? sizeof(float) : sizeof(double)));
     K.H = d((size_t)(m + 1) * m);
     K.cs = d(m);
@@ -1545,13 +1546,13 @@ static void launch_mdot(const Krylov &K, const double *V, int nv, const double *
     bool lds = K.chunk <= 7680;          // <= 60 KB of LDS per workgroup
     size_t shm = lds ? (size_t)K.chunk * sizeof(double) : 0;
     if (norm && lds)
-        LAUNCH((k::mdot<true, true>), K.nblk, shm, st, V, K.N, nv, w, K.N, K.chunk, K.partial, K.nblk);
+        LAUNCH((k::mdot<true, true>), K.nblk, shm, st, V, K.ldv, nv, w, K.N, K.chunk, K.partial, K.nblk);
     else if (norm)
-        LAUNCH((k::mdot<true, false>), K.nblk, shm, st, V, K.N, nv, w, K.N, K.chunk, K.partial, K.nblk);
+        LAUNCH((k::mdot<true, false>), K.nblk, shm, st, V, K.ldv, nv, w, K.N, K.chunk, K.partial, K.nblk);
     else if (lds)
-        LAUNCH((k::mdot<false, true>), K.nblk, shm, st, V, K.N, nv, w, K.N, K.chunk, K.partial, K.nblk);
+        LAUNCH((k::mdot<false, true>), K.nblk, shm, st, V, K.ldv, nv, w, K.N, K.chunk, K.partial, K.nblk);
     else
-        LAUNCH((k::mdot<false, false>), K.nblk, shm, st, V, K.N, nv, w, K.N, K.chunk, K.partial, K.nblk);
+        LAUNCH((k::mdot<false, false>), K.nblk, shm, st, V, K.ldv, nv, w, K.N, K.chunk, K.partial, K.nblk);
 }
 
 // out[0] <- |w|^2 (deterministic)
@@ -1597,7 +1598,7 @@ void Fgmres::begin_cycle(const double *r) {
 
 void Fgmres::enqueue_iteration() {
     const size_t N = K_.N;
-    double *Vj = K_.V + (size_t)j_ * N;
+    double *Vj = K_.V + (size_t)j_ * K_.ldv;
     size_t esz = K_.z_fp32 ? sizeof(float) : sizeof(double);
     void *zj = (char *)K_.Z + (size_t)j_ * N * esz;
     if (defer_ && M_.can_split()) {                                     // step 1 by the caller
@@ -1613,7 +1614,7 @@ void Fgmres::enqueue_iteration() {
 void Fgmres::finish_iteration() {
     if (!pending_) return;
     const size_t N = K_.N;
-    M_.post(K_.V + (size_t)j_ * N, s1_z_, st_);                         // steps 2-8
+    M_.post(K_.V + (size_t)j_ * K_.ldv, s1_z_, st_);                    // steps 2-8
     pending_ = false;
     rest_of_iteration();
 }
@@ -1621,7 +1622,7 @@ void Fgmres::finish_iteration() {
 void Fgmres::rest_of_iteration() {
     const int j = j_, m = K_.m, nv = j + 1;
     const size_t N = K_.N;
-    double *w = K_.V + (size_t)(j + 1) * N;
+    double *w = K_.V + (size_t)(j + 1) * K_.ldv;
     size_t esz = K_.z_fp32 ? sizeof(float) : sizeof(double);
     void *zj = (char *)K_.Z + (size_t)j * N * esz;
     if (K_.z_fp32) spmv_full<float>(S_, (const float *)zj, nullptr, w, st_);   // w = A z_j
@@ -1646,8 +1647,8 @@ void Fgmres::rest_of_iteration() {
         // above; at most 32 vectors RW = 8 throughout is as fast as the finer choice)
         auto fused = [&](auto rwc) {
             constexpr int RW = decltype(rwc)::value;
-            LAUNCH((k::gemv_sub_mdot<RW>), K_.nblk, shm, st_, (const double *)K_.V, N, nv, (const double *)K_.h1, w,
-                   N, K_.chunk, K_.partial, K_.nblk);
+            LAUNCH((k::gemv_sub_mdot<RW>), K_.nblk, shm, st_, (const double *)K_.V, K_.ldv, nv,
+                   (const double *)K_.h1, w, N, K_.chunk, K_.partial, K_.nblk);
         };
         switch ((nv + 7) / 8) {
         case 2:
@@ -1665,15 +1666,15 @@ void Fgmres::rest_of_iteration() {
         default: fused(std::integral_constant<int, 28>{}); break;
         }
     } else {
-        LAUNCH((k::gemv_sub<false>), K_.nblk, 0, st_, (const double *)K_.V, N, nv, (const double *)K_.h1, w, N,
-               K_.chunk, K_.partial);
+        LAUNCH((k::gemv_sub<false>), K_.nblk, 0, st_, (const double *)K_.V, K_.ldv, nv, (const double *)K_.h1, w,
+               N, K_.chunk, K_.partial);
         launch_mdot(K_, K_.V, nv, w, false, st_);
     }
     LAUNCH(k::reduce_rows, nv, 0, st_, (const double *)K_.partial, K_.nblk, K_.h2, (const double *)K_.h1, K_.hsum);
     {
         ktime::Scope ts(ktime::CGS2_SUBTRACT, st_, (nv + 2) * vb);
-        LAUNCH((k::gemv_sub<true>), K_.nblk, 0, st_, (const double *)K_.V, N, nv, (const double *)K_.h2, w, N,
-               K_.chunk, K_.partial);
+        LAUNCH((k::gemv_sub<true>), K_.nblk, 0, st_, (const double *)K_.V, K_.ldv, nv, (const double *)K_.h2, w,
+               N, K_.chunk, K_.partial);
     }
     LAUNCH(k::givens, 1, 0, st_, j, m, (const double *)K_.hsum, (const double *)(K_.h1 + nv),
            (const double *)K_.partial, K_.nblk, K_.H, K_.cs, K_.sn, K_.g, K_.scal, K_.hostscal);
@@ -1686,25 +1687,25 @@ void Fgmres::rest_of_iteration() {
 void Fgmres::rest_dcgs2() {
     const int j = j_, m = K_.m, nv = j + 1;
     const size_t N = K_.N;
-    double *u = K_.V + (size_t)j * N, *w = u + N;
+    double *u = K_.V + (size_t)j * K_.ldv, *w = u + K_.ldv;
     const double vb = (double)N * 8;
     {
         ktime::Scope ts(ktime::DCGS2_PROJECT, st_, (nv + 1) * vb);
         const bool lds = K_.chunk <= 3840;           // w and u: <= 60 KB of LDS
         const size_t shm = lds ? 2 * (size_t)K_.chunk * sizeof(double) : 0;
         if (lds)
-            LAUNCH((k::mdot2<true>), K_.nblk, shm, st_, (const double *)K_.V, N, nv, (const double *)w, N, K_.chunk,
-                   K_.partial, K_.nblk);
+            LAUNCH((k::mdot2<true>), K_.nblk, shm, st_, (const double *)K_.V, K_.ldv, nv, (const double *)w, N,
+                   K_.chunk, K_.partial, K_.nblk);
         else
-            LAUNCH((k::mdot2<false>), K_.nblk, shm, st_, (const double *)K_.V, N, nv, (const double *)w, N,
+            LAUNCH((k::mdot2<false>), K_.nblk, shm, st_, (const double *)K_.V, K_.ldv, nv, (const double *)w, N,
                    K_.chunk, K_.partial, K_.nblk);
     }
     LAUNCH(k::reduce_rows, 2 * nv + 1, 0, st_, (const double *)K_.partial, K_.nblk, K_.h1,
            (const double *)nullptr, (double *)nullptr);
     {
         ktime::Scope ts(ktime::DCGS2_SUBTRACT, st_, (nv + 3) * vb);
-        LAUNCH(k::gemv_sub2, K_.nblk, 0, st_, (const double *)K_.V, N, j, (const double *)K_.h1, u, w, N, K_.chunk,
-               K_.partial, K_.coef);
+        LAUNCH(k::gemv_sub2, K_.nblk, 0, st_, (const double *)K_.V, K_.ldv, j, (const double *)K_.h1, u, w, N,
+               K_.chunk, K_.partial, K_.coef);
     }
     LAUNCH(k::givens2, 1, 0, st_, j, m, (const double *)K_.h1, K_.coef, K_.raw, (const double *)K_.partial,
            K_.nblk, K_.H, K_.cs, K_.sn, K_.g, K_.scal, K_.hostscal);
@@ -1716,7 +1717,7 @@ void Fgmres::rest_dcgs2() {
 // and its norm, then column k - 1 finished and its rotation kept.
 void Fgmres::finish_last_column(int k) {
     const size_t N = K_.N;
-    double *w = K_.V + (size_t)k * N;
+    double *w = K_.V + (size_t)k * K_.ldv;
     launch_mdot(K_, K_.V, k, w, true, st_);
     LAUNCH(k::reduce_rows, k + 1, 0, st_, (const double *)K_.partial, K_.nblk, K_.h2, (const double *)nullptr,
            (double *)nullptr);
@@ -1782,7 +1783,7 @@ bool Fgmres::advance() {
             end_cycle(k);
             return true;
         }
-        double *w = K_.V + (size_t)k * K_.N;
+        double *w = K_.V + (size_t)k * K_.ldv;
         if (orth_ != PS_DCGS2)                       // DCGS2: gemv_sub2 wrote u_k already scaled
             LAUNCH(k::scale_div, grid_for(K_.N), 0, st_, (const double *)w, (const double *)K_.scal, 1, w, K_.N);
         j_ = k;

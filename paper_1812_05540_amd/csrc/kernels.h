@@ -1608,14 +1608,17 @@ __global__ __launch_bounds__(WG) void givens(int j, int m, const double *__restr
 //   h[2j+2] = u . u).
 
 // partial rows (nv = j + 1): k < nv: V_k . w; nv: w . w; nv + 1 + k: V_k . u, over this
-// block's chunk.  Same structure as mdot (eight vectors per pass, three elements per thread
-// per step, fixed-order combination of the four waves); w and u are staged in LDS.
+// block's chunk.  Eight vectors per pass; each thread takes element pairs (16-byte loads:
+// a chunk starts at an even row and the basis vectors at 256-byte boundaries), two pairs
+// per step, all loads of a step issued before any is used; fixed-order combination of the
+// four waves; w and u are staged in LDS.  A pair past an odd chunk end reads the element
+// after it (the basis stride's padding, or unused LDS) without adding it.
 template <bool LDSW>
-__global__ __launch_bounds__(WG) void mdot2(const double *__restrict__ V, size_t ldv, int nv,
+__global__ __launch_bounds__(WG, 4) void mdot2(const double *__restrict__ V, size_t ldv, int nv,
                                            const double *__restrict__ w, size_t n, int chunk,
                                            double *__restrict__ partial, int nblk) {
-    constexpr int U = 3;
-    extern __shared__ double sw[];
+    constexpr int U = 2;
+    extern __shared__ __align__(16) double sw[];
     __shared__ double red[4][2 * MAXV + 2];
     size_t i0 = (size_t)blockIdx.x * chunk;
     int len = i0 < n ? (int)((n - i0) < (size_t)chunk ? (n - i0) : (size_t)chunk) : 0;
@@ -1628,25 +1631,27 @@ __global__ __launch_bounds__(WG) void mdot2(const double *__restrict__ V, size_t
         }
         __syncthreads();
     }
-    const double *ws = LDSW ? sw : wb;
-    const double *us = LDSW ? sw + chunk : ub;
+    const double2 *ws = reinterpret_cast<const double2 *>(LDSW ? sw : wb);
+    const double2 *us = reinterpret_cast<const double2 *>(LDSW ? sw + chunk : ub);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int np = (len + 1) >> 1;
     const int npass = (nv + 7) / 8;
     for (int p = 0; p < npass; ++p) {
         const int k0 = 8 * p, kk = nv - k0 < 8 ? nv - k0 : 8;
         const bool wnorm = p == 0;
         // rows past nv re-read row k0 (in bounds, unused): every load is unconditional
-        const double *v[8];
+        const double2 *v[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) v[q] = V + (size_t)(q < kk ? k0 + q : k0) * ldv + i0;
+        for (int q = 0; q < 8; ++q)
+            v[q] = reinterpret_cast<const double2 *>(V + (size_t)(q < kk ? k0 + q : k0) * ldv + i0);
         double a[8], c[8], an = 0.0;
 #pragma unroll
         for (int q = 0; q < 8; ++q) a[q] = c[q] = 0.0;
-        for (int t0 = threadIdx.x; t0 < len; t0 += U * WG) {
-            double x[U][8], wt[U], ut[U];
+        for (int t0 = threadIdx.x; t0 < np; t0 += U * WG) {
+            double2 x[U][8], wt[U], ut[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int t = t0 + u * WG, tc = t < len ? t : len - 1;
+                const int t = t0 + u * WG, tc = t < np ? t : np - 1;
                 wt[u] = ws[tc];
                 ut[u] = us[tc];
 #pragma unroll
@@ -1654,15 +1659,24 @@ __global__ __launch_bounds__(WG) void mdot2(const double *__restrict__ V, size_t
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                if (t0 + u * WG < len) {
+                const int t = t0 + u * WG;
+                if (t < np) {
+                    const bool hi = 2 * t + 1 < len;
 #pragma unroll
                     for (int q = 0; q < 8; ++q) {
                         if (q < kk) {
-                            a[q] += x[u][q] * wt[u];
-                            c[q] += x[u][q] * ut[u];
+                            a[q] += x[u][q].x * wt[u].x;
+                            c[q] += x[u][q].x * ut[u].x;
+                            if (hi) {
+                                a[q] += x[u][q].y * wt[u].y;
+                                c[q] += x[u][q].y * ut[u].y;
+                            }
                         }
                     }
-                    if (wnorm) an += wt[u] * wt[u];
+                    if (wnorm) {
+                        an += wt[u].x * wt[u].x;
+                        if (hi) an += wt[u].y * wt[u].y;
+                    }
                 }
             }
         }
