@@ -1721,6 +1721,8 @@ __device__ __forceinline__ void dcgs2_coef(const double *__restrict__ h, int j, 
 // it needs no normalising pass and its scale does not compound); partial[blk] = |r|^2 over
 // this block's chunk.  Block 0 stores alpha, t in coef[0], coef[1].  V is read with
 // non-temporal loads, as in gemv_sub (the last pass over it this iteration).
+typedef double vd2 __attribute__((ext_vector_type(2)));
+
 __global__ __launch_bounds__(WG) void gemv_sub2(const double *__restrict__ V, size_t ldv, int j,
                                                const double *__restrict__ h, double *__restrict__ u,
                                                double *__restrict__ w, size_t n, int chunk,
@@ -1747,20 +1749,34 @@ __global__ __launch_bounds__(WG) void gemv_sub2(const double *__restrict__ V, si
     const double naz = sqrt(h[j + 1]);
     size_t i0 = (size_t)blockIdx.x * chunk;
     int len = i0 < n ? (int)((n - i0) < (size_t)chunk ? (n - i0) : (size_t)chunk) : 0;
+    // element pairs per thread (16-byte loads: a chunk starts at an even row and the basis
+    // vectors at 256-byte boundaries); each element's sums run over k in increasing order.
+    // A pair past an odd chunk end reads the element after it (the basis stride's padding)
+    // and neither stores nor adds it.
     double acc = 0.0;
-    for (int e = threadIdx.x; e < len; e += WG) {
-        const size_t i = i0 + e;
-        double su = 0.0, sw = 0.0;
+    const int np = (len + 1) >> 1;
+    for (int e = threadIdx.x; e < np; e += WG) {
+        const size_t i = i0 + 2 * (size_t)e;
+        const bool hi = 2 * e + 1 < len;
+        vd2 su = {0.0, 0.0}, sw = {0.0, 0.0};
         for (int k = 0; k < j; ++k) {
-            const double v = __builtin_nontemporal_load(&V[(size_t)k * ldv + i]);
+            const vd2 v = __builtin_nontemporal_load(reinterpret_cast<const vd2 *>(&V[(size_t)k * ldv + i]));
             su += v * hs[k];
             sw += v * hp[k];
         }
-        const double vn = (u[i] - su) / alpha;
-        const double rn = (w[i] - sw) - t * vn;
-        u[i] = vn;
-        w[i] = naz > 0.0 ? rn / naz : 0.0;
-        acc += rn * rn;
+        const vd2 uu = *reinterpret_cast<const vd2 *>(&u[i]), ww = *reinterpret_cast<const vd2 *>(&w[i]);
+        const double vn0 = (uu.x - su.x) / alpha, vn1 = (uu.y - su.y) / alpha;
+        const double rn0 = (ww.x - sw.x) - t * vn0, rn1 = (ww.y - sw.y) - t * vn1;
+        const double wn0 = naz > 0.0 ? rn0 / naz : 0.0, wn1 = naz > 0.0 ? rn1 / naz : 0.0;
+        if (hi) {
+            *reinterpret_cast<vd2 *>(&u[i]) = vd2{vn0, vn1};
+            *reinterpret_cast<vd2 *>(&w[i]) = vd2{wn0, wn1};
+        } else {
+            u[i] = vn0;
+            w[i] = wn0;
+        }
+        acc += rn0 * rn0;
+        if (hi) acc += rn1 * rn1;
     }
     acc = block_sum(acc, red);
     if (threadIdx.x == 0) partial[blockIdx.x] = acc;
