@@ -1612,7 +1612,8 @@ __global__ __launch_bounds__(WG) void givens(int j, int m, const double *__restr
 // a chunk starts at an even row and the basis vectors at 256-byte boundaries), two pairs
 // per step, all loads of a step issued before any is used; fixed-order combination of the
 // four waves; w and u are staged in LDS.  A pair past an odd chunk end reads the element
-// after it (the basis stride's padding, or unused LDS) without adding it.
+// after it (the basis stride's padding, or unused LDS) without adding it.  Launch bounds ask
+// for four waves per SIMD (at most 128 VGPRs; unbounded, the pair loads take 138).
 template <bool LDSW>
 __global__ __launch_bounds__(WG, 4) void mdot2(const double *__restrict__ V, size_t ldv, int nv,
                                            const double *__restrict__ w, size_t n, int chunk,
