@@ -468,32 +468,35 @@ __global__ __launch_bounds__(DI_WG) void dense_inverse_k(const int *__restrict__
     __syncthreads();
     for (int c = 0; c < n; ++c) {
         // pivot: the first row r >= c with the largest |a_rc| (NaN entries below the
-        // diagonal never win; a NaN on the diagonal makes the matrix singular)
-        const int r = c + tid;
-        double val = -1.0;
-        if (r < n) {
-            const double x = fabs(a[(size_t)r * n + c]);
-            val = (r == c || x == x) ? x : -1.0;
-        }
-        int idx = r < n ? r : n;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            const double ov = __shfl_xor(val, off, 64);
-            const int oi = __shfl_xor(idx, off, 64);
-            if (ov > val || (ov == val && oi < idx)) {
-                val = ov;
-                idx = oi;
+        // diagonal never win; a NaN on the diagonal makes the matrix singular); only the
+        // wavefronts holding rows c..n-1 search
+        const int r = c + tid, nwv = (n - c + 63) / 64;
+        if (wid < nwv) {
+            double val = -1.0;
+            if (r < n) {
+                const double x = fabs(a[(size_t)r * n + c]);
+                val = (r == c || x == x) ? x : -1.0;
             }
-        }
-        if (lane == 0) {
-            rv[wid] = val;
-            ri[wid] = idx;
+            int idx = r < n ? r : n;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                const double ov = __shfl_xor(val, off, 64);
+                const int oi = __shfl_xor(idx, off, 64);
+                if (ov > val || (ov == val && oi < idx)) {
+                    val = ov;
+                    idx = oi;
+                }
+            }
+            if (lane == 0) {
+                rv[wid] = val;
+                ri[wid] = idx;
+            }
         }
         __syncthreads();
         if (tid == 0) {
             double best = rv[0];
             int p = ri[0];
-            for (int w = 1; w < DI_WG / 64; ++w)
+            for (int w = 1; w < nwv; ++w)
                 if (rv[w] > best || (rv[w] == best && ri[w] < p)) {
                     best = rv[w];
                     p = ri[w];
@@ -517,11 +520,13 @@ __global__ __launch_bounds__(DI_WG) void dense_inverse_k(const int *__restrict__
         const double d = a[(size_t)c * n + c];
         for (int rr = c + 1 + tid; rr < n; rr += DI_WG) a[(size_t)rr * n + c] = __ddiv_rn(a[(size_t)rr * n + c], d);
         __syncthreads();
-        const int m = n - c - 1;
-        for (long long e = tid; e < (long long)m * m; e += DI_WG) {
-            const int rr = c + 1 + (int)(e / m), j = c + 1 + (int)(e % m);
+        // trailing update on a 32 x 32 thread layout (rows tid / 32 + 32 k, columns tid % 32
+        // + 32 l): no index division; each element gets the one update of this step
+        for (int rr = c + 1 + (tid >> 5); rr < n; rr += DI_WG / 32) {
             const double f = a[(size_t)rr * n + c];
-            if (f != 0.0) a[(size_t)rr * n + j] = __dsub_rn(a[(size_t)rr * n + j], __dmul_rn(f, a[(size_t)c * n + j]));
+            if (f != 0.0)
+                for (int j = c + 1 + (tid & 31); j < n; j += 32)
+                    a[(size_t)rr * n + j] = __dsub_rn(a[(size_t)rr * n + j], __dmul_rn(f, a[(size_t)c * n + j]));
         }
         __syncthreads();
     }
