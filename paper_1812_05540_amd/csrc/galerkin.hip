@@ -447,6 +447,55 @@ __global__ void l1_inv_k(const int *__restrict__ rp, const int *__restrict__ ci,
 // inverse.  flag[0] = 1: singular or not finite, as on the host.
 constexpr int DI_WG = 1024;
 
+// The best (largest value, then lowest index) of a wavefront's (val, idx) pairs, in every
+// lane: DPP moves within rows of 16 lanes (pair, quad, half-row, row), then the four rows'
+// bests read from lanes 0, 16, 32, 48.  The rule is a total order on distinct indices, so
+// the order of the steps cannot change the result.  Needs every lane active.
+__device__ __forceinline__ bool di_better(double v1, int i1, double v0, int i0) {
+    return v1 > v0 || (v1 == v0 && i1 < i0);
+}
+
+template <int CTRL>
+__device__ __forceinline__ void di_step(double &val, int &idx) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, val);
+    const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xF, 0xF, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+    const double ov = __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+    const int oi = __builtin_amdgcn_mov_dpp(idx, CTRL, 0xF, 0xF, false);
+    if (di_better(ov, oi, val, idx)) {
+        val = ov;
+        idx = oi;
+    }
+}
+
+__device__ __forceinline__ void di_wave_best(double &val, int &idx) {
+    di_step<0xB1>(val, idx);     // lane ^ 1
+    di_step<0x4E>(val, idx);     // lane ^ 2
+    di_step<0x141>(val, idx);    // 7 - i within eight
+    di_step<0x140>(val, idx);    // 15 - i within sixteen
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, val);
+    double bv = val;
+    int bi = idx;
+    auto lane_of = [&](int l, double &v, int &i) {
+        const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+        const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+        v = __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+        i = __builtin_amdgcn_readlane(idx, l);
+    };
+    lane_of(0, bv, bi);
+    for (int l = 16; l < 64; l += 16) {
+        double v;
+        int i;
+        lane_of(l, v, i);
+        if (di_better(v, i, bv, bi)) {
+            bv = v;
+            bi = i;
+        }
+    }
+    val = bv;
+    idx = bi;
+}
+
 template <bool LDS_A>
 __global__ __launch_bounds__(DI_WG) void dense_inverse_k(const int *__restrict__ rp, const int *__restrict__ ci,
                                                         const double *__restrict__ v, int n, double *ga,
@@ -478,15 +527,7 @@ __global__ __launch_bounds__(DI_WG) void dense_inverse_k(const int *__restrict__
                 val = (r == c || x == x) ? x : -1.0;
             }
             int idx = r < n ? r : n;
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                const double ov = __shfl_xor(val, off, 64);
-                const int oi = __shfl_xor(idx, off, 64);
-                if (ov > val || (ov == val && oi < idx)) {
-                    val = ov;
-                    idx = oi;
-                }
-            }
+            di_wave_best(val, idx);
             if (lane == 0) {
                 rv[wid] = val;
                 ri[wid] = idx;
