@@ -1800,6 +1800,25 @@ __global__ __launch_bounds__(WG) void givens2(int j, int m, const double *__rest
     __shared__ double out[4], red[4];
     __shared__ double nw2[1];
     const int tid = threadIdx.x;
+    // every operand is loaded before the first reduction, so the loads' latencies overlap:
+    // one column entry, rotation and product per thread (j < WG), the scalars by thread 0
+    double l_rw = 0.0, l_c = 0.0, l_s = 0.0, l_hs = 0.0, l_hp = 0.0;
+    if (tid < j) {
+        l_rw = raw[tid];
+        l_c = cs[tid];
+        l_s = sn[tid];
+        l_hs = h[j + 2 + tid];
+        l_hp = h[tid];
+    }
+    double l_alpha = 0.0, l_t = 0.0, l_bp = 0.0, l_h1 = 0.0, l_g0 = 0.0, l_gj = 0.0;
+    if (tid == 0) {
+        l_alpha = coef[0];
+        l_t = coef[1];
+        l_bp = coef[2];
+        l_h1 = h[j + 1];
+        l_gj = g[j];
+        if (j > 0) l_g0 = g[j - 1];
+    }
     {
         double a = 0.0;
         for (int b = tid; b < nblk; b += WG) a += wpart[b];
@@ -1807,7 +1826,14 @@ __global__ __launch_bounds__(WG) void givens2(int j, int m, const double *__rest
         if (tid == 0) nw2[0] = a;
     }
     // every operand staged in LDS by the workgroup; one thread runs the dependent chains
-    for (int i = tid; i < j; i += WG) {
+    if (tid < j) {
+        rw[tid] = l_rw;
+        c[tid] = l_c;
+        s[tid] = l_s;
+        hs[tid] = l_hs;
+        hp[tid] = l_hp;
+    }
+    for (int i = tid + WG; i < j; i += WG) {
         rw[i] = raw[i];
         c[i] = cs[i];
         s[i] = sn[i];
@@ -1816,9 +1842,10 @@ __global__ __launch_bounds__(WG) void givens2(int j, int m, const double *__rest
     }
     __syncthreads();
     if (tid == 0) {
-        const double alpha = coef[0], t = coef[1], naz = sqrt(h[j + 1]);
+        const double alpha = l_alpha, t = l_t, naz = sqrt(l_h1);
+        double gcur = l_gj;                      // g[j] as this kernel leaves it
         if (j > 0) {
-            const double bp = coef[2];
+            const double bp = l_bp;
             for (int i = 0; i < j; ++i) fin[i] = rw[i] + bp * hs[i];
             fin[j] = bp * alpha;
             rotate_col(fin, c, s, j - 1);
@@ -1828,8 +1855,9 @@ __global__ __launch_bounds__(WG) void givens2(int j, int m, const double *__rest
             s[j - 1] = sj;
             fin[j - 1] = rho;
             fin[j] = 0.0;
-            const double gj = g[j - 1];
-            g[j] = -sj * gj;
+            const double gj = l_g0;
+            gcur = -sj * gj;
+            g[j] = gcur;
             g[j - 1] = cj * gj;
         }
         // column j as the first pass left it, with its estimate (rotation not kept)
@@ -1843,10 +1871,10 @@ __global__ __launch_bounds__(WG) void givens2(int j, int m, const double *__rest
         out[1] = hn;
         out[2] = naz;
         if (rho == 0.0) {
-            out[0] = fabs(g[j]);
+            out[0] = fabs(gcur);
             out[3] = 1.0;
         } else {
-            out[0] = fabs(col[j + 1] / rho * g[j]);
+            out[0] = fabs(col[j + 1] / rho * gcur);
             out[3] = 0.0;
         }
         col[j] = t;                 // raw[j]
